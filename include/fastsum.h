@@ -1,0 +1,212 @@
+/*
+ * fastsum.h -- C ABI of the MI355X (gfx950) QMC-slicing fast kernel summation
+ * library (libfastsum.so).
+ *
+ * Problem (Sec. 1, eq. kernel_sum): for sources x_n in R^d with real weights
+ * w_n and targets y_m in R^d compute
+ *
+ *     s_m = sum_n w_n F(||x_n - y_m||),            m = 1..M,
+ *
+ * for a radial kernel F.  The library evaluates the slicing approximation
+ * (Sec. 2.1, eq. kernel_sum_sliced)
+ *
+ *     s_m ~ (1/P) sum_p sum_n w_n f(|<xi_p, x_n - y_m>|)
+ *
+ * with caller-supplied unit directions xi_1..xi_P (QMC designs, Sec. 3) and
+ * the 1-D basis function f of F (App. A).  Each 1-D sum is done by fast
+ * Fourier summation (App. I, Steps 1-3): the projections are rescaled by
+ * tau = min{T/R, 1/(2 g_max)}, the rescaled 1-D kernel is replaced by its
+ * Fourier series truncated to |k| <= N_ft/2 (coefficients computed in FP64 on
+ * the host), and the two non-uniform transforms of eq. (1d_sum_fourier) are
+ * done by window spreading on an oversampled grid, an FFT, a coefficient
+ * multiply, an inverse FFT and window interpolation.
+ *
+ * Conventions for every call:
+ *  - Device pointers point to memory of the device that was current when the
+ *    plan was created; float arrays are float32, row-major and contiguous.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Execution calls
+ *    only enqueue work on it; they never allocate, free or synchronise.
+ *  - Argument errors are reported synchronously by the return value and leave
+ *    every output untouched.  No call aborts or throws across the ABI.
+ *  - A plan is used by one stream at a time; distinct plans are independent.
+ */
+#ifndef FASTSUM_H
+#define FASTSUM_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define FASTSUM_API __attribute__((visibility("default")))
+#else
+#define FASTSUM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FASTSUM_OK = 0,
+    FASTSUM_EINVAL = 1,       /* invalid argument (null pointer, size, parameter) */
+    FASTSUM_ENOMEM = 2,       /* device or host allocation failed               */
+    FASTSUM_EDEVICE = 3,      /* a HIP runtime call failed                      */
+    FASTSUM_ERANGE = 4,       /* a projected point lay outside the bound R       */
+    FASTSUM_EUNSUPPORTED = 5, /* valid request this build does not implement     */
+    FASTSUM_ESTATE = 6        /* call order violated (e.g. grad before exec)     */
+} fastsum_status;
+
+/* Kernels of Table 'tab:kernels' (App. A). */
+typedef enum {
+    FASTSUM_GAUSS = 0,   /* F(r) = exp(-r^2 / (2 scale^2))                       */
+    FASTSUM_LAPLACE = 1, /* F(r) = exp(-r / scale)   (alpha = 1/scale)            */
+    FASTSUM_ENERGY = 2   /* F(r) = -r  (negative distance, Riesz r = 1)           */
+} fastsum_kernel;
+
+/* Arithmetic of the projection X . Xi (the only dense contraction). */
+typedef enum {
+    FASTSUM_PROJ_FP32 = 0, /* FP32 inputs, FP32 MFMA, FP32 accumulate            */
+    FASTSUM_PROJ_BF16 = 1  /* inputs rounded to BF16 (nearest-even), BF16 MFMA,  */
+                           /* FP32 accumulate; spread/FFT/gather stay FP32      */
+} fastsum_precision;
+
+/* fastsum_params.flags */
+#define FASTSUM_FLAG_GRAD 1u /* keep what fastsum_grad needs (derivative grids) */
+
+/*
+ * Plan parameters.  Zero in an optional field selects the default.
+ *   d            dimension (1 <= d <= 4096)
+ *   P            number of directions (1 <= P <= 65536)
+ *   n_ft         number of Fourier modes N_ft, even, 16..1024; modes |k| <= N_ft/2
+ *                are kept, with half weight at |k| = N_ft/2 (App. I Step 3)
+ *   window_w     window width in grid cells: 4, 6 or 8; default 6 for Laplace,
+ *                4 otherwise
+ *   oversample   grid size n = oversample * n_ft, 2 (default) or 4; n <= 2048
+ *   kernel       fastsum_kernel
+ *   proj         fastsum_precision
+ *   flags        FASTSUM_FLAG_*
+ *   scale        sigma (Gauss) or 1/alpha (Laplace), > 0; ignored for ENERGY
+ *   T            rescaling threshold (App. I Step 1); default 0.3 Gauss,
+ *                0.1 Laplace, 0.45 energy; must satisfy 0 < T < 0.5
+ *   gmax_factor  g_max = gmax_factor * scale (App. I Step 1); default 5
+ *   R            bound R >= max_n ||x_n|| + max_m ||y_m|| (App. J,
+ *                eq. radius_xy), > 0.  Points violating it set the range flag.
+ */
+typedef struct {
+    int32_t d;
+    int32_t P;
+    int32_t n_ft;
+    int32_t window_w;
+    int32_t oversample;
+    int32_t kernel;
+    int32_t proj;
+    uint32_t flags;
+    double scale;
+    double T;
+    double gmax_factor;
+    double R;
+} fastsum_params;
+
+/* Read-only facts about a plan (for tests and diagnostics). */
+typedef struct {
+    double tau;          /* rescaling factor (App. I Step 1)                  */
+    double beta;         /* shape of the exponential-of-semicircle window     */
+    int32_t n_grid;      /* oversampled grid size n                           */
+    int32_t window_w;    /* window width W in grid cells                      */
+    int32_t poly_degree; /* degree of the per-cell window polynomials         */
+    int32_t n_ft;
+    int64_t n_max, m_max;
+    int32_t proj;
+    uint32_t flags;
+    int32_t grid_lo;     /* first grid cell that points inside the bound touch */
+    int32_t grid_nr;     /* number of such cells (stored grids hold these)    */
+} fastsum_plan_info;
+
+typedef struct fastsum_plan_s* fastsum_plan;
+
+/*
+ * Create a plan: FP64 host precompute of tau, the Fourier coefficients c_k
+ * (App. I Step 2; App. J for the energy kernel), the window tables and the
+ * coefficient multipliers; upload of tau*Xi; allocation of the workspace for
+ * up to n_max sources and m_max targets.
+ *   prm     parameters (copied)
+ *   xi      HOST pointer, d x P row-major: column p (elements xi[i*P + p]) is
+ *           direction xi_p; columns should have unit norm (not renormalised)
+ *   n_max, m_max  capacity, >= 1
+ *   stream  stream used for the uploads (the call returns after they finish)
+ *   out     receives the plan; untouched on error
+ * Errors: EINVAL (bad parameter or pointer), ENOMEM, EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi,
+                                   int64_t n_max, int64_t m_max, void* stream,
+                                   fastsum_plan* out);
+
+/* Release every resource of a plan (synchronises the device).  NULL is a no-op. */
+FASTSUM_API void fastsum_destroy(fastsum_plan plan);
+
+/*
+ * s_m ~ sum_n w_n F(||x_n - y_m||) by Fourier slicing.
+ *   x  device, N x d;  w  device, N;  y  device, M x d, may equal x (then the
+ *   projections are computed once);  s  device, M (written).
+ *   1 <= N <= n_max, 1 <= M <= m_max.
+ * Asynchronous on `stream`.  The projections and grids of the call are kept
+ * in the plan for a following fastsum_grad.  If a projected point exceeds
+ * the bound implied by R a device flag is set (see fastsum_check).
+ */
+FASTSUM_API fastsum_status fastsum_exec(fastsum_plan plan, const float* x, int64_t N,
+                            const float* w, const float* y, int64_t M,
+                            float* s, void* stream);
+
+/*
+ * Adjoint of the last fastsum_exec (which must have used a plan with
+ * FASTSUM_FLAG_GRAD), for a cotangent v = grad_s (device, M):
+ *   grad_y (device, M x d, or NULL): grad_y[m] = v_m * d s_m / d y_m, where
+ *     d s_m/d y_m = (tau/P) sum_p xi_p t'_{m,p} and t'_{m,p} is the derivative
+ *     of the rescaled 1-D Fourier sum at y~_{m,p} (spectral multiplier 2 pi i k).
+ *   grad_w (device, N, or NULL): grad_w[n] = sum_m v_m d s_m / d w_n, the same
+ *     sliced Fourier sum with sources and targets exchanged.
+ * The inputs of the last exec must still be valid.  Asynchronous.
+ * Errors: ESTATE (no exec yet / plan without GRAD), EINVAL.
+ */
+FASTSUM_API fastsum_status fastsum_grad(fastsum_plan plan, const float* grad_s,
+                            float* grad_y, float* grad_w, void* stream);
+
+/*
+ * Synchronise the plan's last stream and report device-side conditions:
+ * returns ERANGE if any projected point of an exec since the previous check
+ * exceeded tau*R (results are then unreliable), OK otherwise; clears the flag.
+ */
+FASTSUM_API fastsum_status fastsum_check(fastsum_plan plan);
+
+/* Copy plan facts into *info.  EINVAL on NULL. */
+FASTSUM_API fastsum_status fastsum_get_info(fastsum_plan plan, fastsum_plan_info* info);
+
+/*
+ * Host-only (no device is touched): the FP64 quantities a plan would use.
+ *   tau_out  receives tau (may be NULL)
+ *   ck_out   receives c_0..c_K, K = n_ft/2 (K+1 doubles; may be NULL)
+ *   phihat_out receives the window transform at k = 0..n/2 (n/2+1 doubles,
+ *            n = oversample*n_ft; may be NULL)
+ * Errors: EINVAL.
+ */
+FASTSUM_API fastsum_status fastsum_host_tables(const fastsum_params* prm, double* tau_out,
+                                   double* ck_out, double* phihat_out);
+
+/*
+ * Diagnostics: synchronously copy an internal buffer of the last exec to host
+ * memory.  which = 0: projections of x (P x N, row p = tau <xi_p, x_n>);
+ * 1: projections of y (P x M); 2: convolved grids (P x grid_nr, cells
+ * grid_lo .. grid_lo+grid_nr-1 of each direction's grid of n cells, which
+ * holds the grid at position (j - n/2)/n).  count must equal the buffer's
+ * element count.  Errors: EINVAL, ESTATE, EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_debug_read(fastsum_plan plan, int32_t which,
+                                  float* host_out, int64_t count);
+
+/* Static, human-readable name of a status code. */
+FASTSUM_API const char* fastsum_status_string(fastsum_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTSUM_H */

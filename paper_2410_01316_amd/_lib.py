@@ -1,0 +1,80 @@
+"""ctypes declarations of libfastsum.so (include/fastsum.h)."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libfastsum.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EUNSUPPORTED, ESTATE = range(7)
+KERNELS = {"gauss": 0, "laplace": 1, "energy": 2}
+PROJ = {"fp32": 0, "bf16": 1}
+FLAG_GRAD = 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("P", ctypes.c_int32), ("n_ft", ctypes.c_int32),
+        ("window_w", ctypes.c_int32), ("oversample", ctypes.c_int32),
+        ("kernel", ctypes.c_int32), ("proj", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("scale", ctypes.c_double), ("T", ctypes.c_double),
+        ("gmax_factor", ctypes.c_double), ("R", ctypes.c_double),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double), ("beta", ctypes.c_double),
+        ("n_grid", ctypes.c_int32), ("window_w", ctypes.c_int32),
+        ("poly_degree", ctypes.c_int32), ("n_ft", ctypes.c_int32),
+        ("n_max", ctypes.c_int64), ("m_max", ctypes.c_int64),
+        ("proj", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("grid_lo", ctypes.c_int32), ("grid_nr", ctypes.c_int32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_st = ctypes.c_int
+
+SIGNATURES = {
+    "fastsum_plan_create": (_st, [ctypes.POINTER(Params), _vp, _i64, _i64, _vp, ctypes.POINTER(_vp)]),
+    "fastsum_destroy": (None, [_vp]),
+    "fastsum_exec": (_st, [_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp]),
+    "fastsum_grad": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "fastsum_check": (_st, [_vp]),
+    "fastsum_get_info": (_st, [_vp, ctypes.POINTER(PlanInfo)]),
+    "fastsum_host_tables": (_st, [ctypes.POINTER(Params), _vp, _vp, _vp]),
+    "fastsum_debug_read": (_st, [_vp, ctypes.c_int32, _vp, _i64]),
+    "fastsum_status_string": (ctypes.c_char_p, [_st]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libfastsum.so once.  Raises ImportError when it is not built:
+    there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing; build it with `python -m paper_2410_01316_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class FastSumError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = load().fastsum_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def check(status, where):
+    if status != OK:
+        raise FastSumError(status, where)

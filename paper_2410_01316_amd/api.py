@@ -1,0 +1,167 @@
+"""Python binding of libfastsum: argument checks and marshalling only.
+
+Every step of the summation runs in the HIP library; PyTorch provides the
+device buffers (tensor storage) and the current HIP stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, shape, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device != device:
+        raise ValueError(f"{name} must be a contiguous float32 tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Plan:
+    """A fast-summation plan: kernel, directions xi (d x P), grid and window
+    parameters, the bound R and workspace for up to n_max sources and m_max
+    targets on one GPU.  See include/fastsum.h for every parameter."""
+
+    def __init__(self, xi, *, kernel, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0,
+                 window_w=0, oversample=0, proj="fp32", grad=False, n_max, m_max,
+                 device=None):
+        lib = L.load()
+        xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float32))
+        if xi.ndim != 2:
+            raise ValueError("xi must be a (d, P) array")
+        self.d, self.P = xi.shape
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.type != "cuda":
+            raise ValueError("the plan lives on a GPU")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.kernel = kernel
+        self.prm = L.Params(self.d, self.P, int(n_ft), int(window_w), int(oversample),
+                            L.KERNELS[kernel], L.PROJ[proj], L.FLAG_GRAD if grad else 0,
+                            float(scale), float(T), float(gmax_factor), float(R))
+        self.n_max, self.m_max = int(n_max), int(m_max)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.fastsum_plan_create(ctypes.byref(self.prm), xi.ctypes.data_as(ctypes.c_void_p),
+                                         self.n_max, self.m_max, _stream_ptr(self.device),
+                                         ctypes.byref(self._h))
+        L.check(st, "fastsum_plan_create")
+        self._lib = lib
+        self._last = None
+
+    # -- forward / adjoint ------------------------------------------------
+    def __call__(self, x, w, y=None, out=None):
+        """s_m ~ sum_n w_n F(||x_n - y_m||); y defaults to x."""
+        if y is None:
+            y = x
+        N, M = x.shape[0], y.shape[0]
+        _need(x, "x", (N, self.d), self.device)
+        _need(w, "w", (N,), self.device)
+        _need(y, "y", (M, self.d), self.device)
+        if out is None:
+            out = torch.empty(M, dtype=torch.float32, device=self.device)
+        _need(out, "out", (M,), self.device)
+        with torch.cuda.device(self.device):
+            st = self._lib.fastsum_exec(self._h, _ptr(x), N, _ptr(w), _ptr(y), M, _ptr(out),
+                                        _stream_ptr(self.device))
+        L.check(st, "fastsum_exec")
+        self._last = (x, w, y)          # keep the inputs alive for grad
+        return out
+
+    def grad(self, grad_s, want_y=True, want_w=True):
+        """(grad_y, grad_w) of the last call for the cotangent grad_s."""
+        if self._last is None:
+            raise L.FastSumError(L.ESTATE, "grad before exec")
+        x, w, y = self._last
+        M, N = y.shape[0], x.shape[0]
+        _need(grad_s, "grad_s", (M,), self.device)
+        gy = torch.empty((M, self.d), dtype=torch.float32, device=self.device) if want_y else None
+        gw = torch.empty(N, dtype=torch.float32, device=self.device) if want_w else None
+        with torch.cuda.device(self.device):
+            st = self._lib.fastsum_grad(self._h, _ptr(grad_s),
+                                        _ptr(gy) if gy is not None else None,
+                                        _ptr(gw) if gw is not None else None,
+                                        _stream_ptr(self.device))
+        L.check(st, "fastsum_grad")
+        return gy, gw
+
+    # -- diagnostics --------------------------------------------------------
+    def check(self):
+        """Raise FastSumError(ERANGE) if a point exceeded the bound R."""
+        with torch.cuda.device(self.device):
+            L.check(self._lib.fastsum_check(self._h), "fastsum_check")
+
+    def info(self):
+        inf = L.PlanInfo()
+        L.check(self._lib.fastsum_get_info(self._h, ctypes.byref(inf)), "fastsum_get_info")
+        return {k: getattr(inf, k) for k, _ in L.PlanInfo._fields_}
+
+    def debug_read(self, which):
+        """Copy of an internal buffer of the last exec: 0 x-projections (P,N),
+        1 y-projections (P,M), 2 convolved grids (P, grid_nr)."""
+        x, w, y = self._last
+        inf = self.info()
+        cols = {0: x.shape[0], 1: y.shape[0], 2: inf["grid_nr"]}[which]
+        out = np.empty((self.P, cols), dtype=np.float32)
+        with torch.cuda.device(self.device):
+            st = self._lib.fastsum_debug_read(self._h, which, out.ctypes.data_as(ctypes.c_void_p),
+                                              out.size)
+        L.check(st, "fastsum_debug_read")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.fastsum_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FastSum(torch.autograd.Function):
+    """s = FastSum.apply(plan, x, y, w): differentiable in y and w (the plan
+    must be created with grad=True).  The gradient in x is not provided."""
+
+    @staticmethod
+    def forward(ctx, plan, x, y, w):
+        ctx.plan = plan
+        return plan(x.detach(), w.detach(), y.detach())
+
+    @staticmethod
+    def backward(ctx, grad_s):
+        plan = ctx.plan
+        gy, gw = plan.grad(grad_s.contiguous(), want_y=ctx.needs_input_grad[2],
+                           want_w=ctx.needs_input_grad[3])
+        return None, None, gy, gw
+
+
+def host_tables(kernel, d, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0, window_w=0,
+                oversample=0):
+    """FP64 host precompute of a plan without touching a device:
+    (tau, c_0..c_K, phihat_0..phihat_{n/2})."""
+    lib = L.load()
+    prm = L.Params(int(d), 1, int(n_ft), int(window_w), int(oversample), L.KERNELS[kernel], 0,
+                   0, float(scale), float(T), float(gmax_factor), float(R))
+    n = (oversample or 2) * n_ft
+    tau = ctypes.c_double()
+    ck = np.empty(n_ft // 2 + 1)
+    ph = np.empty(n // 2 + 1)
+    st = lib.fastsum_host_tables(ctypes.byref(prm), ctypes.byref(tau),
+                                 ck.ctypes.data_as(ctypes.c_void_p),
+                                 ph.ctypes.data_as(ctypes.c_void_p))
+    L.check(st, "fastsum_host_tables")
+    return tau.value, ck, ph

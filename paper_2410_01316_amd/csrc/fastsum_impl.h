@@ -1,0 +1,81 @@
+// Internal declarations shared by the host plan code (plan.cpp) and the
+// device kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fastsum {
+
+constexpr int kBlock = 256;        // threads per workgroup for every kernel
+constexpr int kMaxPairs = 4;       // W/2 for W <= 8
+constexpr int kMaxHalfCoef = 4;    // coefficients per even/odd half-polynomial
+
+// Window weights of one point as polynomials of sp = frac(u) - 1/2, where u
+// is the point's position in grid cells.  Tap t (t < W/2) and its mirror tap
+// W-1-t share an even part E_t(sp^2) and an odd part sp*O_t(sp^2):
+//   weight_t = E_t + sp O_t,   weight_{W-1-t} = E_t - sp O_t.
+struct WindowArgs {
+    float even[kMaxPairs][kMaxHalfCoef];
+    float odd[kMaxPairs][kMaxHalfCoef];
+};
+
+// Grid geometry: n cells, position u = x~ * n + n/2 for x~ in [-1/2, 1/2).
+// Only cells [lo, lo + nr) can receive or serve weight for points inside the
+// plan's bound; positions are clamped to [u_min, u_max] so that every tap of
+// every (even out-of-bound) point stays inside that range.
+struct GridGeom {
+    int n;
+    int lo;
+    int nr;
+    float u_min;
+    float u_max;
+};
+
+// ---- launchers (kernels.hip); all asynchronous on `stream` ----
+
+// out[p*ld + j] = sum_i A[p*dpad + i] * X[j*d + i] for p < P, j < N, with
+// A = tau * Xi^T zero-padded to (P_pad x dpad).  Sets *flag if |out| > bound.
+hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
+                              const float* A, int P, float* out, int64_t ld,
+                              float bound, int* flag, hipStream_t stream);
+hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
+                               const uint16_t* A, int P, float* out, int64_t ld,
+                               float bound, int* flag, hipStream_t stream);
+
+// partial[(c*P + p)*nr + j - lo] = sum over sources i of chunk c of
+//   w[i] * window(cell j - u(proj[p*ld + i]))
+hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
+                         int64_t N, int P, GridGeom g, int nchunk,
+                         int64_t chunk_len, const WindowArgs& win,
+                         float* partial, hipStream_t stream);
+
+// Per pair of directions: sum the chunk partials, complex FFT of size n,
+// multiply by mult (and separately by mult_d when grid_d != nullptr),
+// inverse FFT, store the cells [lo, lo+nr) of the real grids.
+hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
+                          const float2* tw, const float2* mult,
+                          const float2* mult_d, float* grid, float* grid_d,
+                          hipStream_t stream);
+
+// spart[b*ldm + m] = sum over the directions p of group b (pg per group) of
+//   sum_taps grid[p*nr + cell - lo] * window(cell - u(proj[p*ld + m]))
+// accumulated in FP64.  If tout != nullptr the per-direction values are
+// written to tout[p*ld_t + m] instead and spart is not touched.
+hipError_t launch_gather(int W, const float* proj, int64_t ld, int64_t M,
+                         int P, GridGeom g, const float* grid, int pg,
+                         int pstage, const WindowArgs& win, double* spart,
+                         int64_t ldm, float* tout, int64_t ld_t,
+                         hipStream_t stream);
+
+// s[m] = (float)(scale * sum_b spart[b*ldm + m]), b < nb.
+hipError_t launch_reduce(const double* spart, int nb, int64_t ldm, int64_t M,
+                         double scale, float* s, hipStream_t stream);
+
+// grad_y[m*d + i] = v[m] * coef * sum_p tprime[p*ld + m] * A[p*dpad + i]
+hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
+                              int P, int d, const float* A, int dpad,
+                              float coef, const float* v, float* grad_y,
+                              hipStream_t stream);
+
+}  // namespace fastsum

@@ -1,0 +1,620 @@
+// Host side of libfastsum: FP64 precompute, plan/workspace management and the
+// C ABI declared in include/fastsum.h.
+#include "fastsum.h"
+#include "fastsum_impl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace fastsum;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ---------------------------------------------------------------------------
+// FP64 numerics
+// ---------------------------------------------------------------------------
+
+// log of the d-dimensional Fourier transform of F(||.||) at radius w
+// (Table 'tab:kernels', column 3, transform convention of eq. Fourier).
+double log_ft_d(int kernel, double w, int d, double scale) {
+    if (kernel == FASTSUM_GAUSS) {
+        const double s2 = scale * scale;
+        return 0.5 * d * std::log(2.0 * kPi * s2) - 2.0 * kPi * kPi * s2 * w * w;
+    }
+    const double alpha = 1.0 / scale;   // Laplace
+    return std::lgamma(0.5 * (d + 1)) + d * std::log(2.0) + 0.5 * (d - 1) * std::log(kPi) -
+           d * std::log(alpha) -
+           0.5 * (d + 1) * std::log1p(4.0 * kPi * kPi * w * w / (alpha * alpha));
+}
+
+// One-dimensional Fourier transform of t -> f(|t|) through
+// F_1[f(|.|)](w) = pi^{d/2}/Gamma(d/2) |w|^{d-1} F_d[F](|w|)  (App. A).
+double sliced_ft(int kernel, double w, int d, double scale) {
+    w = std::fabs(w);
+    const double lf = log_ft_d(kernel, w, d, scale);
+    if (d == 1) return std::exp(lf);
+    if (w == 0.0) return 0.0;
+    return std::exp(0.5 * d * std::log(kPi) - std::lgamma(0.5 * d) + (d - 1) * std::log(w) + lf);
+}
+
+double energy_cd(int d) {
+    return std::exp(0.5 * std::log(kPi) + std::lgamma(0.5 * (d + 1)) - std::lgamma(0.5 * d));
+}
+
+// c_k, k = 0..K, of the 1-periodic rescaled kernel (App. I Step 2; for the
+// energy kernel the triangle-wave extension of -(c_d/tau)|x|).
+void fourier_coefficients(int kernel, int d, double scale, double tau, int n_ft,
+                          std::vector<double>& c) {
+    const int K = n_ft / 2;
+    c.assign(K + 1, 0.0);
+    if (kernel == FASTSUM_ENERGY) {
+        const double cd = energy_cd(d);
+        c[0] = -cd / (4.0 * tau);
+        for (int k = 1; k <= K; k += 2) c[k] = cd / (tau * kPi * kPi * double(k) * double(k));
+        return;
+    }
+    for (int k = 0; k <= K; ++k) c[k] = tau * sliced_ft(kernel, tau * k, d, scale);
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_m.
+void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(m);
+    w.resize(m);
+    for (int i = 0; i < (m + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (m + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int j = 1; j <= m; ++j) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+            }
+            dp = m * (z * p0 - p1) / (z * z - 1.0);
+            const double dz = p0 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[m - 1 - i] = z;
+        w[i] = w[m - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Solve the small dense system V a = b (partial pivoting), in place.
+bool solve_dense(std::vector<double>& V, std::vector<double>& b, int n) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(V[r * n + c]) > std::fabs(V[piv * n + c])) piv = r;
+        if (V[piv * n + c] == 0.0) return false;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(V[c * n + k], V[piv * n + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = V[r * n + c] / V[c * n + c];
+            for (int k = c; k < n; ++k) V[r * n + k] -= f * V[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double acc = b[c];
+        for (int k = c + 1; k < n; ++k) acc -= V[c * n + k] * b[k];
+        b[c] = acc / V[c * n + c];
+    }
+    return true;
+}
+
+// Exponential-of-semicircle window phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
+// |z| <= 1, z = (cell - u) / (W/2).  Tap t of a point with sp = frac(u) - 1/2
+// sits at z_t = (t + 1/2 - W/2 - sp) / (W/2).  The weight of tap t is
+// replaced by its degree-D interpolant in sp at Chebyshev points; everything
+// downstream (phihat, the multipliers) is computed from these polynomials, so
+// the deconvolution matches the window the kernels actually apply.
+struct WindowPoly {
+    int W = 4, D = 4;
+    double beta = 0.0;
+    std::vector<double> coef;   // W x (D+1), monomial coefficients in sp
+    double eval(int t, double sp) const {
+        double acc = 0.0;
+        for (int i = D; i >= 0; --i) acc = acc * sp + coef[t * (D + 1) + i];
+        return acc;
+    }
+};
+
+bool build_window(int W, WindowPoly& win) {
+    win.W = W;
+    win.D = (W == 4) ? 4 : (W == 6 ? 5 : 7);
+    win.beta = 2.6 * W;
+    const int nc = win.D + 1;
+    win.coef.assign(W * nc, 0.0);
+    std::vector<double> nodes(nc);
+    for (int i = 0; i < nc; ++i) nodes[i] = 0.5 * std::cos(kPi * (i + 0.5) / nc);
+    for (int t = 0; t < W / 2; ++t) {
+        std::vector<double> V(nc * nc), b(nc);
+        for (int i = 0; i < nc; ++i) {
+            const double sp = nodes[i];
+            const double z = (t + 0.5 - 0.5 * W - sp) / (0.5 * W);
+            b[i] = std::fabs(z) < 1.0 ? std::exp(win.beta * (std::sqrt(1.0 - z * z) - 1.0)) : 0.0;
+            double pw = 1.0;
+            for (int k = 0; k < nc; ++k) { V[i * nc + k] = pw; pw *= sp; }
+        }
+        if (!solve_dense(V, b, nc)) return false;
+        for (int k = 0; k < nc; ++k) {
+            win.coef[t * nc + k] = b[k];
+            // mirror tap: weight_{W-1-t}(sp) = weight_t(-sp)
+            win.coef[(W - 1 - t) * nc + k] = (k % 2) ? -b[k] : b[k];
+        }
+    }
+    return true;
+}
+
+// phihat(k) = integral of the piecewise-polynomial window against
+// exp(-2 pi i k x), x in units of the unit period, for k = 0..kmax.
+// A point at u and the cells it touches are (t + 1/2 - W/2 - sp)/n apart.
+void window_transform(const WindowPoly& win, int n, int kmax, std::vector<double>& out) {
+    std::vector<double> gx, gw;
+    gauss_legendre(48, gx, gw);
+    out.assign(kmax + 1, 0.0);
+    for (int k = 0; k <= kmax; ++k) {
+        double acc = 0.0;
+        for (int t = 0; t < win.W; ++t)
+            for (size_t q = 0; q < gx.size(); ++q) {
+                const double sp = 0.5 * gx[q];             // sp in [-1/2, 1/2]
+                const double dist = (t + 0.5 - 0.5 * win.W - sp) / n;
+                acc += 0.5 * gw[q] * win.eval(t, sp) * std::cos(2.0 * kPi * k * dist);
+            }
+        out[k] = acc / n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// parameters
+// ---------------------------------------------------------------------------
+
+struct Resolved {
+    fastsum_params p;
+    int n = 0;          // grid size
+    double tau = 0.0;
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+fastsum_status resolve_params(const fastsum_params* in, Resolved& r) {
+    if (!in) return FASTSUM_EINVAL;
+    fastsum_params p = *in;
+    if (p.kernel < FASTSUM_GAUSS || p.kernel > FASTSUM_ENERGY) return FASTSUM_EINVAL;
+    if (p.d < 1 || p.d > 4096 || p.P < 1 || p.P > 65536) return FASTSUM_EINVAL;
+    if (p.n_ft < 16 || p.n_ft > 4096 || (p.n_ft % 2)) return FASTSUM_EINVAL;
+    // Laplace keeps a k^-2 spectrum up to N_ft/2, where the width-4 window's
+    // aliasing error reaches ~1e-4; width 6 brings it to ~4e-6.
+    if (p.window_w == 0) p.window_w = (p.kernel == FASTSUM_LAPLACE) ? 6 : 4;
+    if (p.window_w != 4 && p.window_w != 6 && p.window_w != 8) return FASTSUM_EINVAL;
+    if (p.oversample == 0) p.oversample = 2;
+    if (p.oversample != 2 && p.oversample != 4) return FASTSUM_EINVAL;
+    if (p.proj != FASTSUM_PROJ_FP32 && p.proj != FASTSUM_PROJ_BF16) return FASTSUM_EINVAL;
+    if (p.flags & ~FASTSUM_FLAG_GRAD) return FASTSUM_EINVAL;
+    if (p.T == 0.0) p.T = p.kernel == FASTSUM_GAUSS ? 0.3 : (p.kernel == FASTSUM_LAPLACE ? 0.1 : 0.45);
+    if (p.gmax_factor == 0.0) p.gmax_factor = 5.0;
+    if (!(p.R > 0.0) || !std::isfinite(p.R)) return FASTSUM_EINVAL;
+    if (p.kernel != FASTSUM_ENERGY && (!(p.scale > 0.0) || !std::isfinite(p.scale)))
+        return FASTSUM_EINVAL;
+    if (!(p.gmax_factor > 0.0)) return FASTSUM_EINVAL;
+    const int n = p.oversample * p.n_ft;
+    if (n > 2048 || !is_pow2(n)) return FASTSUM_EINVAL;
+    // every tap of a point with |x~| <= T must stay inside one period
+    if (!(p.T > 0.0) || p.T > 0.5 - (p.window_w / 2 + 2.0) / n) return FASTSUM_EINVAL;
+    r.p = p;
+    r.n = n;
+    r.tau = (p.kernel == FASTSUM_ENERGY) ? p.T / p.R
+                                         : std::min(p.T / p.R, 1.0 / (2.0 * p.gmax_factor * p.scale));
+    return FASTSUM_OK;
+}
+
+GridGeom make_geom(int n, int W, double tauR) {
+    GridGeom g;
+    g.n = n;
+    const int half = (int)std::ceil(tauR * n) + W / 2 + 1;
+    int lo = std::max(0, n / 2 - half);
+    lo &= ~3;
+    g.lo = lo;
+    g.nr = n - 2 * lo;
+    g.u_min = (float)(lo + W / 2 - 1);
+    g.u_max = (float)(n - lo - W / 2 - 1);
+    return g;
+}
+
+WindowArgs pack_window(const WindowPoly& win) {
+    WindowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const int nc = win.D + 1;
+    for (int t = 0; t < win.W / 2; ++t)
+        for (int k = 0; k < nc; ++k) {
+            if (k % 2 == 0) a.even[t][k / 2] = (float)win.coef[t * nc + k];
+            else a.odd[t][k / 2] = (float)win.coef[t * nc + k];
+        }
+    return a;
+}
+
+uint16_t f32_to_bf16_host(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan object
+// ---------------------------------------------------------------------------
+
+struct fastsum_plan_s {
+    Resolved r;
+    WindowPoly win;
+    WindowArgs win_args;
+    GridGeom geom;
+    int d = 0, P = 0, dpad = 0, W = 4;
+    int64_t n_max = 0, m_max = 0, ld_x = 0, ld_y = 0, ldm = 0;
+    int nchunk_cap = 1, pstage = 8, ngroup_cap = 1;
+    float bound = 0.f;
+    int device = 0;
+    // device buffers
+    float* A = nullptr;            // tau * Xi^T, P x dpad
+    uint16_t* A16 = nullptr;       // BF16 copy
+    float* xproj = nullptr;
+    float* yproj = nullptr;
+    float* partial = nullptr;
+    float* grid = nullptr;
+    float* grid_d = nullptr;
+    float* grid_w = nullptr;       // grids of the weight adjoint
+    double* spart = nullptr;
+    float* tprime = nullptr;
+    float2* mult = nullptr;
+    float2* mult_d = nullptr;
+    float2* tw = nullptr;
+    int* flag = nullptr;
+    // last exec
+    bool have_exec = false, last_same = false;
+    const float* last_x = nullptr;
+    const float* last_w = nullptr;
+    const float* last_y = nullptr;
+    int64_t last_N = 0, last_M = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+void free_plan(fastsum_plan_s* p) {
+    if (!p) return;
+    void* bufs[] = {p->A, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
+                    p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+template <typename T>
+bool dev_alloc(T** ptr, size_t count) {
+    if (count == 0) count = 1;
+    return hipMalloc((void**)ptr, count * sizeof(T)) == hipSuccess;
+}
+
+int spread_chunks(int64_t N, int P) {
+    // aim for >= 2048 workgroups, chunks of >= 2048 sources
+    int64_t want = (2048 + P - 1) / P;
+    int64_t maxc = std::max<int64_t>(1, (N + 2047) / 2048);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxc, 64)));
+}
+
+int gather_group(int64_t M, int P, int pstage) {
+    // aim for about 1024 workgroups; group size a multiple of pstage, <= 128
+    const int64_t tiles = (M + kBlock * 4 - 1) / (kBlock * 4);
+    int64_t groups = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+    int64_t pg = (P + groups - 1) / groups;
+    pg = round_up(std::max<int64_t>(pg, 1), pstage);
+    pg = std::min<int64_t>(pg, 128);
+    pg = std::max<int64_t>(pg, pstage);
+    return (int)pg;
+}
+
+fastsum_status check(hipError_t e) {
+    if (e == hipSuccess) return FASTSUM_OK;
+    if (e == hipErrorOutOfMemory) return FASTSUM_ENOMEM;
+    return FASTSUM_EDEVICE;
+}
+
+#define FS_TRY(expr)                                  \
+    do {                                              \
+        fastsum_status _st = check(expr);             \
+        if (_st != FASTSUM_OK) return _st;            \
+    } while (0)
+
+// One 1-D Fourier summation pass for every direction:
+// spread (sources) -> fftconv -> gather (targets) into s.
+fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_src,
+                        const float* wts, int64_t Nsrc, const float* tgt_proj,
+                        int64_t ld_tgt, int64_t Mtgt, float* out, float* grid,
+                        float* grid_d, hipStream_t st) {
+    const int P = pl->P;
+    const int nchunk = spread_chunks(Nsrc, P);
+    const int64_t chunk_len = round_up((Nsrc + nchunk - 1) / nchunk, kBlock);
+    FS_TRY(launch_spread(pl->W, src_proj, ld_src, wts, Nsrc, P, pl->geom, nchunk, chunk_len,
+                         pl->win_args, pl->partial, st));
+    FS_TRY(launch_fftconv(pl->partial, nchunk, P, pl->geom, pl->tw, pl->mult, pl->mult_d,
+                          grid, grid_d, st));
+    const int pg = gather_group(Mtgt, P, pl->pstage);
+    const int ng = (P + pg - 1) / pg;
+    FS_TRY(launch_gather(pl->W, tgt_proj, ld_tgt, Mtgt, P, pl->geom, grid, pg, pl->pstage,
+                         pl->win_args, pl->spart, pl->ldm, nullptr, 0, st));
+    FS_TRY(launch_reduce(pl->spart, ng, pl->ldm, Mtgt, 1.0 / P, out, st));
+    return FASTSUM_OK;
+}
+
+fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out, int64_t ld,
+                       hipStream_t st) {
+    if (pl->r.p.proj == FASTSUM_PROJ_BF16)
+        return check(launch_project_bf16(X, N, pl->d, pl->dpad, pl->A16, pl->P, out, ld,
+                                         pl->bound, pl->flag, st));
+    return check(launch_project_f32(X, N, pl->d, pl->dpad, pl->A, pl->P, out, ld, pl->bound,
+                                    pl->flag, st));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* fastsum_status_string(fastsum_status s) {
+    switch (s) {
+        case FASTSUM_OK: return "ok";
+        case FASTSUM_EINVAL: return "invalid argument";
+        case FASTSUM_ENOMEM: return "out of memory";
+        case FASTSUM_EDEVICE: return "HIP runtime error";
+        case FASTSUM_ERANGE: return "point outside the bound R";
+        case FASTSUM_EUNSUPPORTED: return "unsupported";
+        case FASTSUM_ESTATE: return "invalid call order";
+    }
+    return "unknown status";
+}
+
+fastsum_status fastsum_host_tables(const fastsum_params* prm, double* tau_out, double* ck_out,
+                                   double* phihat_out) {
+    Resolved r;
+    fastsum_status st = resolve_params(prm, r);
+    if (st != FASTSUM_OK) return st;
+    if (tau_out) *tau_out = r.tau;
+    if (ck_out) {
+        std::vector<double> c;
+        fourier_coefficients(r.p.kernel, r.p.d, r.p.scale, r.tau, r.p.n_ft, c);
+        std::copy(c.begin(), c.end(), ck_out);
+    }
+    if (phihat_out) {
+        WindowPoly win;
+        if (!build_window(r.p.window_w, win)) return FASTSUM_EINVAL;
+        std::vector<double> ph;
+        window_transform(win, r.n, r.n / 2, ph);
+        std::copy(ph.begin(), ph.end(), phihat_out);
+    }
+    return FASTSUM_OK;
+}
+
+fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, int64_t n_max,
+                                   int64_t m_max, void* stream, fastsum_plan* out) {
+    if (!prm || !xi || !out || n_max < 1 || m_max < 1) return FASTSUM_EINVAL;
+    Resolved r;
+    fastsum_status st = resolve_params(prm, r);
+    if (st != FASTSUM_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+
+    fastsum_plan_s* pl = new (std::nothrow) fastsum_plan_s();
+    if (!pl) return FASTSUM_ENOMEM;
+    pl->r = r;
+    pl->d = r.p.d;
+    pl->P = r.p.P;
+    pl->W = r.p.window_w;
+    pl->dpad = (int)round_up(pl->d, 4);
+    pl->n_max = n_max;
+    pl->m_max = m_max;
+    if (!build_window(pl->W, pl->win)) { delete pl; return FASTSUM_EINVAL; }
+    pl->win_args = pack_window(pl->win);
+    const double tauR = r.tau * r.p.R;
+    pl->geom = make_geom(r.n, pl->W, tauR);
+    pl->bound = (float)(tauR * (1.0 + 1e-5) + 1e-7);
+    if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return FASTSUM_EDEVICE; }
+
+    const int P = pl->P, n = r.n, nr = pl->geom.nr;
+    const int64_t cap = std::max(n_max, m_max);
+    pl->ld_x = round_up(n_max, 64);
+    pl->ld_y = round_up(m_max, 64);
+    pl->ldm = round_up(cap, 64);
+    pl->pstage = std::max(1, std::min(8, 12288 / nr));
+    pl->ngroup_cap = (P + pl->pstage - 1) / pl->pstage;
+    // spread_chunks grows with the source count, and the weight adjoint
+    // spreads the targets: size for the larger of the two roles
+    pl->nchunk_cap = spread_chunks(cap, P);
+    const bool grad = (r.p.flags & FASTSUM_FLAG_GRAD) != 0;
+
+    bool ok = dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
+              dev_alloc(&pl->A16, (size_t)P * pl->dpad) &&
+              dev_alloc(&pl->xproj, (size_t)P * pl->ld_x) &&
+              dev_alloc(&pl->yproj, (size_t)P * pl->ld_y) &&
+              dev_alloc(&pl->partial, (size_t)pl->nchunk_cap * P * nr) &&
+              dev_alloc(&pl->grid, (size_t)P * nr) &&
+              dev_alloc(&pl->spart, (size_t)pl->ngroup_cap * pl->ldm) &&
+              dev_alloc(&pl->mult, (size_t)n) && dev_alloc(&pl->tw, (size_t)n) &&
+              dev_alloc(&pl->flag, 1);
+    if (ok && grad)
+        ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
+             dev_alloc(&pl->mult_d, (size_t)n) && dev_alloc(&pl->tprime, (size_t)P * pl->ld_y);
+    if (!ok) { free_plan(pl); return FASTSUM_ENOMEM; }
+
+    // tables
+    std::vector<double> c;
+    fourier_coefficients(r.p.kernel, pl->d, r.p.scale, r.tau, r.p.n_ft, c);
+    std::vector<double> ph;
+    window_transform(pl->win, n, n / 2, ph);
+    const int K = r.p.n_ft / 2;
+    std::vector<float2> mult(n), mult_d(n), tw(n);
+    for (int k = 0; k < n; ++k) {
+        const int ks = (k <= n / 2) ? k : k - n;
+        const int a = std::abs(ks);
+        double m = 0.0;
+        if (a <= K) {
+            const double cp = (a == K) ? 0.5 * c[a] : c[a];
+            const double den = n * ph[a];
+            m = cp / (den * den);
+        }
+        mult[k] = make_float2((float)m, 0.f);
+        mult_d[k] = make_float2(0.f, (float)(2.0 * kPi * ks * m));
+        tw[k] = make_float2((float)std::cos(2.0 * kPi * k / n), (float)-std::sin(2.0 * kPi * k / n));
+    }
+    std::vector<float> A((size_t)P * pl->dpad, 0.f);
+    std::vector<uint16_t> A16((size_t)P * pl->dpad, 0);
+    for (int p = 0; p < P; ++p)
+        for (int i = 0; i < pl->d; ++i) {
+            const float v = (float)(r.tau * (double)xi[(size_t)i * P + p]);
+            A[(size_t)p * pl->dpad + i] = v;
+            A16[(size_t)p * pl->dpad + i] = f32_to_bf16_host(v);
+        }
+    hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->A16, A16.data(), A16.size() * 2, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->mult, mult.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && grad)
+        e = hipMemcpyAsync(pl->mult_d, mult_d.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->flag, 0, sizeof(int), hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) { free_plan(pl); return FASTSUM_EDEVICE; }
+    *out = pl;
+    return FASTSUM_OK;
+}
+
+void fastsum_destroy(fastsum_plan plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+}
+
+fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const float* w,
+                            const float* y, int64_t M, float* s, void* stream) {
+    if (!pl || !x || !w || !y || !s) return FASTSUM_EINVAL;
+    if (N < 1 || M < 1 || N > pl->n_max || M > pl->m_max) return FASTSUM_EINVAL;
+    const bool same = (x == y);
+    if (same && N != M) return FASTSUM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    fastsum_status r = project(pl, x, N, pl->xproj, pl->ld_x, st);
+    if (r != FASTSUM_OK) return r;
+    const float* yp = pl->xproj;
+    int64_t ldy = pl->ld_x;
+    if (!same) {
+        r = project(pl, y, M, pl->yproj, pl->ld_y, st);
+        if (r != FASTSUM_OK) return r;
+        yp = pl->yproj;
+        ldy = pl->ld_y;
+    }
+    r = sum_pass(pl, pl->xproj, pl->ld_x, w, N, yp, ldy, M, s, pl->grid,
+                 (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, st);
+    if (r != FASTSUM_OK) return r;
+    pl->have_exec = true;
+    pl->last_same = same;
+    pl->last_x = x;
+    pl->last_w = w;
+    pl->last_y = y;
+    pl->last_N = N;
+    pl->last_M = M;
+    pl->last_stream = st;
+    return FASTSUM_OK;
+}
+
+fastsum_status fastsum_grad(fastsum_plan pl, const float* grad_s, float* grad_y, float* grad_w,
+                            void* stream) {
+    if (!pl || !grad_s) return FASTSUM_EINVAL;
+    if (!(pl->r.p.flags & FASTSUM_FLAG_GRAD) || !pl->have_exec) return FASTSUM_ESTATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int P = pl->P;
+    const float* yp = pl->last_same ? pl->xproj : pl->yproj;
+    const int64_t ldy = pl->last_same ? pl->ld_x : pl->ld_y;
+    const int64_t M = pl->last_M, N = pl->last_N;
+    if (grad_y) {
+        // t'_{m,p}: interpolate the derivative grids of the last exec
+        const int pg = gather_group(M, P, pl->pstage);
+        FS_TRY(launch_gather(pl->W, yp, ldy, M, P, pl->geom, pl->grid_d, pg, pl->pstage,
+                             pl->win_args, nullptr, 0, pl->tprime, pl->ld_y, st));
+        FS_TRY(launch_backproject(pl->tprime, pl->ld_y, M, P, pl->d, pl->A, pl->dpad,
+                                  (float)(1.0 / P), grad_s, grad_y, st));
+    }
+    if (grad_w) {
+        // K^T v: the same sliced Fourier sum, sources y with weights v, targets x
+        fastsum_status r = sum_pass(pl, yp, ldy, grad_s, M, pl->xproj, pl->ld_x, N, grad_w,
+                                    pl->grid_w, nullptr, st);
+        if (r != FASTSUM_OK) return r;
+    }
+    return FASTSUM_OK;
+}
+
+fastsum_status fastsum_check(fastsum_plan pl) {
+    if (!pl) return FASTSUM_EINVAL;
+    int h = 0;
+    hipError_t e = hipStreamSynchronize(pl->last_stream);
+    if (e == hipSuccess) e = hipMemcpy(&h, pl->flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && h) e = hipMemset(pl->flag, 0, sizeof(int));
+    if (e != hipSuccess) return FASTSUM_EDEVICE;
+    return h ? FASTSUM_ERANGE : FASTSUM_OK;
+}
+
+fastsum_status fastsum_get_info(fastsum_plan pl, fastsum_plan_info* info) {
+    if (!pl || !info) return FASTSUM_EINVAL;
+    info->tau = pl->r.tau;
+    info->beta = pl->win.beta;
+    info->n_grid = pl->r.n;
+    info->window_w = pl->W;
+    info->poly_degree = pl->win.D;
+    info->n_ft = pl->r.p.n_ft;
+    info->n_max = pl->n_max;
+    info->m_max = pl->m_max;
+    info->proj = pl->r.p.proj;
+    info->flags = pl->r.p.flags;
+    info->grid_lo = pl->geom.lo;
+    info->grid_nr = pl->geom.nr;
+    return FASTSUM_OK;
+}
+
+fastsum_status fastsum_debug_read(fastsum_plan pl, int32_t which, float* host_out,
+                                  int64_t count) {
+    if (!pl || !host_out) return FASTSUM_EINVAL;
+    if (!pl->have_exec) return FASTSUM_ESTATE;
+    const float* src = nullptr;
+    int64_t rows = pl->P, cols = 0, ld = 0;
+    if (which == 0) { src = pl->xproj; cols = pl->last_N; ld = pl->ld_x; }
+    else if (which == 1) {
+        src = pl->last_same ? pl->xproj : pl->yproj;
+        cols = pl->last_M;
+        ld = pl->last_same ? pl->ld_x : pl->ld_y;
+    } else if (which == 2) { src = pl->grid; cols = pl->geom.nr; ld = pl->geom.nr; }
+    else return FASTSUM_EINVAL;
+    if (count != rows * cols) return FASTSUM_EINVAL;
+    if (hipStreamSynchronize(pl->last_stream) != hipSuccess) return FASTSUM_EDEVICE;
+    if (hipMemcpy2D(host_out, cols * sizeof(float), src, ld * sizeof(float), cols * sizeof(float),
+                    rows, hipMemcpyDeviceToHost) != hipSuccess)
+        return FASTSUM_EDEVICE;
+    return FASTSUM_OK;
+}
+
+}  // extern "C"
