@@ -1,0 +1,281 @@
+#!/usr/bin/env python
+"""Throughput of QMC-slicing fast kernel summation on one MI355X.
+
+One step = one full pass of the summation path (projection of sources and
+targets, window spreading, FFT convolution, window gather with the FP64
+reduction over directions) on the d=50, N=M=60000, P=1000, N_ft=1024
+Gaussian-mixture workload with signed weights, inputs resident in HBM.
+
+Prints ONE JSON line.  value = N*M*steps / elapsed (pairs per second).
+Beside it: the dominant kernel's roofline (algorithmic bytes or flops per
+launch divided by its average duration from HIP events recorded on the
+launch stream over the timed region), the error against the FP64 direct sum
+on a seeded target sample, the FP64 CPU oracle timed on a bounded sample, and
+the other forms (Laplace, BF16 vs FP32 projection at d=784, MMD gradient).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N·M/s at 1e-3 rel err vs FP64 direct; plain FP32 vs BF16/batched; HBM %peak"
+PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TFs": 157.3, "bf16_mfma_TFs": 2500.0}
+KERNEL_SRC = os.path.join(ROOT, "paper_2410_01316_amd", "csrc", "kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def f32dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def make_plan(cfg, **kw):
+    import paper_2410_01316_amd as F
+    T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45}[cfg["kernel"]]
+    return F.Plan(cfg["xi"], kernel=cfg["kernel"], n_ft=cfg["n_ft"], scale=cfg["scale"],
+                  R=cfg["R"], T=T, n_max=cfg["N"], m_max=cfg["M"], **kw)
+
+
+def timed_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def algorithmic(phase, info, N, M, d, P, proj):
+    """Bytes (and flops) one launch of a phase must move in this design,
+    inputs and outputs counted once (model with materialised projections)."""
+    nr = info["grid_nr"]
+    if phase == "project":         # average of the x and y launches
+        pts = (N + M) / 2.0
+        byts = pts * d * 4 + P * d * 4 + P * pts * 4
+        return byts, 2.0 * pts * d * P
+    if phase == "spread":
+        return P * N * 4 + N * 4 + info["last_spread_chunks"] * P * nr * 4, 0.0
+    if phase == "fftconv":
+        return info["last_spread_chunks"] * P * nr * 4 + P * nr * 4, 0.0
+    if phase == "gather":
+        return P * M * 4 + P * nr * 4 + info["last_gather_groups"] * M * 8, 0.0
+    if phase == "reduce":
+        return info["last_gather_groups"] * M * 8 + M * 4, 0.0
+    return 0.0, 0.0
+
+
+def kernel_source_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    path = os.path.join(PROFILES, f"{phase}_scale_d50_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, s_gpu, n_sample, seed=123):
+    """FP64 direct sum (the oracle, untuned) on a seeded sample of targets,
+    single BLAS thread; also the GPU error on the same targets."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(cfg["M"], size=min(n_sample, cfg["M"]), replace=False))
+    d64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    x, y, w = d64(cfg["x"]), d64(cfg["y"])[idx], d64(cfg["w"])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s1 = O.kernel_sum_direct(cfg["kernel"], x, y, w, cfg["scale"])
+        dt = time.perf_counter() - t0
+    sg = np.asarray(s_gpu, np.float64)[idx]
+    err = float(np.linalg.norm(sg - s1) / np.linalg.norm(s1))
+    pairs = len(idx) * cfg["N"]
+    return dict(value=pairs / dt, unit="pairs/s", cores=1, kind="oracle",
+                sample=f"FP64 direct sum, {len(idx)} seeded targets x all {cfg['N']} sources "
+                       f"(d={cfg['d']}), {dt:.1f} s"), err, idx, s1
+
+
+def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, err_kind=None):
+    """Time one more form; returns a dict (ms, pairs/s, optional error)."""
+    import torch
+    import oracle as O
+    plan = make_plan(cfg, proj=proj, grad=grad)
+    x, w = f32dev(cfg["x"]), f32dev(cfg["w"])
+    y = x if cfg.get("same_xy") else f32dev(cfg["y"])
+    out = torch.empty(cfg["M"], dtype=torch.float32, device="cuda")
+    ones = torch.ones(cfg["M"], dtype=torch.float32, device="cuda")
+
+    def step():
+        plan(x, w, y, out=out)
+        if grad:
+            plan.grad(ones, want_y=True, want_w=False)
+
+    ms = timed_steps(step, steps, warmup) * 1e3
+    plan.check()
+    res = dict(ms_per_step=round(ms, 4), pairs_per_s=cfg["N"] * cfg["M"] / (ms * 1e-3),
+               N=cfg["N"], M=cfg["M"], d=cfg["d"], P=cfg["P"], n_ft=cfg["n_ft"],
+               kernel=cfg["kernel"], proj=proj, grad=grad)
+    if err_targets:
+        rng = np.random.default_rng(7)
+        idx = np.sort(rng.choice(cfg["M"], size=err_targets, replace=False))
+        d64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+        xo, yo, wo = d64(cfg["x"]), d64(cfg["y"])[idx], d64(cfg["w"])
+        s1 = O.kernel_sum_direct(cfg["kernel"], xo, yo, wo, cfg["scale"])
+        sg = out.cpu().numpy().astype(np.float64)[idx]
+        res["rel_l2_vs_fp64_direct"] = float(np.linalg.norm(sg - s1) / np.linalg.norm(s1))
+        s_abs = O.kernel_sum_direct(cfg["kernel"], xo, yo, np.abs(wo), cfg["scale"])
+        res["err_scale_vs_fp64_direct"] = float(np.linalg.norm(sg - s1) / np.linalg.norm(s_abs))
+        res["error_sample_targets"] = int(err_targets)
+    plan.close()
+    del x, w, y, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kernel", default="gauss", choices=["gauss", "laplace"])
+    ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of "
+              "it (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2410_01316_amd as F
+    from workloads import make_config
+
+    F.load_library()
+    torch.cuda.set_device(0)
+    t_start = time.perf_counter()
+    log("bench: building inputs (d=50, N=M=60000, P=1000 distance-QMC)")
+    cfg = make_config("scale", kernel=args.kernel)
+    plan = make_plan(cfg)
+    x, y, w = f32dev(cfg["x"]), f32dev(cfg["y"]), f32dev(cfg["w"])
+    s = torch.empty(cfg["M"], dtype=torch.float32, device="cuda")
+    N, M, d, P = cfg["N"], cfg["M"], cfg["d"], cfg["P"]
+
+    for _ in range(args.warmup):
+        plan(x, w, y, out=s)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()
+    log(f"bench: timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan(x, w, y, out=s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = plan.profile_read()
+    plan.profile(False)
+    plan.check()
+    info = plan.info()
+    ms_per_step = elapsed / args.steps * 1e3
+    value = N * M * args.steps / elapsed
+
+    # roofline of the dominant kernel
+    dom = max((p for p in phases if phases[p][1] > 0), key=lambda p: phases[p][0])
+    tot_ms, launches = phases[dom]
+    avg_s = tot_ms / launches * 1e-3
+    byts, flops = algorithmic(dom, info, N, M, d, P, "fp32")
+    if flops > 0 and flops / byts > PEAK["fp32_mfma_TFs"] * 1e12 / (PEAK["hbm_GBs"] * 1e9):
+        roof = dict(bound="mfma", achieved=flops / avg_s / 1e12, peak=PEAK["fp32_mfma_TFs"],
+                    unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["algorithmic_bytes_per_launch"] = byts
+    roof["algorithmic_flops_per_launch"] = flops
+    roof["traffic"] = measured_traffic(dom)
+    phase_report = {}
+    for p, (t, c) in phases.items():
+        if c:
+            b, fl = algorithmic(p, info, N, M, d, P, "fp32")
+            phase_report[p] = dict(avg_us=t / c * 1e3, launches_per_step=c / args.steps,
+                                   hbm_frac=(b / (t / c * 1e-3)) / (PEAK["hbm_GBs"] * 1e9))
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "scale: d=50 N=M=60000 10-component Gaussian mixture, "
+                               "w~N(0,1), P=1000 distance-QMC, N_ft=1024",
+                   "kernel": args.kernel, "N": N, "M": M, "d": d, "P": P,
+                   "n_ft": cfg["n_ft"], "window_w": info["window_w"],
+                   "n_grid": info["n_grid"], "sigma": cfg["scale"], "R": cfg["R"]},
+        "roofline": roof,
+        "phases": phase_report,
+    }
+    s_host = s.cpu().numpy()
+    plan.close()
+    del x, y, w, s
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle on {args.cpu_sample} targets")
+        base, err, idx, _ = cpu_baseline(cfg, s_host, args.cpu_sample)
+        result["cpu_baseline"] = base
+        result["accuracy"] = {"rel_l2_vs_fp64_direct": err, "sample_targets": len(idx),
+                              "note": "error of the slicing estimator at this P (method "
+                                      "error dominates; window + FP32 error <= 1e-4)"}
+    if not args.no_forms:
+        forms = {}
+        fsteps = max(3, args.steps // 4)
+        log("bench: form laplace")
+        forms["laplace_fp32"] = run_form("laplace", make_config("scale", kernel="laplace"),
+                                         fsteps, 2, err_targets=64)
+        log("bench: form precision (d=784)")
+        cfg3 = make_config("precision")
+        forms["precision_fp32"] = run_form("precision", cfg3, fsteps, 1, proj="fp32",
+                                           err_targets=16)
+        forms["precision_bf16"] = run_form("precision", cfg3, fsteps, 1, proj="bf16",
+                                           err_targets=16)
+        del cfg3
+        log("bench: form mmd (forward + adjoint)")
+        forms["mmd_gauss_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="gauss"),
+                                               fsteps, 2, grad=True)
+        forms["mmd_energy_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="energy"),
+                                                fsteps, 2, grad=True)
+        result["forms"] = forms
+    result["wall_s"] = time.perf_counter() - t_start
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -119,6 +119,8 @@ typedef struct {
     uint32_t flags;
     int32_t grid_lo;     /* first grid cell that points inside the bound touch */
     int32_t grid_nr;     /* number of such cells (stored grids hold these)    */
+    int32_t last_spread_chunks;  /* source chunks of the last exec's spread   */
+    int32_t last_gather_groups;  /* direction groups of the last exec's gather */
 } fastsum_plan_info;
 
 typedef struct fastsum_plan_s* fastsum_plan;
@@ -201,6 +203,28 @@ FASTSUM_API fastsum_status fastsum_host_tables(const fastsum_params* prm, double
  */
 FASTSUM_API fastsum_status fastsum_debug_read(fastsum_plan plan, int32_t which,
                                   float* host_out, int64_t count);
+
+/*
+ * Per-phase timing.  While enabled, every exec/grad records a pair of HIP
+ * events on its stream around each kernel launch of a phase.
+ * fastsum_profile_read synchronises those events, adds their elapsed times
+ * per phase into ms_total[FASTSUM_PHASE_COUNT] and counts launches into
+ * launches[FASTSUM_PHASE_COUNT] (both may be NULL), then forgets them.
+ * Errors: EINVAL, EDEVICE.
+ */
+typedef enum {
+    FASTSUM_PHASE_PROJECT = 0,     /* x~ = tau X Xi (and y~)                */
+    FASTSUM_PHASE_SPREAD = 1,      /* window spreading onto the grids       */
+    FASTSUM_PHASE_FFTCONV = 2,     /* FFT, coefficient multiply, inverse FFT */
+    FASTSUM_PHASE_GATHER = 3,      /* window interpolation + FP64 sum over P */
+    FASTSUM_PHASE_REDUCE = 4,      /* final FP64 reduction of partial sums   */
+    FASTSUM_PHASE_BACKPROJECT = 5, /* grad_y = (tau/P) sum_p xi_p t'_p       */
+    FASTSUM_PHASE_COUNT = 6
+} fastsum_phase;
+
+FASTSUM_API fastsum_status fastsum_profile(fastsum_plan plan, int32_t enable);
+FASTSUM_API fastsum_status fastsum_profile_read(fastsum_plan plan, double* ms_total,
+                                                int64_t* launches);
 
 /* Static, human-readable name of a status code. */
 FASTSUM_API const char* fastsum_status_string(fastsum_status status);

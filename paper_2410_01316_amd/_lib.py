@@ -9,6 +9,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EUNSUPPORTED, ESTATE = range(7)
 KERNELS = {"gauss": 0, "laplace": 1, "energy": 2}
 PROJ = {"fp32": 0, "bf16": 1}
 FLAG_GRAD = 1
+PHASES = ("project", "spread", "fftconv", "gather", "reduce", "backproject")
 
 
 class Params(ctypes.Structure):
@@ -29,6 +30,7 @@ class PlanInfo(ctypes.Structure):
         ("n_max", ctypes.c_int64), ("m_max", ctypes.c_int64),
         ("proj", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("grid_lo", ctypes.c_int32), ("grid_nr", ctypes.c_int32),
+        ("last_spread_chunks", ctypes.c_int32), ("last_gather_groups", ctypes.c_int32),
     ]
 
 
@@ -46,6 +48,8 @@ SIGNATURES = {
     "fastsum_host_tables": (_st, [ctypes.POINTER(Params), _vp, _vp, _vp]),
     "fastsum_debug_read": (_st, [_vp, ctypes.c_int32, _vp, _i64]),
     "fastsum_status_string": (ctypes.c_char_p, [_st]),
+    "fastsum_profile": (_st, [_vp, ctypes.c_int32]),
+    "fastsum_profile_read": (_st, [_vp, _vp, _vp]),
 }
 
 _lib = None

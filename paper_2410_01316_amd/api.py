@@ -120,6 +120,20 @@ class Plan:
         L.check(st, "fastsum_debug_read")
         return out
 
+    def profile(self, enable=True):
+        """Record HIP events around every kernel launch of later calls."""
+        L.check(self._lib.fastsum_profile(self._h, 1 if enable else 0), "fastsum_profile")
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} since the last read (synchronises)."""
+        ms = np.zeros(len(L.PHASES))
+        cnt = np.zeros(len(L.PHASES), dtype=np.int64)
+        with torch.cuda.device(self.device):
+            st = self._lib.fastsum_profile_read(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                                cnt.ctypes.data_as(ctypes.c_void_p))
+        L.check(st, "fastsum_profile_read")
+        return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(L.PHASES)}
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             self._lib.fastsum_destroy(self._h)

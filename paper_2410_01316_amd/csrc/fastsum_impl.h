@@ -45,9 +45,11 @@ hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
 
 // partial[(c*P + p)*nr + j - lo] = sum over sources i of chunk c of
 //   w[i] * window(cell j - u(proj[p*ld + i]))
+// chunk_len must be a multiple of 4 * kBlock and below 2^21; chunk_exp is
+// scratch for nchunk ints.
 hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
                          int64_t N, int P, GridGeom g, int nchunk,
-                         int64_t chunk_len, const WindowArgs& win,
+                         int64_t chunk_len, int* chunk_exp, const WindowArgs& win,
                          float* partial, hipStream_t stream);
 
 // Per pair of directions: sum the chunk partials, complex FFT of size n,

@@ -82,14 +82,29 @@ __global__ __launch_bounds__(kBlock) void project_f32_kernel(
 
     for (int k0 = 0; k0 < d; k0 += kProjKC) {
         const int kc = min(kProjKC, d - k0);
-        __syncthreads();
-        for (int e = tid; e < kProjBM * kProjKC; e += kBlock) {
-            const int r = e / kProjKC, k = e % kProjKC;
-            As[r][k] = (k < kc && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k0 + k] : 0.f;
+        // issue every load of the stage before touching LDS
+        constexpr int QA = kProjBM * kProjKC / kBlock, QX = kProjBN * kProjKC / kBlock;
+        float va[QA], vx[QX];
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * kBlock, r = e / kProjKC, k = e % kProjKC;
+            va[q] = (k < kc && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k0 + k] : 0.f;
         }
-        for (int e = tid; e < kProjBN * kProjKC; e += kBlock) {
-            const int r = e / kProjKC, k = e % kProjKC;
-            Xs[r][k] = (k < kc && n0 + r < N) ? X[(n0 + r) * d + k0 + k] : 0.f;
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int e = tid + q * kBlock, r = e / kProjKC, k = e % kProjKC;
+            vx[q] = (k < kc && n0 + r < N) ? X[(n0 + r) * d + k0 + k] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * kBlock;
+            As[e / kProjKC][e % kProjKC] = va[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int e = tid + q * kBlock;
+            Xs[e / kProjKC][e % kProjKC] = vx[q];
         }
         __syncthreads();
         for (int ks = 0; ks < kc; ks += 4) {
@@ -152,14 +167,29 @@ __global__ __launch_bounds__(kBlock) void project_bf16_kernel(
 
     for (int k0 = 0; k0 < d; k0 += kProjKCh) {
         const int kc = min(kProjKCh, d - k0);
-        __syncthreads();
-        for (int e = tid; e < kProjBM * kProjKCh; e += kBlock) {
-            const int r = e / kProjKCh, k = e % kProjKCh;
-            As[r][k] = (k < kc && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k0 + k] : (unsigned short)0;
+        constexpr int QA = kProjBM * kProjKCh / kBlock, QX = kProjBN * kProjKCh / kBlock;
+        unsigned short va[QA];
+        float vx[QX];
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * kBlock, r = e / kProjKCh, k = e % kProjKCh;
+            va[q] = (k < kc && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k0 + k] : (unsigned short)0;
         }
-        for (int e = tid; e < kProjBN * kProjKCh; e += kBlock) {
-            const int r = e / kProjKCh, k = e % kProjKCh;
-            Xs[r][k] = (k < kc && n0 + r < N) ? f32_to_bf16_rne(X[(n0 + r) * d + k0 + k]) : (unsigned short)0;
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int e = tid + q * kBlock, r = e / kProjKCh, k = e % kProjKCh;
+            vx[q] = (k < kc && n0 + r < N) ? X[(n0 + r) * d + k0 + k] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * kBlock;
+            As[e / kProjKCh][e % kProjKCh] = va[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int e = tid + q * kBlock;
+            Xs[e / kProjKCh][e % kProjKCh] = f32_to_bf16_rne(vx[q]);
         }
         __syncthreads();
         for (int ks = 0; ks < kc; ks += 32) {
@@ -217,46 +247,117 @@ hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
 
 // ---------------------------------------------------------------------------
 // spread: one workgroup = one direction x one chunk of sources
+//
+// LDS float atomics are slow on this chip, integer ones are not: every tap
+// w * phi is scaled by 2^k (k chosen per chunk so that |w| 2^k < 2^40),
+// rounded to a 64-bit integer and added with an integer LDS atomic.  The sum
+// is exact (no overflow for chunks below 2^21 sources) and independent of
+// the order of the atomics, so the spread grids are bitwise reproducible.
 // ---------------------------------------------------------------------------
+
+// k per chunk: |w_i| < 2^(40 - k) for every source i of the chunk.
+__global__ __launch_bounds__(kBlock) void chunk_scale_kernel(
+    const float* __restrict__ w, int64_t N, int64_t chunk_len, int* __restrict__ chunk_exp) {
+    __shared__ float red[kBlock];
+    const int64_t i0 = (int64_t)blockIdx.x * chunk_len;
+    const int64_t i1 = min(N, i0 + chunk_len);
+    float m = 0.f;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) m = fmaxf(m, fabsf(w[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float mx = red[0];
+        int e = 0;
+        if (mx > 0.f && mx <= 3.4e38f) (void)frexpf(mx, &e);   // mx < 2^e
+        chunk_exp[blockIdx.x] = (mx > 0.f && mx <= 3.4e38f) ? 40 - e : 0;
+    }
+}
+
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+    // round(v) as a two's-complement 64-bit integer, valid for |v| < 2^51
+    const double kMagic = 6755399441055744.0;   // 1.5 * 2^52
+    return (unsigned long long)(__double_as_longlong((double)v + kMagic) -
+                                __double_as_longlong(kMagic));
+}
+
+template <int W>
+__device__ __forceinline__ void spread_point(float xt, float ws, const GridGeom& g,
+                                             const WindowArgs& win,
+                                             unsigned long long* lds64) {
+    float sp;
+    const int base = grid_position(xt, g, W / 2 - 1, sp);
+    float wt[W];
+    window_weights<W>(sp, win, wt);
+#pragma unroll
+    for (int t = 0; t < W; ++t) atomicAdd(&lds64[base + t], to_fixed(ws * wt[t]));
+}
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void spread_kernel(
     const float* __restrict__ proj, int64_t ld, const float* __restrict__ w,
-    int64_t N, int P, GridGeom g, int64_t chunk_len, WindowArgs win,
-    float* __restrict__ partial) {
-    extern __shared__ float lds[];
+    int64_t N, int P, GridGeom g, int64_t chunk_len, const int* __restrict__ chunk_exp,
+    WindowArgs win, float* __restrict__ partial) {
+    extern __shared__ unsigned long long lds64[];
     const int p = blockIdx.x;
     const int c = blockIdx.y;
-    for (int j = threadIdx.x; j < g.nr; j += kBlock) lds[j] = 0.f;
+    for (int j = threadIdx.x; j < g.nr; j += kBlock) lds64[j] = 0ull;
     __syncthreads();
-    const int64_t i0 = (int64_t)c * chunk_len;
+    const int k = chunk_exp[c];
+    const float scale = ldexpf(1.f, k);
+    const int64_t i0 = (int64_t)c * chunk_len;          // multiple of 4
     const int64_t i1 = min(N, i0 + chunk_len);
     const float* __restrict__ row = proj + (int64_t)p * ld;
-#pragma unroll 4
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        float sp;
-        const int base = grid_position(row[i], g, W / 2 - 1, sp);
-        float wt[W];
-        window_weights<W>(sp, win, wt);
-        const float wi = w[i];
-#pragma unroll
-        for (int t = 0; t < W; ++t) atomicAdd(&lds[base + t], wi * wt[t]);
+    // four consecutive sources per thread and step; the projection row is
+    // padded to a multiple of 64 floats, weights past the chunk count as 0
+    int64_t i = i0 + 4 * threadIdx.x;
+    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f), wv = xv;
+    if (i < i1) {
+        xv = *reinterpret_cast<const float4*>(row + i);
+        wv.x = w[i];
+        wv.y = (i + 1 < i1) ? w[i + 1] : 0.f;
+        wv.z = (i + 2 < i1) ? w[i + 2] : 0.f;
+        wv.w = (i + 3 < i1) ? w[i + 3] : 0.f;
+    }
+    for (; i < i1; i += 4 * kBlock) {
+        const int64_t inext = i + 4 * kBlock;
+        float4 xn = xv, wn = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (inext < i1) {
+            xn = *reinterpret_cast<const float4*>(row + inext);
+            wn.x = w[inext];
+            wn.y = (inext + 1 < i1) ? w[inext + 1] : 0.f;
+            wn.z = (inext + 2 < i1) ? w[inext + 2] : 0.f;
+            wn.w = (inext + 3 < i1) ? w[inext + 3] : 0.f;
+        }
+        spread_point<W>(xv.x, wv.x * scale, g, win, lds64);
+        spread_point<W>(xv.y, wv.y * scale, g, win, lds64);
+        spread_point<W>(xv.z, wv.z * scale, g, win, lds64);
+        spread_point<W>(xv.w, wv.w * scale, g, win, lds64);
+        xv = xn;
+        wv = wn;
     }
     __syncthreads();
+    const double unscale = ldexp(1.0, -k);
     float* __restrict__ dst = partial + ((int64_t)c * P + p) * g.nr;
-    for (int j = threadIdx.x; j < g.nr; j += kBlock) dst[j] = lds[j];
+    for (int j = threadIdx.x; j < g.nr; j += kBlock)
+        dst[j] = (float)((double)(long long)lds64[j] * unscale);
 }
 
 hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
                          int64_t N, int P, GridGeom g, int nchunk,
-                         int64_t chunk_len, const WindowArgs& win,
+                         int64_t chunk_len, int* chunk_exp, const WindowArgs& win,
                          float* partial, hipStream_t stream) {
+    hipLaunchKernelGGL(chunk_scale_kernel, dim3((unsigned)nchunk), dim3(kBlock), 0, stream, w, N,
+                       chunk_len, chunk_exp);
     dim3 grid((unsigned)P, (unsigned)nchunk);
-    const size_t lds = (size_t)g.nr * sizeof(float);
+    const size_t lds = (size_t)g.nr * sizeof(unsigned long long);
     switch (W) {
-        case 4: hipLaunchKernelGGL(spread_kernel<4>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, win, partial); break;
-        case 6: hipLaunchKernelGGL(spread_kernel<6>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, win, partial); break;
-        case 8: hipLaunchKernelGGL(spread_kernel<8>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, win, partial); break;
+        case 4: hipLaunchKernelGGL(spread_kernel<4>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial); break;
+        case 6: hipLaunchKernelGGL(spread_kernel<6>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial); break;
+        case 8: hipLaunchKernelGGL(spread_kernel<8>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -376,7 +477,20 @@ hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
 // gather: one workgroup = a tile of targets x a group of directions
 // ---------------------------------------------------------------------------
 
-constexpr int kGatherTPT = 4;   // targets per thread
+constexpr int kGatherTPT = 4;   // consecutive targets per thread (one float4)
+
+template <int W>
+__device__ __forceinline__ float interp(float xt, const float* gl, const GridGeom& g,
+                                        const WindowArgs& win) {
+    float sp;
+    const int base = grid_position(xt, g, W / 2 - 1, sp);
+    float wt[W];
+    window_weights<W>(sp, win, wt);
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < W; ++k) t = fmaf(gl[base + k], wt[k], t);
+    return t;
+}
 
 template <int W, bool WRITE_T>
 __global__ __launch_bounds__(kBlock) void gather_kernel(
@@ -386,46 +500,61 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(
     int64_t ld_t) {
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
-    const int64_t m0 = (int64_t)blockIdx.x * (kBlock * kGatherTPT);
+    const int64_t m = (int64_t)blockIdx.x * (kBlock * kGatherTPT) + kGatherTPT * tid;
+    const bool active = m < M;
     const int p_begin = blockIdx.y * pg;
     const int p_end = min(P, p_begin + pg);
-    double acc[kGatherTPT];
-#pragma unroll
-    for (int s = 0; s < kGatherTPT; ++s) acc[s] = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int ps = p_begin; ps < p_end; ps += pstage) {
         const int np = min(pstage, p_end - ps);
         __syncthreads();
-        const float* __restrict__ src = grid + (int64_t)ps * g.nr;
-        for (int j = tid; j < np * g.nr; j += kBlock) lds[j] = src[j];
+        {   // stage np grids (np * nr floats, nr a multiple of 4)
+            const float4* __restrict__ src4 = reinterpret_cast<const float4*>(grid + (int64_t)ps * g.nr);
+            float4* dst4 = reinterpret_cast<float4*>(lds);
+            const int n4 = np * g.nr / 4;
+            int j = tid;
+            for (; j + 3 * kBlock < n4; j += 4 * kBlock) {
+                const float4 v0 = src4[j], v1 = src4[j + kBlock], v2 = src4[j + 2 * kBlock],
+                             v3 = src4[j + 3 * kBlock];
+                dst4[j] = v0;
+                dst4[j + kBlock] = v1;
+                dst4[j + 2 * kBlock] = v2;
+                dst4[j + 3 * kBlock] = v3;
+            }
+            for (; j < n4; j += kBlock) dst4[j] = src4[j];
+        }
         __syncthreads();
-        for (int pp = 0; pp < np; ++pp) {
-            const float* __restrict__ row = proj + (int64_t)(ps + pp) * ld;
-            const float* gl = lds + pp * g.nr;
-#pragma unroll
-            for (int s = 0; s < kGatherTPT; ++s) {
-                const int64_t m = m0 + s * kBlock + tid;
-                if (m < M) {
-                    float sp;
-                    const int base = grid_position(row[m], g, W / 2 - 1, sp);
-                    float wt[W];
-                    window_weights<W>(sp, win, wt);
-                    float t = 0.f;
-#pragma unroll
-                    for (int k = 0; k < W; ++k) t = fmaf(gl[base + k], wt[k], t);
-                    if (WRITE_T)
-                        tout[(int64_t)(ps + pp) * ld_t + m] = t;
-                    else
-                        acc[s] += (double)t;
+        if (active) {
+            // rows are padded to a multiple of 64 floats: the float4 at m is in bounds
+            const float* __restrict__ rowp = proj + (int64_t)ps * ld + m;
+            float4 cur = *reinterpret_cast<const float4*>(rowp);
+            for (int pp = 0; pp < np; ++pp) {
+                float4 nxt = cur;
+                if (pp + 1 < np) nxt = *reinterpret_cast<const float4*>(rowp + (int64_t)(pp + 1) * ld);
+                const float* gl = lds + pp * g.nr;
+                const float t0 = interp<W>(cur.x, gl, g, win);
+                const float t1 = interp<W>(cur.y, gl, g, win);
+                const float t2 = interp<W>(cur.z, gl, g, win);
+                const float t3 = interp<W>(cur.w, gl, g, win);
+                if (WRITE_T) {
+                    *reinterpret_cast<float4*>(tout + (int64_t)(ps + pp) * ld_t + m) =
+                        make_float4(t0, t1, t2, t3);
+                } else {
+                    a0 += (double)t0;
+                    a1 += (double)t1;
+                    a2 += (double)t2;
+                    a3 += (double)t3;
                 }
+                cur = nxt;
             }
         }
     }
-    if (!WRITE_T) {
-#pragma unroll
-        for (int s = 0; s < kGatherTPT; ++s) {
-            const int64_t m = m0 + s * kBlock + tid;
-            if (m < M) spart[(int64_t)blockIdx.y * ldm + m] = acc[s];
-        }
+    if (!WRITE_T && active) {
+        double* __restrict__ dst = spart + (int64_t)blockIdx.y * ldm + m;
+        dst[0] = a0;
+        if (m + 1 < M) dst[1] = a1;
+        if (m + 2 < M) dst[2] = a2;
+        if (m + 3 < M) dst[3] = a3;
     }
 }
 

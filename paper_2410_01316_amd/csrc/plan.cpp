@@ -287,21 +287,31 @@ struct fastsum_plan_s {
     float2* mult_d = nullptr;
     float2* tw = nullptr;
     int* flag = nullptr;
+    int* chunk_exp = nullptr;      // per-chunk fixed-point exponents
     // last exec
     bool have_exec = false, last_same = false;
     const float* last_x = nullptr;
     const float* last_w = nullptr;
     const float* last_y = nullptr;
     int64_t last_N = 0, last_M = 0;
+    int last_nchunk = 0, last_ngroup = 0;
     hipStream_t last_stream = nullptr;
+    // profiling
+    struct Rec { int phase; hipEvent_t a, b; };
+    bool prof = false;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
 
 void free_plan(fastsum_plan_s* p) {
     if (!p) return;
+    for (auto& r : p->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : p->pool) (void)hipEventDestroy(e);
     void* bufs[] = {p->A, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
-                    p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag};
+                    p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
+                    p->chunk_exp};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -313,11 +323,48 @@ bool dev_alloc(T** ptr, size_t count) {
     return hipMalloc((void**)ptr, count * sizeof(T)) == hipSuccess;
 }
 
+hipEvent_t take_event(fastsum_plan_s* p) {
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records HIP events around one kernel launch when profiling is enabled.
+struct PhaseTimer {
+    fastsum_plan_s* p;
+    int phase;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    PhaseTimer(fastsum_plan_s* pl, int ph, hipStream_t s) : p(pl), phase(ph), st(s) {
+        if (p->prof && (a = take_event(p)) != nullptr) (void)hipEventRecord(a, st);
+    }
+    ~PhaseTimer() {
+        if (!a) return;
+        hipEvent_t b = take_event(p);
+        if (!b) { p->pool.push_back(a); return; }
+        (void)hipEventRecord(b, st);
+        p->recs.push_back({phase, a, b});
+    }
+};
+
+constexpr int64_t kChunkAlign = 4 * kBlock;      // spread chunks start on float4 steps
+constexpr int64_t kMaxChunk = (int64_t)1 << 20;   // keeps the 64-bit fixed-point sums exact
+
 int spread_chunks(int64_t N, int P) {
-    // aim for >= 2048 workgroups, chunks of >= 2048 sources
+    // aim for >= 2048 workgroups, chunks of >= 4096 sources, <= 2^20 sources
     int64_t want = (2048 + P - 1) / P;
-    int64_t maxc = std::max<int64_t>(1, (N + 2047) / 2048);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxc, 64)));
+    int64_t maxc = std::max<int64_t>(1, (N + 4095) / 4096);
+    int64_t c = std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxc, 64)));
+    return (int)std::max<int64_t>(c, (N + kMaxChunk - 1) / kMaxChunk);
+}
+
+int64_t spread_chunk_len(int64_t N, int nchunk) {
+    return round_up((N + nchunk - 1) / nchunk, kChunkAlign);
 }
 
 int gather_group(int64_t M, int P, int pstage) {
@@ -351,21 +398,34 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
                         float* grid_d, hipStream_t st) {
     const int P = pl->P;
     const int nchunk = spread_chunks(Nsrc, P);
-    const int64_t chunk_len = round_up((Nsrc + nchunk - 1) / nchunk, kBlock);
-    FS_TRY(launch_spread(pl->W, src_proj, ld_src, wts, Nsrc, P, pl->geom, nchunk, chunk_len,
-                         pl->win_args, pl->partial, st));
-    FS_TRY(launch_fftconv(pl->partial, nchunk, P, pl->geom, pl->tw, pl->mult, pl->mult_d,
-                          grid, grid_d, st));
+    const int64_t chunk_len = spread_chunk_len(Nsrc, nchunk);
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
+        FS_TRY(launch_spread(pl->W, src_proj, ld_src, wts, Nsrc, P, pl->geom, nchunk, chunk_len,
+                             pl->chunk_exp, pl->win_args, pl->partial, st));
+    }
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
+        FS_TRY(launch_fftconv(pl->partial, nchunk, P, pl->geom, pl->tw, pl->mult, pl->mult_d,
+                              grid, grid_d, st));
+    }
     const int pg = gather_group(Mtgt, P, pl->pstage);
     const int ng = (P + pg - 1) / pg;
-    FS_TRY(launch_gather(pl->W, tgt_proj, ld_tgt, Mtgt, P, pl->geom, grid, pg, pl->pstage,
-                         pl->win_args, pl->spart, pl->ldm, nullptr, 0, st));
+    pl->last_nchunk = nchunk;
+    pl->last_ngroup = ng;
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
+        FS_TRY(launch_gather(pl->W, tgt_proj, ld_tgt, Mtgt, P, pl->geom, grid, pg, pl->pstage,
+                             pl->win_args, pl->spart, pl->ldm, nullptr, 0, st));
+    }
+    PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
     FS_TRY(launch_reduce(pl->spart, ng, pl->ldm, Mtgt, 1.0 / P, out, st));
     return FASTSUM_OK;
 }
 
 fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out, int64_t ld,
                        hipStream_t st) {
+    PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
     if (pl->r.p.proj == FASTSUM_PROJ_BF16)
         return check(launch_project_bf16(X, N, pl->d, pl->dpad, pl->A16, pl->P, out, ld,
                                          pl->bound, pl->flag, st));
@@ -459,7 +519,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
               dev_alloc(&pl->grid, (size_t)P * nr) &&
               dev_alloc(&pl->spart, (size_t)pl->ngroup_cap * pl->ldm) &&
               dev_alloc(&pl->mult, (size_t)n) && dev_alloc(&pl->tw, (size_t)n) &&
-              dev_alloc(&pl->flag, 1);
+              dev_alloc(&pl->flag, 1) && dev_alloc(&pl->chunk_exp, (size_t)pl->nchunk_cap);
     if (ok && grad)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
              dev_alloc(&pl->mult_d, (size_t)n) && dev_alloc(&pl->tprime, (size_t)P * pl->ld_y);
@@ -555,8 +615,12 @@ fastsum_status fastsum_grad(fastsum_plan pl, const float* grad_s, float* grad_y,
     if (grad_y) {
         // t'_{m,p}: interpolate the derivative grids of the last exec
         const int pg = gather_group(M, P, pl->pstage);
-        FS_TRY(launch_gather(pl->W, yp, ldy, M, P, pl->geom, pl->grid_d, pg, pl->pstage,
-                             pl->win_args, nullptr, 0, pl->tprime, pl->ld_y, st));
+        {
+            PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
+            FS_TRY(launch_gather(pl->W, yp, ldy, M, P, pl->geom, pl->grid_d, pg, pl->pstage,
+                                 pl->win_args, nullptr, 0, pl->tprime, pl->ld_y, st));
+        }
+        PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
         FS_TRY(launch_backproject(pl->tprime, pl->ld_y, M, P, pl->d, pl->A, pl->dpad,
                                   (float)(1.0 / P), grad_s, grad_y, st));
     }
@@ -593,6 +657,8 @@ fastsum_status fastsum_get_info(fastsum_plan pl, fastsum_plan_info* info) {
     info->flags = pl->r.p.flags;
     info->grid_lo = pl->geom.lo;
     info->grid_nr = pl->geom.nr;
+    info->last_spread_chunks = pl->last_nchunk;
+    info->last_gather_groups = pl->last_ngroup;
     return FASTSUM_OK;
 }
 
@@ -615,6 +681,30 @@ fastsum_status fastsum_debug_read(fastsum_plan pl, int32_t which, float* host_ou
                     rows, hipMemcpyDeviceToHost) != hipSuccess)
         return FASTSUM_EDEVICE;
     return FASTSUM_OK;
+}
+
+fastsum_status fastsum_profile(fastsum_plan pl, int32_t enable) {
+    if (!pl) return FASTSUM_EINVAL;
+    pl->prof = enable != 0;
+    return FASTSUM_OK;
+}
+
+fastsum_status fastsum_profile_read(fastsum_plan pl, double* ms_total, int64_t* launches) {
+    if (!pl) return FASTSUM_EINVAL;
+    if (ms_total) std::fill(ms_total, ms_total + FASTSUM_PHASE_COUNT, 0.0);
+    if (launches) std::fill(launches, launches + FASTSUM_PHASE_COUNT, (int64_t)0);
+    fastsum_status st = FASTSUM_OK;
+    for (auto& r : pl->recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            st = FASTSUM_EDEVICE;
+        if (ms_total) ms_total[r.phase] += ms;
+        if (launches) launches[r.phase] += 1;
+        pl->pool.push_back(r.a);
+        pl->pool.push_back(r.b);
+    }
+    pl->recs.clear();
+    return st;
 }
 
 }  // extern "C"

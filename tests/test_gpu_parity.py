@@ -159,7 +159,9 @@ def test_repeated_calls_and_reuse_smaller_inputs():
     x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
     a = plan(x, w, y).cpu().numpy()
     b = plan(x, w, y).cpu().numpy()
-    assert rel_l2(a, b) < 1e-6            # LDS atomics: order may differ
+    # spreading accumulates exact 64-bit fixed-point sums and nothing else
+    # uses atomics, so repeated calls are bitwise identical
+    assert np.array_equal(a, b)
     c = plan(x[:300].contiguous(), w[:300].contiguous(), y[:200].contiguous()).cpu().numpy()
     sub = dict(cfg, x=cfg["x"][:300], w=cfg["w"][:300], y=cfg["y"][:200])
     assert rel_l2(c, _o3(sub)) < 1e-4
