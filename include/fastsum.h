@@ -205,6 +205,90 @@ FASTSUM_API fastsum_status fastsum_debug_read(fastsum_plan plan, int32_t which,
                                   float* host_out, int64_t count);
 
 /*
+ * Batched form: many independent kernel-sum problems that share the kernel
+ * type, P, the window and T, run by ONE persistent launch per phase
+ * (projection, chunk scaling, spreading, FFT convolution, gather, reduction)
+ * whose workgroups walk a task list of tiles drawn from every problem.  The
+ * six launches are captured into a HIP graph on a private stream and the
+ * graph is replayed while pointers and sizes repeat.
+ *
+ * Per problem at plan time: d_i, n_ft_i, scale_i, R_i, directions xi_i
+ * (HOST, d_i x P row-major, as in fastsum_plan_create) and capacities.
+ */
+typedef struct {
+    int32_t d;
+    int32_t n_ft;
+    double scale;
+    double R;
+    const float* xi;     /* host, d x P */
+    int64_t n_max, m_max;
+} fastsum_problem_desc;
+
+/* Per problem at exec time: device pointers and sizes, 1 <= N <= n_max,
+ * 1 <= M <= m_max; y may equal x (then N must equal M). */
+typedef struct {
+    const float* x;      /* N x d */
+    const float* w;      /* N     */
+    const float* y;      /* M x d */
+    float* s;            /* M, written */
+    int64_t N, M;
+} fastsum_problem_io;
+
+/* Launch-shape knobs (chosen by an autotuner); 0 selects the default. */
+typedef struct {
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4)  */
+    int32_t spread_chunk;   /* sources per spread tile, multiple of 4096           */
+    int32_t gather_group;   /* directions per gather tile, multiple of 8            */
+    int32_t use_graph;      /* 0/1: capture and replay a HIP graph (default); -1:  */
+                            /* launch the phases directly on the caller's stream  */
+} fastsum_batch_tuning;
+
+typedef struct fastsum_batch_s* fastsum_batch;
+
+/*
+ * common supplies kernel, P, window_w, oversample, T and gmax_factor; proj
+ * must be FASTSUM_PROJ_FP32 and flags 0 (no adjoint in the batched form).
+ * d, n_ft, scale and R of common are ignored.  tuning may be NULL.
+ * Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED (BF16 or GRAD requested).
+ */
+FASTSUM_API fastsum_status fastsum_batch_create(const fastsum_params* common,
+                                                const fastsum_problem_desc* probs,
+                                                int32_t n_problems,
+                                                const fastsum_batch_tuning* tuning,
+                                                void* stream, fastsum_batch* out);
+
+/* Replace the launch-shape knobs (drops the captured graph). */
+FASTSUM_API fastsum_status fastsum_batch_set_tuning(fastsum_batch batch,
+                                                    const fastsum_batch_tuning* tuning);
+
+/*
+ * Run every problem: s_i ~ sum_n w_{i,n} F(||x_{i,n} - y_{i,m}||).  io has
+ * n_problems entries in creation order.  When pointers or sizes differ from
+ * the previous call the task lists are rebuilt, uploaded and the graph is
+ * re-captured (this path synchronises `stream` once); otherwise the graph is
+ * replayed on `stream` asynchronously.  Errors: EINVAL, EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_batch_exec(fastsum_batch batch,
+                                              const fastsum_problem_io* io,
+                                              int32_t n_problems, void* stream);
+
+/* As fastsum_check, for every problem of the batch. */
+FASTSUM_API fastsum_status fastsum_batch_check(fastsum_batch batch);
+
+FASTSUM_API void fastsum_batch_destroy(fastsum_batch batch);
+
+/*
+ * Host-only N_ft selection rule: the smallest candidate N_ft whose discarded
+ * Fourier mass sum_{|k| > N_ft/2} |c_k| is at most tol * sum_k |c_k| (FP64,
+ * c_k of prm's kernel, d, scale, T, R; tails summed to |k| = 4096).  Falls
+ * back to the largest candidate.  Errors: EINVAL.
+ */
+FASTSUM_API fastsum_status fastsum_choose_nft(const fastsum_params* prm,
+                                              const int32_t* candidates,
+                                              int32_t n_candidates, double tol,
+                                              int32_t* chosen);
+
+/*
  * Per-phase timing.  While enabled, every exec/grad records a pair of HIP
  * events on its stream around each kernel launch of a phase.
  * fastsum_profile_read synchronises those events, adds their elapsed times

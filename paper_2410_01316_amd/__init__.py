@@ -7,6 +7,7 @@ The computation lives in libfastsum.so (HIP kernels for gfx950 behind the C
 ABI of include/fastsum.h); this package only marshals arguments.
 """
 from ._lib import FastSumError, load as load_library, LIB_PATH
-from .api import Plan, FastSum, host_tables
+from .api import Plan, FastSum, Batch, host_tables, choose_nft
 
-__all__ = ["Plan", "FastSum", "FastSumError", "host_tables", "load_library", "LIB_PATH"]
+__all__ = ["Plan", "FastSum", "Batch", "FastSumError", "host_tables", "choose_nft",
+           "load_library", "LIB_PATH"]

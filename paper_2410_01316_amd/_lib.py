@@ -34,6 +34,22 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n_ft", ctypes.c_int32), ("scale", ctypes.c_double),
+                ("R", ctypes.c_double), ("xi", ctypes.c_void_p), ("n_max", ctypes.c_int64),
+                ("m_max", ctypes.c_int64)]
+
+
+class ProblemIO(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("w", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("s", ctypes.c_void_p), ("N", ctypes.c_int64), ("M", ctypes.c_int64)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("spread_chunk", ctypes.c_int32),
+                ("gather_group", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _st = ctypes.c_int
@@ -49,6 +65,14 @@ SIGNATURES = {
     "fastsum_debug_read": (_st, [_vp, ctypes.c_int32, _vp, _i64]),
     "fastsum_status_string": (ctypes.c_char_p, [_st]),
     "fastsum_profile": (_st, [_vp, ctypes.c_int32]),
+    "fastsum_batch_create": (_st, [ctypes.POINTER(Params), ctypes.POINTER(ProblemDesc), ctypes.c_int32,
+                                   ctypes.POINTER(BatchTuning), _vp, ctypes.POINTER(_vp)]),
+    "fastsum_batch_set_tuning": (_st, [_vp, ctypes.POINTER(BatchTuning)]),
+    "fastsum_batch_exec": (_st, [_vp, ctypes.POINTER(ProblemIO), ctypes.c_int32, _vp]),
+    "fastsum_batch_check": (_st, [_vp]),
+    "fastsum_batch_destroy": (None, [_vp]),
+    "fastsum_choose_nft": (_st, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                 ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]),
     "fastsum_profile_read": (_st, [_vp, _vp, _vp]),
 }
 

@@ -179,3 +179,105 @@ def host_tables(kernel, d, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0, window_w=
                                  ph.ctypes.data_as(ctypes.c_void_p))
     L.check(st, "fastsum_host_tables")
     return tau.value, ck, ph
+
+
+def choose_nft(kernel, d, R, scale=1.0, T=0.0, gmax_factor=0.0, candidates=(256, 512, 1024),
+               tol=1e-4):
+    """Smallest N_ft among candidates whose discarded Fourier-coefficient mass
+    is at most tol times the total (FP64 host rule of the library)."""
+    lib = L.load()
+    prm = L.Params(int(d), 1, int(candidates[0]), 0, 0, L.KERNELS[kernel], 0, 0, float(scale),
+                   float(T), float(gmax_factor), float(R))
+    arr = (ctypes.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    out = ctypes.c_int32()
+    L.check(lib.fastsum_choose_nft(ctypes.byref(prm), arr, len(candidates), float(tol),
+                                   ctypes.byref(out)), "fastsum_choose_nft")
+    return out.value
+
+
+class Batch:
+    """Many independent kernel sums (shared kernel, P, window, T) run by one
+    persistent launch per phase and replayed from a HIP graph.
+
+    problems: list of dicts with keys xi (d x P), n_ft, scale, R, n_max, m_max.
+    """
+
+    TUNING_KEYS = ("blocks_per_cu", "spread_chunk", "gather_group", "use_graph")
+
+    def __init__(self, problems, *, kernel, T=0.0, gmax_factor=0.0, window_w=0, oversample=0,
+                 tuning=None, device=None):
+        lib = L.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        xis = [np.ascontiguousarray(np.asarray(p["xi"], dtype=np.float32)) for p in problems]
+        P = {x.shape[1] for x in xis}
+        if len(P) != 1:
+            raise ValueError("every problem of a batch uses the same number of directions")
+        self.P = P.pop()
+        self.d = [x.shape[0] for x in xis]
+        self.n_max = [int(p["n_max"]) for p in problems]
+        self.m_max = [int(p["m_max"]) for p in problems]
+        descs = (L.ProblemDesc * len(problems))()
+        for i, (p, x) in enumerate(zip(problems, xis)):
+            descs[i] = L.ProblemDesc(x.shape[0], int(p["n_ft"]), float(p.get("scale", 1.0)),
+                                     float(p["R"]), x.ctypes.data_as(ctypes.c_void_p),
+                                     self.n_max[i], self.m_max[i])
+        common = L.Params(0, self.P, 0, int(window_w), int(oversample), L.KERNELS[kernel], 0, 0,
+                          1.0, float(T), float(gmax_factor), 1.0)
+        self._h = ctypes.c_void_p()
+        tun = self._tuning_struct(tuning or {})
+        with torch.cuda.device(self.device):
+            st = lib.fastsum_batch_create(ctypes.byref(common), descs, len(problems),
+                                          ctypes.byref(tun), _stream_ptr(self.device),
+                                          ctypes.byref(self._h))
+        L.check(st, "fastsum_batch_create")
+        self._lib = lib
+        self.n = len(problems)
+        self._keep = None
+        self.tuning = dict(tuning or {})
+
+    def _tuning_struct(self, t):
+        return L.BatchTuning(*[int(t.get(k, 0)) for k in self.TUNING_KEYS])
+
+    def set_tuning(self, **kw):
+        tun = self._tuning_struct(kw)
+        L.check(self._lib.fastsum_batch_set_tuning(self._h, ctypes.byref(tun)),
+                "fastsum_batch_set_tuning")
+        self.tuning = dict(kw)
+
+    def __call__(self, xs, ws, ys, outs=None):
+        """Run every problem; returns the list of result tensors."""
+        if not (len(xs) == len(ws) == len(ys) == self.n):
+            raise ValueError(f"expected {self.n} problems")
+        if outs is None:
+            outs = [torch.empty(y.shape[0], dtype=torch.float32, device=self.device) for y in ys]
+        io = (L.ProblemIO * self.n)()
+        for i in range(self.n):
+            x, w, y, s = xs[i], ws[i], ys[i], outs[i]
+            N, M = x.shape[0], y.shape[0]
+            _need(x, f"x[{i}]", (N, self.d[i]), self.device)
+            _need(w, f"w[{i}]", (N,), self.device)
+            _need(y, f"y[{i}]", (M, self.d[i]), self.device)
+            _need(s, f"s[{i}]", (M,), self.device)
+            io[i] = L.ProblemIO(x.data_ptr(), w.data_ptr(), y.data_ptr(), s.data_ptr(), N, M)
+        with torch.cuda.device(self.device):
+            st = self._lib.fastsum_batch_exec(self._h, io, self.n, _stream_ptr(self.device))
+        L.check(st, "fastsum_batch_exec")
+        self._keep = (xs, ws, ys, outs)
+        return outs
+
+    def check(self):
+        with torch.cuda.device(self.device):
+            L.check(self._lib.fastsum_batch_check(self._h), "fastsum_batch_check")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.fastsum_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -80,4 +80,58 @@ hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
                               float coef, const float* v, float* grad_y,
                               hipStream_t stream);
 
+// ---- batched form: one persistent launch per phase over a task list ----
+
+// Everything one problem of a batch needs on the device.
+struct BatchProblem {
+    const float* x;        // N x d sources   (exec time)
+    const float* w;        // N weights       (exec time)
+    const float* y;        // M x d targets   (exec time)
+    float* s;              // M results       (exec time)
+    int64_t N, M;
+    const float* A;        // tau * Xi^T, P x dpad
+    float* xproj;          // P x ldx
+    float* yproj;          // P x ldy
+    float* partial;        // nchunk x P x nr
+    float* grid;           // P x nr
+    double* spart;         // ngroup x ldm
+    int* chunk_exp;        // nchunk
+    const float2* mult;    // n coefficient multipliers
+    const float2* tw;      // n twiddles
+    int64_t ldx, ldy, ldm;
+    int64_t chunk_len;
+    GridGeom g;
+    int d, dpad;
+    int nchunk, pg, ngroup;
+    int same_xy;
+    float bound;
+};
+
+// One tile of one phase of one problem; a, b, c are phase-specific indices.
+struct BatchTask {
+    int prob;
+    int a;
+    int b;
+    int c;
+};
+
+enum BatchPhase {
+    kBatchProject = 0,   // a = 0 (x) / 1 (y), b = point tile, c = direction tile
+    kBatchScale = 1,     // a = chunk
+    kBatchSpread = 2,    // a = direction, b = chunk
+    kBatchFftconv = 3,   // a = direction pair
+    kBatchGather = 4,    // a = target tile, b = direction group
+    kBatchReduce = 5,    // a = block of kBlock targets
+    kBatchPhases = 6
+};
+
+constexpr int kProjTileP = 64;          // projection tile: directions
+constexpr int kProjTileN = 128;         // projection tile: points
+constexpr int kGatherTile = 4 * kBlock; // targets per gather tile
+
+hipError_t launch_batch_phase(int phase, int W, const BatchProblem* probs,
+                              const BatchTask* tasks, int ntasks, int P, int pstage,
+                              const WindowArgs& win, int* flag, int grid_blocks,
+                              size_t lds_bytes, hipStream_t stream);
+
 }  // namespace fastsum

@@ -3,11 +3,15 @@
 // Data flow of one summation (App. I Steps 1-3 applied per direction, then
 // the average over directions of eq. kernel_sum_sliced):
 //   project   x~ = tau <xi_p, x_n>  (P x N, direction-major)   MFMA GEMM
-//   spread    u_p[j] = sum_n w_n phi(j - u(x~_{n,p}))             LDS atomics
+//   spread    u_p[j] = sum_n w_n phi(j - u(x~_{n,p}))             LDS int64 atomics
 //   fftconv   g_p = IDFT(mult . DFT(u_p))                         LDS FFT
 //   gather    s_m = (1/P) sum_p sum_j g_p[j] phi(j - u(y~_{m,p}))  FP64 sum
 // mult_k = c'_k / (n phihat_k)^2 folds the Fourier coefficients of the
 // rescaled 1-D kernel and the window deconvolution into one table.
+//
+// Every phase is a tile function.  The single-problem kernels map
+// blockIdx to one tile; the batched kernels are persistent and walk a task
+// list of tiles drawn from many problems (one launch per phase).
 #include "fastsum_impl.h"
 
 #include <hip/hip_runtime.h>
@@ -58,22 +62,59 @@ __device__ __forceinline__ int grid_position(float xt, const GridGeom& g,
 }
 
 // ---------------------------------------------------------------------------
-// projection: out[p][j] = sum_i A[p][i] X[j][i]   (MFMA 16x16x4 f32)
+// projection: out[p][j] = sum_i A[p][i] X[j][i]   (MFMA, 64 x 128 tiles)
 // ---------------------------------------------------------------------------
 
 constexpr int kProjBM = 64;    // directions per workgroup tile
 constexpr int kProjBN = 128;   // points per workgroup tile (32 per wave)
 constexpr int kProjKC = 32;    // k-chunk staged in LDS (f32)
+constexpr int kProjKCh = 64;   // k-chunk staged in LDS (bf16)
 
-__global__ __launch_bounds__(kBlock) void project_f32_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad,
-    const float* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
-    float bound, int* __restrict__ flag) {
-    __shared__ float As[kProjBM][kProjKC + 1];
-    __shared__ float Xs[kProjBN][kProjKC + 1];
+struct ProjSmemF32 {
+    float As[kProjBM][kProjKC + 1];
+    float Xs[kProjBN][kProjKC + 1];
+};
+struct ProjSmemBF16 {
+    // row stride 72 halves = 144 bytes keeps 16-byte fragment loads aligned
+    __attribute__((aligned(16))) unsigned short As[kProjBM][kProjKCh + 8];
+    __attribute__((aligned(16))) unsigned short Xs[kProjBN][kProjKCh + 8];
+};
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)          // inf / nan: keep, quiet nan
+        return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ void project_store(const f32x4 (&acc)[4][2], int p0, int64_t n0,
+                                              int P, int64_t N, float* __restrict__ out,
+                                              int64_t ld, float bound, int* __restrict__ flag) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool bad = false;
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + bi * 16 + 4 * (lane >> 4) + r;
+                const int64_t n = n0 + wave * 32 + bj * 16 + (lane & 15);
+                if (p < P && n < N) {
+                    const float v = acc[bi][bj][r];
+                    out[(int64_t)p * ld + n] = v;
+                    bad |= !(fabsf(v) <= bound);
+                }
+            }
+    if (bad) atomicOr(flag, 1);
+}
+
+__device__ __forceinline__ void project_tile_f32(
+    ProjSmemF32& sm, const float* __restrict__ X, int64_t N, int d, int dpad,
+    const float* __restrict__ A, int P, float* __restrict__ out, int64_t ld, float bound,
+    int* __restrict__ flag, int p0, int64_t n0) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int p0 = blockIdx.y * kProjBM;
-    const int64_t n0 = (int64_t)blockIdx.x * kProjBN;
     f32x4 acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -99,21 +140,21 @@ __global__ __launch_bounds__(kBlock) void project_f32_kernel(
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + q * kBlock;
-            As[e / kProjKC][e % kProjKC] = va[q];
+            sm.As[e / kProjKC][e % kProjKC] = va[q];
         }
 #pragma unroll
         for (int q = 0; q < QX; ++q) {
             const int e = tid + q * kBlock;
-            Xs[e / kProjKC][e % kProjKC] = vx[q];
+            sm.Xs[e / kProjKC][e % kProjKC] = vx[q];
         }
         __syncthreads();
         for (int ks = 0; ks < kc; ks += 4) {
             float a[4], b[2];
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) a[bi] = As[bi * 16 + (lane & 15)][ks + (lane >> 4)];
+            for (int bi = 0; bi < 4; ++bi) a[bi] = sm.As[bi * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
-                b[bj] = Xs[wave * 32 + bj * 16 + (lane & 15)][ks + (lane >> 4)];
+                b[bj] = sm.Xs[wave * 32 + bj * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -121,44 +162,14 @@ __global__ __launch_bounds__(kBlock) void project_f32_kernel(
                     acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
         }
     }
-    bool bad = false;
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int p = p0 + bi * 16 + 4 * (lane >> 4) + r;
-                const int64_t n = n0 + wave * 32 + bj * 16 + (lane & 15);
-                if (p < P && n < N) {
-                    const float v = acc[bi][bj][r];
-                    out[(int64_t)p * ld + n] = v;
-                    bad |= !(fabsf(v) <= bound);
-                }
-            }
-    if (bad) atomicOr(flag, 1);
+    project_store(acc, p0, n0, P, N, out, ld, bound, flag);
 }
 
-__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u)          // inf / nan: keep, quiet nan
-        return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
-constexpr int kProjKCh = 64;   // k-chunk staged in LDS (bf16)
-
-__global__ __launch_bounds__(kBlock) void project_bf16_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad,
-    const unsigned short* __restrict__ A, int P, float* __restrict__ out,
-    int64_t ld, float bound, int* __restrict__ flag) {
-    // row stride 72 halves = 144 bytes keeps 16-byte fragment loads aligned
-    __shared__ __attribute__((aligned(16))) unsigned short As[kProjBM][kProjKCh + 8];
-    __shared__ __attribute__((aligned(16))) unsigned short Xs[kProjBN][kProjKCh + 8];
+__device__ __forceinline__ void project_tile_bf16(
+    ProjSmemBF16& sm, const float* __restrict__ X, int64_t N, int d, int dpad,
+    const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
+    float bound, int* __restrict__ flag, int p0, int64_t n0) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int p0 = blockIdx.y * kProjBM;
-    const int64_t n0 = (int64_t)blockIdx.x * kProjBN;
     f32x4 acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -184,12 +195,12 @@ __global__ __launch_bounds__(kBlock) void project_bf16_kernel(
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + q * kBlock;
-            As[e / kProjKCh][e % kProjKCh] = va[q];
+            sm.As[e / kProjKCh][e % kProjKCh] = va[q];
         }
 #pragma unroll
         for (int q = 0; q < QX; ++q) {
             const int e = tid + q * kBlock;
-            Xs[e / kProjKCh][e % kProjKCh] = f32_to_bf16_rne(vx[q]);
+            sm.Xs[e / kProjKCh][e % kProjKCh] = f32_to_bf16_rne(vx[q]);
         }
         __syncthreads();
         for (int ks = 0; ks < kc; ks += 32) {
@@ -197,10 +208,10 @@ __global__ __launch_bounds__(kBlock) void project_bf16_kernel(
             const int kk = ks + 8 * (lane >> 4);
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
-                a[bi] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&As[bi * 16 + (lane & 15)][kk]));
+                a[bi] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sm.As[bi * 16 + (lane & 15)][kk]));
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj)
-                b[bj] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Xs[wave * 32 + bj * 16 + (lane & 15)][kk]));
+                b[bj] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sm.Xs[wave * 32 + bj * 16 + (lane & 15)][kk]));
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -208,22 +219,24 @@ __global__ __launch_bounds__(kBlock) void project_bf16_kernel(
                     acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
         }
     }
-    bool bad = false;
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int p = p0 + bi * 16 + 4 * (lane >> 4) + r;
-                const int64_t n = n0 + wave * 32 + bj * 16 + (lane & 15);
-                if (p < P && n < N) {
-                    const float v = acc[bi][bj][r];
-                    out[(int64_t)p * ld + n] = v;
-                    bad |= !(fabsf(v) <= bound);
-                }
-            }
-    if (bad) atomicOr(flag, 1);
+    project_store(acc, p0, n0, P, N, out, ld, bound, flag);
+}
+
+__global__ __launch_bounds__(kBlock) void project_f32_kernel(
+    const float* __restrict__ X, int64_t N, int d, int dpad, const float* __restrict__ A,
+    int P, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag) {
+    __shared__ ProjSmemF32 sm;
+    project_tile_f32(sm, X, N, d, dpad, A, P, out, ld, bound, flag, blockIdx.y * kProjBM,
+                     (int64_t)blockIdx.x * kProjBN);
+}
+
+__global__ __launch_bounds__(kBlock) void project_bf16_kernel(
+    const float* __restrict__ X, int64_t N, int d, int dpad,
+    const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
+    float bound, int* __restrict__ flag) {
+    __shared__ ProjSmemBF16 sm;
+    project_tile_bf16(sm, X, N, d, dpad, A, P, out, ld, bound, flag, blockIdx.y * kProjBM,
+                      (int64_t)blockIdx.x * kProjBN);
 }
 
 hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
@@ -246,7 +259,7 @@ hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
 }
 
 // ---------------------------------------------------------------------------
-// spread: one workgroup = one direction x one chunk of sources
+// spread: one tile = one direction x one chunk of sources
 //
 // LDS float atomics are slow on this chip, integer ones are not: every tap
 // w * phi is scaled by 2^k (k chosen per chunk so that |w| 2^k < 2^40),
@@ -255,14 +268,15 @@ hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
 // the order of the atomics, so the spread grids are bitwise reproducible.
 // ---------------------------------------------------------------------------
 
-// k per chunk: |w_i| < 2^(40 - k) for every source i of the chunk.
-__global__ __launch_bounds__(kBlock) void chunk_scale_kernel(
-    const float* __restrict__ w, int64_t N, int64_t chunk_len, int* __restrict__ chunk_exp) {
-    __shared__ float red[kBlock];
-    const int64_t i0 = (int64_t)blockIdx.x * chunk_len;
+// k for one chunk: |w_i| < 2^(40 - k) for every source i of the chunk.
+__device__ __forceinline__ void chunk_scale_tile(float* red, const float* __restrict__ w,
+                                                 int64_t N, int64_t chunk_len, int c,
+                                                 int* __restrict__ chunk_exp) {
+    const int64_t i0 = (int64_t)c * chunk_len;
     const int64_t i1 = min(N, i0 + chunk_len);
     float m = 0.f;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) m = fmaxf(m, fabsf(w[i]));
+    __syncthreads();               // red may still be read by a previous tile
     red[threadIdx.x] = m;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
@@ -272,9 +286,16 @@ __global__ __launch_bounds__(kBlock) void chunk_scale_kernel(
     if (threadIdx.x == 0) {
         const float mx = red[0];
         int e = 0;
-        if (mx > 0.f && mx <= 3.4e38f) (void)frexpf(mx, &e);   // mx < 2^e
-        chunk_exp[blockIdx.x] = (mx > 0.f && mx <= 3.4e38f) ? 40 - e : 0;
+        const bool ok = mx > 0.f && mx <= 3.4e38f;
+        if (ok) (void)frexpf(mx, &e);   // mx < 2^e
+        chunk_exp[c] = ok ? 40 - e : 0;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void chunk_scale_kernel(
+    const float* __restrict__ w, int64_t N, int64_t chunk_len, int* __restrict__ chunk_exp) {
+    __shared__ float red[kBlock];
+    chunk_scale_tile(red, w, N, chunk_len, blockIdx.x, chunk_exp);
 }
 
 __device__ __forceinline__ unsigned long long to_fixed(float v) {
@@ -297,13 +318,12 @@ __device__ __forceinline__ void spread_point(float xt, float ws, const GridGeom&
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void spread_kernel(
-    const float* __restrict__ proj, int64_t ld, const float* __restrict__ w,
-    int64_t N, int P, GridGeom g, int64_t chunk_len, const int* __restrict__ chunk_exp,
-    WindowArgs win, float* __restrict__ partial) {
-    extern __shared__ unsigned long long lds64[];
-    const int p = blockIdx.x;
-    const int c = blockIdx.y;
+__device__ __forceinline__ void spread_tile(
+    unsigned long long* lds64, const float* __restrict__ proj, int64_t ld,
+    const float* __restrict__ w, int64_t N, int P, const GridGeom& g, int64_t chunk_len,
+    const int* __restrict__ chunk_exp, const WindowArgs& win, float* __restrict__ partial,
+    int p, int c) {
+    __syncthreads();               // LDS may still be read by a previous tile
     for (int j = threadIdx.x; j < g.nr; j += kBlock) lds64[j] = 0ull;
     __syncthreads();
     const int k = chunk_exp[c];
@@ -344,6 +364,16 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(
     float* __restrict__ dst = partial + ((int64_t)c * P + p) * g.nr;
     for (int j = threadIdx.x; j < g.nr; j += kBlock)
         dst[j] = (float)((double)(long long)lds64[j] * unscale);
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void spread_kernel(
+    const float* __restrict__ proj, int64_t ld, const float* __restrict__ w,
+    int64_t N, int P, GridGeom g, int64_t chunk_len, const int* __restrict__ chunk_exp,
+    WindowArgs win, float* __restrict__ partial) {
+    extern __shared__ unsigned long long lds64[];
+    spread_tile<W>(lds64, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial,
+                   blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
@@ -420,18 +450,18 @@ __device__ float2* fft_lds(float2* a, float2* b, int n, const float2* __restrict
     return a;
 }
 
-__global__ __launch_bounds__(kBlock) void fftconv_kernel(
-    const float* __restrict__ partial, int nchunk, int P, GridGeom g,
+__device__ __forceinline__ void fftconv_tile(
+    float2* cbuf, const float* __restrict__ partial, int nchunk, int P, const GridGeom& g,
     const float2* __restrict__ tw, const float2* __restrict__ mult,
-    const float2* __restrict__ mult_d, float* __restrict__ grid,
-    float* __restrict__ grid_d) {
-    extern __shared__ float2 cbuf[];
+    const float2* __restrict__ mult_d, float* __restrict__ grid, float* __restrict__ grid_d,
+    int pair) {
     const int n = g.n;
     float2* b0 = cbuf;
     float2* b1 = cbuf + n;
     float2* b2 = cbuf + 2 * n;
-    const int pa = 2 * blockIdx.x, pb = pa + 1;
+    const int pa = 2 * pair, pb = pa + 1;
     const bool has_b = pb < P;
+    __syncthreads();               // LDS may still be read by a previous tile
     for (int j = threadIdx.x; j < n; j += kBlock) {
         float re = 0.f, im = 0.f;
         const int r = j - g.lo;
@@ -462,6 +492,15 @@ __global__ __launch_bounds__(kBlock) void fftconv_kernel(
     }
 }
 
+__global__ __launch_bounds__(kBlock) void fftconv_kernel(
+    const float* __restrict__ partial, int nchunk, int P, GridGeom g,
+    const float2* __restrict__ tw, const float2* __restrict__ mult,
+    const float2* __restrict__ mult_d, float* __restrict__ grid,
+    float* __restrict__ grid_d) {
+    extern __shared__ float2 cbuf[];
+    fftconv_tile(cbuf, partial, nchunk, P, g, tw, mult, mult_d, grid, grid_d, blockIdx.x);
+}
+
 hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
                           const float2* tw, const float2* mult,
                           const float2* mult_d, float* grid, float* grid_d,
@@ -474,7 +513,7 @@ hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
 }
 
 // ---------------------------------------------------------------------------
-// gather: one workgroup = a tile of targets x a group of directions
+// gather: one tile = 1024 targets x a group of directions
 // ---------------------------------------------------------------------------
 
 constexpr int kGatherTPT = 4;   // consecutive targets per thread (one float4)
@@ -493,16 +532,15 @@ __device__ __forceinline__ float interp(float xt, const float* gl, const GridGeo
 }
 
 template <int W, bool WRITE_T>
-__global__ __launch_bounds__(kBlock) void gather_kernel(
-    const float* __restrict__ proj, int64_t ld, int64_t M, int P, GridGeom g,
-    const float* __restrict__ grid, int pg, int pstage, WindowArgs win,
-    double* __restrict__ spart, int64_t ldm, float* __restrict__ tout,
-    int64_t ld_t) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void gather_tile(
+    float* lds, const float* __restrict__ proj, int64_t ld, int64_t M, int P,
+    const GridGeom& g, const float* __restrict__ grid, int pg, int pstage,
+    const WindowArgs& win, double* __restrict__ spart, int64_t ldm, float* __restrict__ tout,
+    int64_t ld_t, int mtile, int group) {
     const int tid = threadIdx.x;
-    const int64_t m = (int64_t)blockIdx.x * (kBlock * kGatherTPT) + kGatherTPT * tid;
+    const int64_t m = (int64_t)mtile * (kBlock * kGatherTPT) + kGatherTPT * tid;
     const bool active = m < M;
-    const int p_begin = blockIdx.y * pg;
+    const int p_begin = group * pg;
     const int p_end = min(P, p_begin + pg);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int ps = p_begin; ps < p_end; ps += pstage) {
@@ -550,12 +588,23 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(
         }
     }
     if (!WRITE_T && active) {
-        double* __restrict__ dst = spart + (int64_t)blockIdx.y * ldm + m;
+        double* __restrict__ dst = spart + (int64_t)group * ldm + m;
         dst[0] = a0;
         if (m + 1 < M) dst[1] = a1;
         if (m + 2 < M) dst[2] = a2;
         if (m + 3 < M) dst[3] = a3;
     }
+}
+
+template <int W, bool WRITE_T>
+__global__ __launch_bounds__(kBlock) void gather_kernel(
+    const float* __restrict__ proj, int64_t ld, int64_t M, int P, GridGeom g,
+    const float* __restrict__ grid, int pg, int pstage, WindowArgs win,
+    double* __restrict__ spart, int64_t ldm, float* __restrict__ tout,
+    int64_t ld_t) {
+    extern __shared__ float lds[];
+    gather_tile<W, WRITE_T>(lds, proj, ld, M, P, g, grid, pg, pstage, win, spart, ldm, tout,
+                            ld_t, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_gather(int W, const float* proj, int64_t ld, int64_t M,
@@ -584,14 +633,19 @@ hipError_t launch_gather(int W, const float* proj, int64_t ld, int64_t M,
 // reduction over direction groups (FP64) and back-projection
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void reduce_kernel(
-    const double* __restrict__ spart, int nb, int64_t ldm, int64_t M,
-    double scale, float* __restrict__ s) {
-    const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void reduce_tile(const double* __restrict__ spart, int nb,
+                                            int64_t ldm, int64_t M, double scale,
+                                            float* __restrict__ s, int64_t m) {
     if (m >= M) return;
     double acc = 0.0;
     for (int b = 0; b < nb; ++b) acc += spart[(int64_t)b * ldm + m];
     s[m] = (float)(acc * scale);
+}
+
+__global__ __launch_bounds__(kBlock) void reduce_kernel(
+    const double* __restrict__ spart, int nb, int64_t ldm, int64_t M,
+    double scale, float* __restrict__ s) {
+    reduce_tile(spart, nb, ldm, M, scale, s, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 hipError_t launch_reduce(const double* spart, int nb, int64_t ldm, int64_t M,
@@ -645,6 +699,126 @@ hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
     dim3 grid((unsigned)((M + kBlock - 1) / kBlock), (unsigned)((d + kBpDim - 1) / kBpDim));
     hipLaunchKernelGGL(backproject_kernel, grid, dim3(kBlock), 0, stream, tprime, ld, M,
                        P, d, A, dpad, coef, v, grad_y);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched form: persistent kernels walking task lists
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void batch_project_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P, int* __restrict__ flag) {
+    __shared__ ProjSmemF32 sm;
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        const bool is_y = tk.a != 0;
+        project_tile_f32(sm, is_y ? pr.y : pr.x, is_y ? pr.M : pr.N, pr.d, pr.dpad, pr.A, P,
+                         is_y ? pr.yproj : pr.xproj, is_y ? pr.ldy : pr.ldx, pr.bound, flag,
+                         tk.c * kProjBM, (int64_t)tk.b * kProjBN);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_scale_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks) {
+    __shared__ float red[kBlock];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        chunk_scale_tile(red, pr.w, pr.N, pr.chunk_len, tk.a, pr.chunk_exp);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void batch_spread_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P, WindowArgs win) {
+    extern __shared__ unsigned long long lds64[];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        spread_tile<W>(lds64, pr.xproj, pr.ldx, pr.w, pr.N, P, pr.g, pr.chunk_len,
+                       pr.chunk_exp, win, pr.partial, tk.a, tk.b);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_fftconv_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P) {
+    extern __shared__ float2 cbuf[];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        fftconv_tile(cbuf, pr.partial, pr.nchunk, P, pr.g, pr.tw, pr.mult, nullptr, pr.grid,
+                     nullptr, tk.a);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void batch_gather_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P, int pstage, WindowArgs win) {
+    extern __shared__ float lds[];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        const float* yp = pr.same_xy ? pr.xproj : pr.yproj;
+        const int64_t ldy = pr.same_xy ? pr.ldx : pr.ldy;
+        gather_tile<W, false>(lds, yp, ldy, pr.M, P, pr.g, pr.grid, pr.pg, pstage, win,
+                              pr.spart, pr.ldm, nullptr, 0, tk.a, tk.b);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_reduce_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P) {
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        reduce_tile(pr.spart, pr.ngroup, pr.ldm, pr.M, 1.0 / P, pr.s,
+                    (int64_t)tk.a * kBlock + threadIdx.x);
+    }
+}
+
+hipError_t launch_batch_phase(int phase, int W, const BatchProblem* probs,
+                              const BatchTask* tasks, int ntasks, int P, int pstage,
+                              const WindowArgs& win, int* flag, int grid_blocks,
+                              size_t lds_bytes, hipStream_t stream) {
+    if (ntasks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(grid_blocks < ntasks ? grid_blocks : ntasks)), block(kBlock);
+    switch (phase) {
+        case kBatchProject:
+            hipLaunchKernelGGL(batch_project_kernel, grid, block, 0, stream, probs, tasks, ntasks, P, flag);
+            break;
+        case kBatchScale:
+            hipLaunchKernelGGL(batch_scale_kernel, grid, block, 0, stream, probs, tasks, ntasks);
+            break;
+        case kBatchSpread:
+            switch (W) {
+                case 4: hipLaunchKernelGGL(batch_spread_kernel<4>, grid, block, lds_bytes, stream, probs, tasks, ntasks, P, win); break;
+                case 6: hipLaunchKernelGGL(batch_spread_kernel<6>, grid, block, lds_bytes, stream, probs, tasks, ntasks, P, win); break;
+                case 8: hipLaunchKernelGGL(batch_spread_kernel<8>, grid, block, lds_bytes, stream, probs, tasks, ntasks, P, win); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case kBatchFftconv:
+            hipLaunchKernelGGL(batch_fftconv_kernel, grid, block, lds_bytes, stream, probs, tasks, ntasks, P);
+            break;
+        case kBatchGather:
+            switch (W) {
+                case 4: hipLaunchKernelGGL(batch_gather_kernel<4>, grid, block, lds_bytes, stream, probs, tasks, ntasks, P, pstage, win); break;
+                case 6: hipLaunchKernelGGL(batch_gather_kernel<6>, grid, block, lds_bytes, stream, probs, tasks, ntasks, P, pstage, win); break;
+                case 8: hipLaunchKernelGGL(batch_gather_kernel<8>, grid, block, lds_bytes, stream, probs, tasks, ntasks, P, pstage, win); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case kBatchReduce:
+            hipLaunchKernelGGL(batch_reduce_kernel, grid, block, 0, stream, probs, tasks, ntasks, P);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

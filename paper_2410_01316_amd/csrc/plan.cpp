@@ -13,11 +13,13 @@
 #include <new>
 #include <vector>
 
+#include "host_common.h"
+
 using namespace fastsum;
+using namespace fastsum::host;
 
-namespace {
-
-constexpr double kPi = 3.14159265358979323846264338327950288;
+namespace fastsum {
+namespace host {
 
 // ---------------------------------------------------------------------------
 // FP64 numerics
@@ -54,7 +56,11 @@ double energy_cd(int d) {
 // energy kernel the triangle-wave extension of -(c_d/tau)|x|).
 void fourier_coefficients(int kernel, int d, double scale, double tau, int n_ft,
                           std::vector<double>& c) {
-    const int K = n_ft / 2;
+    fourier_coefficients_upto(kernel, d, scale, tau, n_ft / 2, c);
+}
+
+void fourier_coefficients_upto(int kernel, int d, double scale, double tau, int K,
+                               std::vector<double>& c) {
     c.assign(K + 1, 0.0);
     if (kernel == FASTSUM_ENERGY) {
         const double cd = energy_cd(d);
@@ -115,23 +121,6 @@ bool solve_dense(std::vector<double>& V, std::vector<double>& b, int n) {
     return true;
 }
 
-// Exponential-of-semicircle window phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
-// |z| <= 1, z = (cell - u) / (W/2).  Tap t of a point with sp = frac(u) - 1/2
-// sits at z_t = (t + 1/2 - W/2 - sp) / (W/2).  The weight of tap t is
-// replaced by its degree-D interpolant in sp at Chebyshev points; everything
-// downstream (phihat, the multipliers) is computed from these polynomials, so
-// the deconvolution matches the window the kernels actually apply.
-struct WindowPoly {
-    int W = 4, D = 4;
-    double beta = 0.0;
-    std::vector<double> coef;   // W x (D+1), monomial coefficients in sp
-    double eval(int t, double sp) const {
-        double acc = 0.0;
-        for (int i = D; i >= 0; --i) acc = acc * sp + coef[t * (D + 1) + i];
-        return acc;
-    }
-};
-
 bool build_window(int W, WindowPoly& win) {
     win.W = W;
     win.D = (W == 4) ? 4 : (W == 6 ? 5 : 7);
@@ -181,12 +170,6 @@ void window_transform(const WindowPoly& win, int n, int kmax, std::vector<double
 // ---------------------------------------------------------------------------
 // parameters
 // ---------------------------------------------------------------------------
-
-struct Resolved {
-    fastsum_params p;
-    int n = 0;          // grid size
-    double tau = 0.0;
-};
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -254,9 +237,65 @@ uint16_t f32_to_bf16_host(float f) {
     return (uint16_t)(u >> 16);
 }
 
+void build_tables(int kernel, int d, double scale, double tau, int n_ft, int n,
+                  const WindowPoly& win, std::vector<float2>& mult,
+                  std::vector<float2>& mult_d, std::vector<float2>& tw) {
+    std::vector<double> c;
+    fourier_coefficients(kernel, d, scale, tau, n_ft, c);
+    std::vector<double> ph;
+    window_transform(win, n, n / 2, ph);
+    const int K = n_ft / 2;
+    mult.assign(n, make_float2(0.f, 0.f));
+    mult_d.assign(n, make_float2(0.f, 0.f));
+    tw.assign(n, make_float2(0.f, 0.f));
+    for (int k = 0; k < n; ++k) {
+        const int ks = (k <= n / 2) ? k : k - n;
+        const int a = std::abs(ks);
+        double m = 0.0;
+        if (a <= K) {
+            const double cp = (a == K) ? 0.5 * c[a] : c[a];
+            const double den = n * ph[a];
+            m = cp / (den * den);
+        }
+        mult[k] = make_float2((float)m, 0.f);
+        mult_d[k] = make_float2(0.f, (float)(2.0 * kPi * ks * m));
+        tw[k] = make_float2((float)std::cos(2.0 * kPi * k / n), (float)-std::sin(2.0 * kPi * k / n));
+    }
+}
+
+int spread_chunks(int64_t N, int P) {
+    // aim for >= 2048 workgroups, chunks of >= 4096 sources, <= 2^20 sources
+    int64_t want = (2048 + P - 1) / P;
+    int64_t maxc = std::max<int64_t>(1, (N + 4095) / 4096);
+    int64_t c = std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxc, 64)));
+    return (int)std::max<int64_t>(c, (N + kMaxChunk - 1) / kMaxChunk);
+}
+
+int64_t spread_chunk_len(int64_t N, int nchunk) {
+    return round_up((N + nchunk - 1) / nchunk, kChunkAlign);
+}
+
+int gather_group(int64_t M, int P, int pstage) {
+    // aim for about 1024 workgroups; group size a multiple of pstage, <= 128
+    const int64_t tiles = (M + kGatherTile - 1) / kGatherTile;
+    int64_t groups = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
+    int64_t pg = (P + groups - 1) / groups;
+    pg = round_up(std::max<int64_t>(pg, 1), pstage);
+    pg = std::min<int64_t>(pg, 128);
+    pg = std::max<int64_t>(pg, pstage);
+    return (int)pg;
+}
+
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-}  // namespace
+fastsum_status status_of(hipError_t e) {
+    if (e == hipSuccess) return FASTSUM_OK;
+    if (e == hipErrorOutOfMemory) return FASTSUM_ENOMEM;
+    return FASTSUM_EDEVICE;
+}
+
+}  // namespace host
+}  // namespace fastsum
 
 // ---------------------------------------------------------------------------
 // plan object
@@ -352,37 +391,7 @@ struct PhaseTimer {
     }
 };
 
-constexpr int64_t kChunkAlign = 4 * kBlock;      // spread chunks start on float4 steps
-constexpr int64_t kMaxChunk = (int64_t)1 << 20;   // keeps the 64-bit fixed-point sums exact
-
-int spread_chunks(int64_t N, int P) {
-    // aim for >= 2048 workgroups, chunks of >= 4096 sources, <= 2^20 sources
-    int64_t want = (2048 + P - 1) / P;
-    int64_t maxc = std::max<int64_t>(1, (N + 4095) / 4096);
-    int64_t c = std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(maxc, 64)));
-    return (int)std::max<int64_t>(c, (N + kMaxChunk - 1) / kMaxChunk);
-}
-
-int64_t spread_chunk_len(int64_t N, int nchunk) {
-    return round_up((N + nchunk - 1) / nchunk, kChunkAlign);
-}
-
-int gather_group(int64_t M, int P, int pstage) {
-    // aim for about 1024 workgroups; group size a multiple of pstage, <= 128
-    const int64_t tiles = (M + kBlock * 4 - 1) / (kBlock * 4);
-    int64_t groups = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
-    int64_t pg = (P + groups - 1) / groups;
-    pg = round_up(std::max<int64_t>(pg, 1), pstage);
-    pg = std::min<int64_t>(pg, 128);
-    pg = std::max<int64_t>(pg, pstage);
-    return (int)pg;
-}
-
-fastsum_status check(hipError_t e) {
-    if (e == hipSuccess) return FASTSUM_OK;
-    if (e == hipErrorOutOfMemory) return FASTSUM_ENOMEM;
-    return FASTSUM_EDEVICE;
-}
+fastsum_status check(hipError_t e) { return status_of(e); }
 
 #define FS_TRY(expr)                                  \
     do {                                              \
@@ -526,25 +535,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     if (!ok) { free_plan(pl); return FASTSUM_ENOMEM; }
 
     // tables
-    std::vector<double> c;
-    fourier_coefficients(r.p.kernel, pl->d, r.p.scale, r.tau, r.p.n_ft, c);
-    std::vector<double> ph;
-    window_transform(pl->win, n, n / 2, ph);
-    const int K = r.p.n_ft / 2;
-    std::vector<float2> mult(n), mult_d(n), tw(n);
-    for (int k = 0; k < n; ++k) {
-        const int ks = (k <= n / 2) ? k : k - n;
-        const int a = std::abs(ks);
-        double m = 0.0;
-        if (a <= K) {
-            const double cp = (a == K) ? 0.5 * c[a] : c[a];
-            const double den = n * ph[a];
-            m = cp / (den * den);
-        }
-        mult[k] = make_float2((float)m, 0.f);
-        mult_d[k] = make_float2(0.f, (float)(2.0 * kPi * ks * m));
-        tw[k] = make_float2((float)std::cos(2.0 * kPi * k / n), (float)-std::sin(2.0 * kPi * k / n));
-    }
+    std::vector<float2> mult, mult_d, tw;
+    build_tables(r.p.kernel, pl->d, r.p.scale, r.tau, r.p.n_ft, n, pl->win, mult, mult_d, tw);
     std::vector<float> A((size_t)P * pl->dpad, 0.f);
     std::vector<uint16_t> A16((size_t)P * pl->dpad, 0);
     for (int p = 0; p < P; ++p)

@@ -90,3 +90,33 @@ def test_null_arguments_rejected_without_device():
     assert lib.fastsum_check(None) == L.EINVAL
     assert lib.fastsum_get_info(None, None) == L.EINVAL
     lib.fastsum_destroy(None)
+
+
+def test_choose_nft_rule():
+    # wide kernel relative to the data: the smallest candidate suffices;
+    # Laplace keeps a k^-2 tail: the largest candidate is needed at tol 1e-4
+    assert F.choose_nft("gauss", 3, 3.0, scale=1.0) == 256
+    assert F.choose_nft("laplace", 10, 3.0, scale=1.0) == 1024
+    # monotone in the tolerance
+    v = [F.choose_nft("gauss", 10, 10.0, scale=0.3, tol=t) for t in (1e-2, 1e-6, 1e-12)]
+    assert v == sorted(v)
+    lib = L.load()
+    bad = L.Params(3, 1, 128, 0, 0, 0, 0, 0, 1.0, 0.0, 0.0, -1.0)
+    out = ctypes.c_int32()
+    arr = (ctypes.c_int32 * 1)(256)
+    assert lib.fastsum_choose_nft(ctypes.byref(bad), arr, 1, 1e-4, ctypes.byref(out)) == L.EINVAL
+
+
+def test_batch_create_rejects_bad_arguments_without_device():
+    lib = L.load()
+    common = L.Params(0, 8, 0, 0, 0, 0, 1, 0, 1.0, 0.0, 0.0, 1.0)   # BF16: unsupported
+    out = ctypes.c_void_p()
+    desc = (L.ProblemDesc * 1)()
+    assert lib.fastsum_batch_create(ctypes.byref(common), desc, 1, None, None,
+                                    ctypes.byref(out)) == L.EUNSUPPORTED
+    common.proj = 0
+    assert lib.fastsum_batch_create(ctypes.byref(common), None, 1, None, None,
+                                    ctypes.byref(out)) == L.EINVAL
+    assert lib.fastsum_batch_exec(None, None, 0, None) == L.EINVAL
+    assert lib.fastsum_batch_check(None) == L.EINVAL
+    lib.fastsum_batch_destroy(None)
