@@ -40,7 +40,31 @@ def orthogonal_directions(d, P, rng):
     return np.concatenate(blocks, axis=1)[:, :P]
 
 
-def distance_qmc_directions(d, P, rng, iters=400, lr=None):
+def _distance_qmc_torch(xi0, iters, lr, device):
+    """The same projected-Adam iteration as below, in float64 torch on
+    `device` (used for large P, where the O(P^2 d) energy gradient dominates)."""
+    import torch
+    xi = torch.tensor(xi0, dtype=torch.float64, device=device)
+    m = torch.zeros_like(xi)
+    v = torch.zeros_like(xi)
+    b1, b2, eps = 0.9, 0.999, 1e-12
+    eye = torch.eye(xi.shape[0], dtype=torch.bool, device=device)
+    for it in range(1, iters + 1):
+        g = (xi @ xi.T).clamp_(-1.0, 1.0)
+        ia = 1.0 / torch.sqrt(torch.clamp(2.0 - 2.0 * g, min=1e-24))
+        ia.masked_fill_(eye, 0.0)
+        ib = 1.0 / torch.sqrt(torch.clamp(2.0 + 2.0 * g, min=1e-24))
+        grad = xi * (ia.sum(1) + ib.sum(1))[:, None] + (ib - ia) @ xi
+        grad -= (grad * xi).sum(1, keepdim=True) * xi
+        m = b1 * m + (1 - b1) * grad
+        v = b2 * v + (1 - b2) * grad * grad
+        step = lr * (1.0 - 0.9 * it / iters)
+        xi = xi + step * (m / (1 - b1 ** it)) / (torch.sqrt(v / (1 - b2 ** it)) + eps)
+        xi = xi / torch.linalg.norm(xi, dim=1, keepdim=True)
+    return xi.cpu().numpy()
+
+
+def distance_qmc_directions(d, P, rng, iters=400, lr=None, device=None):
     """Distance QMC design: P unit vectors that (locally) minimise the
     symmetrised distance energy E_sym(xi) = -2 sum_{p,q} (|xi_p - xi_q| +
     |xi_p + xi_q|)  (eq. distance-sym, App. H), by projected Adam steps
@@ -51,6 +75,8 @@ def distance_qmc_directions(d, P, rng, iters=400, lr=None):
     xi = iid_directions(d, P, rng).T.copy()          # (P, d) rows
     if lr is None:                       # a fraction of the typical spacing
         lr = 0.05 * P ** (-1.0 / max(d - 1, 1))
+    if device is not None:
+        return _distance_qmc_torch(xi, iters, lr, device).T.copy()
     m = np.zeros_like(xi)
     v = np.zeros_like(xi)
     b1, b2, eps = 0.9, 0.999, 1e-12
@@ -72,9 +98,10 @@ def distance_qmc_directions(d, P, rng, iters=400, lr=None):
     return xi.T.copy()
 
 
-def directions(kind, d, P, seed, rotate=True):
+def directions(kind, d, P, seed, rotate=True, device=None):
     """Direction set by name ('iid', 'sobol', 'orth', 'distance'); QMC sets
-    get a seeded Haar rotation so the estimator is unbiased (App. E)."""
+    get a seeded Haar rotation so the estimator is unbiased (App. E).
+    device: optional torch device for the distance-QMC construction."""
     rng = np.random.default_rng(seed)
     if kind == "iid":
         return iid_directions(d, P, rng)
@@ -83,7 +110,7 @@ def directions(kind, d, P, seed, rotate=True):
     elif kind == "orth":
         xi = orthogonal_directions(d, P, rng)
     elif kind == "distance":
-        xi = distance_qmc_directions(d, P, rng)
+        xi = distance_qmc_directions(d, P, rng, device=device)
     else:
         raise ValueError(f"unknown direction set {kind!r}")
     if rotate:
