@@ -86,10 +86,10 @@ def kernel_source_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(phase):
+def measured_traffic(phase, P):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different kernel source."""
-    path = os.path.join(PROFILES, f"{phase}_scale_d50_traffic.txt")
+    path = os.path.join(PROFILES, f"{phase}_scale_d50_P{P}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--dirs-cache", default="",
+                    help="directory for generated direction sets (reused when present)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -258,7 +260,14 @@ def main():
         return float(np.linalg.norm(sg - s1) / np.linalg.norm(s1))
 
     def plan_for(P):
-        xi = directions("distance", d, P, 101, device="cuda")
+        path = os.path.join(args.dirs_cache, f"distance_d{d}_P{P}_s101.npy") if args.dirs_cache else ""
+        if path and os.path.exists(path):
+            xi = np.load(path)
+        else:
+            xi = directions("distance", d, P, 101, device="cuda")
+            if path:
+                os.makedirs(args.dirs_cache, exist_ok=True)
+                np.save(path, xi)
         return make_plan(dict(cfg, xi=xi, P=P))
 
     ladder = []
@@ -324,7 +333,7 @@ def main():
     roof["avg_launch_us"] = avg_s * 1e6
     roof["algorithmic_bytes_per_launch"] = byts
     roof["algorithmic_flops_per_launch"] = flops
-    roof["traffic"] = measured_traffic(dom)
+    roof["traffic"] = measured_traffic(dom, P)
     phase_report = {}
     for p, (t, c) in phases.items():
         if c:

@@ -127,7 +127,7 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
         d.partial = reinterpret_cast<float*>(b->arena + pp.off_partial);
         d.grid = reinterpret_cast<float*>(b->arena + pp.off_grid);
         d.spart = reinterpret_cast<double*>(b->arena + pp.off_spart);
-        d.chunk_exp = reinterpret_cast<int*>(b->arena + pp.off_exp);
+        d.slice_max = reinterpret_cast<float*>(b->arena + pp.off_exp);
         d.mult = reinterpret_cast<const float2*>(b->arena + pp.off_mult);
         d.tw = reinterpret_cast<const float2*>(b->arena + pp.off_tw);
         d.ldx = pp.ldx;
@@ -152,7 +152,8 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
         if (!d.same_xy)
             for (int t = 0; t < mt; ++t)
                 for (int c = 0; c < ptiles; ++c) ph[kBatchProject].push_back({i, 1, t, c});
-        for (int c = 0; c < d.nchunk; ++c) ph[kBatchScale].push_back({i, c, 0, 0});
+        for (int c = 0; c < (int)((q.N + kSliceLen - 1) / kSliceLen); ++c)
+            ph[kBatchScale].push_back({i, c, 0, 0});
         for (int c = 0; c < d.nchunk; ++c)
             for (int p = 0; p < P; ++p) ph[kBatchSpread].push_back({i, p, c, 0});
         for (int a = 0; a < (P + 1) / 2; ++a) ph[kBatchFftconv].push_back({i, a, 0, 0});
@@ -300,19 +301,19 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
         pp.off_partial = off; off = align256(off + sizeof(float) * (size_t)nc * P * nr);
         pp.off_grid = off; off = align256(off + sizeof(float) * (size_t)P * nr);
         pp.off_spart = off; off = align256(off + sizeof(double) * (size_t)ng * pp.ldm);
-        pp.off_exp = off; off = align256(off + sizeof(int) * (size_t)nc);
+        pp.off_exp = off; off = align256(off + sizeof(float) * (size_t)((pp.n_max + kSliceLen - 1) / kSliceLen));
         pp.off_mult = off; off = align256(off + sizeof(float2) * (size_t)n);
         pp.off_tw = off; off = align256(off + sizeof(float2) * (size_t)n);
         const size_t ptiles = (P + kProjTileP - 1) / kProjTileP;
         tasks += ptiles * ((pp.n_max + kProjTileN - 1) / kProjTileN + (pp.m_max + kProjTileN - 1) / kProjTileN);
-        tasks += (size_t)nc * (P + 1);
+        tasks += (size_t)nc * P + (pp.n_max + kSliceLen - 1) / kSliceLen;
         tasks += (P + 1) / 2;
         tasks += (size_t)ng * ((pp.m_max + kGatherTile - 1) / kGatherTile);
         tasks += (pp.m_max + kBlock - 1) / kBlock;
     }
     b->arena_bytes = off;
     b->task_cap = tasks;
-    b->lds_spread = (size_t)max_nr * sizeof(unsigned long long);
+    b->lds_spread = (size_t)max_nr * (sizeof(double) + sizeof(int));
     b->lds_fft = (size_t)3 * max_n * sizeof(float2);
     b->lds_gather = (size_t)b->pstage * max_nr * sizeof(float);
 

@@ -45,11 +45,12 @@ hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
 
 // partial[(c*P + p)*nr + j - lo] = sum over sources i of chunk c of
 //   w[i] * window(cell j - u(proj[p*ld + i]))
-// chunk_len must be a multiple of 4 * kBlock and below 2^21; chunk_exp is
-// scratch for nchunk ints.
+// chunk_len must be a multiple of kSliceLen; slice_max is scratch for
+// ceil(N / kSliceLen) floats.
+constexpr int kSliceLen = 4096;
 hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
                          int64_t N, int P, GridGeom g, int nchunk,
-                         int64_t chunk_len, int* chunk_exp, const WindowArgs& win,
+                         int64_t chunk_len, float* slice_max, const WindowArgs& win,
                          float* partial, hipStream_t stream);
 
 // Per pair of directions: sum the chunk partials, complex FFT of size n,
@@ -95,7 +96,7 @@ struct BatchProblem {
     float* partial;        // nchunk x P x nr
     float* grid;           // P x nr
     double* spart;         // ngroup x ldm
-    int* chunk_exp;        // nchunk
+    float* slice_max;      // ceil(N / kSliceLen)
     const float2* mult;    // n coefficient multipliers
     const float2* tw;      // n twiddles
     int64_t ldx, ldy, ldm;
@@ -117,7 +118,7 @@ struct BatchTask {
 
 enum BatchPhase {
     kBatchProject = 0,   // a = 0 (x) / 1 (y), b = point tile, c = direction tile
-    kBatchScale = 1,     // a = chunk
+    kBatchScale = 1,     // a = slice of kSliceLen sources
     kBatchSpread = 2,    // a = direction, b = chunk
     kBatchFftconv = 3,   // a = direction pair
     kBatchGather = 4,    // a = target tile, b = direction group

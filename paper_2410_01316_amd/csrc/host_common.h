@@ -12,7 +12,7 @@ namespace fastsum {
 namespace host {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr int64_t kChunkAlign = 4 * kBlock;      // spread chunks start on float4 steps
+constexpr int64_t kChunkAlign = kSliceLen;       // spread chunks start on fixed-point slices
 constexpr int64_t kMaxChunk = (int64_t)1 << 20;   // keeps the 64-bit fixed-point sums exact
 
 // Exponential-of-semicircle window phi(z) = exp(beta (sqrt(1 - z^2) - 1)),

@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace fastsum {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -88,26 +90,39 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
     return (unsigned short)(u >> 16);
 }
 
+// The MFMAs compute C^T: acc[bi][bj] holds rows n = wave*32 + bj*16 +
+// 4*(lane/16) + r (r = 0..3) of direction column p = bi*16 + lane%16, i.e.
+// four consecutive points of one output row: one 16-byte store each.
 __device__ __forceinline__ void project_store(const f32x4 (&acc)[4][2], int p0, int64_t n0,
                                               int P, int64_t N, float* __restrict__ out,
                                               int64_t ld, float bound, int* __restrict__ flag) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool bad = false;
+    float mx = 0.f;
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < 4; ++bi) {
+        const int p = p0 + bi * 16 + (lane & 15);
+        if (p >= P) continue;
+        float* __restrict__ row = out + (int64_t)p * ld;
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj) {
+            const int64_t n = n0 + wave * 32 + bj * 16 + 4 * (lane >> 4);
+            const f32x4 v = acc[bi][bj];
+            if (n + 3 < N) {
+                *reinterpret_cast<float4*>(row + n) = make_float4(v[0], v[1], v[2], v[3]);
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int p = p0 + bi * 16 + 4 * (lane >> 4) + r;
-                const int64_t n = n0 + wave * 32 + bj * 16 + (lane & 15);
-                if (p < P && n < N) {
-                    const float v = acc[bi][bj][r];
-                    out[(int64_t)p * ld + n] = v;
-                    bad |= !(fabsf(v) <= bound);
-                }
+                for (int r = 0; r < 4; ++r)
+                    if (n + r < N) {
+                        row[n + r] = v[r];
+                        mx = fmaxf(mx, fabsf(v[r]));
+                    }
             }
-    if (bad) atomicOr(flag, 1);
+            // NaN never compares: catch it separately
+            if (v[0] != v[0] || v[1] != v[1] || v[2] != v[2] || v[3] != v[3]) mx = INFINITY;
+        }
+    }
+    if (!(mx <= bound)) atomicOr(flag, 1);
 }
 
 __device__ __forceinline__ void project_tile_f32(
@@ -159,7 +174,7 @@ __device__ __forceinline__ void project_tile_f32(
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
         }
     }
     project_store(acc, p0, n0, P, N, out, ld, bound, flag);
@@ -216,10 +231,87 @@ __device__ __forceinline__ void project_tile_bf16(
             for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
         }
     }
     project_store(acc, p0, n0, P, N, out, ld, bound, flag);
+}
+
+// d <= 64: the block keeps its 128-point X tile in LDS for its whole life
+// and walks a range of 64-direction tiles, so X is read from memory once per
+// direction range instead of once per direction tile.  The next A tile is
+// loaded into registers while the current one feeds the MFMAs.
+constexpr int kXresMaxD = 64;
+constexpr int kXresLd = kXresMaxD + 1;
+constexpr int kXresQA = kProjBM * kXresMaxD / kBlock;   // A floats per thread and tile
+
+struct ProjSmemXres {
+    float Xs[kProjBN][kXresLd];
+    float As[kProjBM][kXresLd];
+};
+
+__device__ __forceinline__ void xres_load_a(float (&va)[kXresQA], const float* __restrict__ A,
+                                            int P, int d, int dpad, int p0) {
+#pragma unroll
+    for (int q = 0; q < kXresQA; ++q) {
+        const int e = threadIdx.x + q * kBlock, r = e / kXresMaxD, k = e % kXresMaxD;
+        va[q] = (k < d && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k] : 0.f;
+    }
+}
+
+__device__ __forceinline__ void project_tile_f32_xres(
+    ProjSmemXres& sm, const float* __restrict__ X, int64_t N, int d, int dpad,
+    const float* __restrict__ A, int P, float* __restrict__ out, int64_t ld, float bound,
+    int* __restrict__ flag, int p_begin, int p_end, int64_t n0) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kend = (d + 3) & ~3;                  // MFMA k-steps of 4, zero padded
+    float va[kXresQA];
+    xres_load_a(va, A, P, d, dpad, p_begin);
+    __syncthreads();                                // LDS may still be read by a previous tile
+    // X tile: rows n0..n0+127 are contiguous in memory (row length d)
+    for (int e = tid; e < kProjBN * kXresLd; e += kBlock) {
+        const int r = e / kXresLd, k = e % kXresLd;
+        sm.Xs[r][k] = (k < d && n0 + r < N) ? X[(n0 + r) * d + k] : 0.f;
+    }
+    for (int p0 = p_begin; p0 < p_end; p0 += kProjBM) {
+        __syncthreads();                            // previous tile's MFMAs are done with As
+#pragma unroll
+        for (int q = 0; q < kXresQA; ++q) {
+            const int e = tid + q * kBlock;
+            sm.As[e / kXresMaxD][e % kXresMaxD] = va[q];
+        }
+        __syncthreads();
+        if (p0 + kProjBM < p_end) xres_load_a(va, A, P, d, dpad, p0 + kProjBM);   // prefetch
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < kend; ks += 4) {
+            float a[4], b[2];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) a[bi] = sm.As[bi * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                b[bj] = sm.Xs[wave * 32 + bj * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
+        }
+        project_store(acc, p0, n0, P, N, out, ld, bound, flag);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void project_f32_xres_kernel(
+    const float* __restrict__ X, int64_t N, int d, int dpad, const float* __restrict__ A,
+    int P, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag,
+    int prange) {
+    __shared__ ProjSmemXres sm;
+    const int p_begin = blockIdx.y * prange;
+    project_tile_f32_xres(sm, X, N, d, dpad, A, P, out, ld, bound, flag, p_begin,
+                          min(P, p_begin + prange), (int64_t)blockIdx.x * kProjBN);
 }
 
 __global__ __launch_bounds__(kBlock) void project_f32_kernel(
@@ -239,9 +331,23 @@ __global__ __launch_bounds__(kBlock) void project_bf16_kernel(
                       (int64_t)blockIdx.x * kProjBN);
 }
 
+int project_xres_range(int64_t N, int P) {
+    const int64_t ntiles = (N + kProjBN - 1) / kProjBN;
+    const int64_t ranges = std::max<int64_t>(1, (2048 + ntiles - 1) / ntiles);
+    const int64_t pr = (P + ranges - 1) / ranges;
+    return (int)(((pr + kProjBM - 1) / kProjBM) * kProjBM);
+}
+
 hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
                               const float* A, int P, float* out, int64_t ld,
                               float bound, int* flag, hipStream_t stream) {
+    if (d <= kXresMaxD) {
+        const int prange = project_xres_range(N, P);
+        dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + prange - 1) / prange));
+        hipLaunchKernelGGL(project_f32_xres_kernel, grid, dim3(kBlock), 0, stream, X, N, d, dpad,
+                           A, P, out, ld, bound, flag, prange);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + kProjBM - 1) / kProjBM));
     hipLaunchKernelGGL(project_f32_kernel, grid, dim3(kBlock), 0, stream, X, N, d,
                        dpad, A, P, out, ld, bound, flag);
@@ -261,133 +367,137 @@ hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
 // ---------------------------------------------------------------------------
 // spread: one tile = one direction x one chunk of sources
 //
-// LDS float atomics are slow on this chip, integer ones are not: every tap
-// w * phi is scaled by 2^k (k chosen per chunk so that |w| 2^k < 2^40),
-// rounded to a 64-bit integer and added with an integer LDS atomic.  The sum
-// is exact (no overflow for chunks below 2^21 sources) and independent of
-// the order of the atomics, so the spread grids are bitwise reproducible.
+// LDS float atomics are slow on this chip, 32-bit integer ones are fast.
+// Sources are taken in slices of kSlice = 4096: within a slice every tap
+// w * phi is scaled by 2^k (|w| 2^k < 2^18 for the slice's largest |w|),
+// rounded to an integer and added with an integer LDS atomic.  A cell of a
+// slice then holds at most 4096 terms below 2^18 * 1.01 in magnitude, so its
+// sum is exact in 32 bits.  After each slice the cells are moved into an
+// FP64 LDS accumulator (fixed order).  Grids are bitwise reproducible.
 // ---------------------------------------------------------------------------
 
-// k for one chunk: |w_i| < 2^(40 - k) for every source i of the chunk.
-__device__ __forceinline__ void chunk_scale_tile(float* red, const float* __restrict__ w,
-                                                 int64_t N, int64_t chunk_len, int c,
-                                                 int* __restrict__ chunk_exp) {
-    const int64_t i0 = (int64_t)c * chunk_len;
-    const int64_t i1 = min(N, i0 + chunk_len);
+constexpr int kSlice = 4096;                       // sources per fixed-point slice
+constexpr int kSliceSteps = kSlice / (4 * kBlock); // float4 steps per thread and slice
+
+// slice_max[s] = max |w_i| over sources i of slice s
+__device__ __forceinline__ void slice_max_tile(float* red, const float* __restrict__ w,
+                                               int64_t N, int s, float* __restrict__ slice_max) {
+    const int64_t i0 = (int64_t)s * kSlice;
+    float v[kSlice / kBlock];
+#pragma unroll
+    for (int q = 0; q < kSlice / kBlock; ++q) {
+        const int64_t i = i0 + threadIdx.x + (int64_t)q * kBlock;
+        v[q] = (i < N) ? fabsf(w[i]) : 0.f;
+    }
     float m = 0.f;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) m = fmaxf(m, fabsf(w[i]));
+#pragma unroll
+    for (int q = 0; q < kSlice / kBlock; ++q) m = fmaxf(m, v[q]);
     __syncthreads();               // red may still be read by a previous tile
     red[threadIdx.x] = m;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const float mx = red[0];
-        int e = 0;
-        const bool ok = mx > 0.f && mx <= 3.4e38f;
-        if (ok) (void)frexpf(mx, &e);   // mx < 2^e
-        chunk_exp[c] = ok ? 40 - e : 0;
-    }
+    if (threadIdx.x == 0) slice_max[s] = red[0];
 }
 
-__global__ __launch_bounds__(kBlock) void chunk_scale_kernel(
-    const float* __restrict__ w, int64_t N, int64_t chunk_len, int* __restrict__ chunk_exp) {
+__global__ __launch_bounds__(kBlock) void slice_max_kernel(
+    const float* __restrict__ w, int64_t N, float* __restrict__ slice_max) {
     __shared__ float red[kBlock];
-    chunk_scale_tile(red, w, N, chunk_len, blockIdx.x, chunk_exp);
+    slice_max_tile(red, w, N, blockIdx.x, slice_max);
 }
 
-__device__ __forceinline__ unsigned long long to_fixed(float v) {
-    // round(v) as a two's-complement 64-bit integer, valid for |v| < 2^51
-    const double kMagic = 6755399441055744.0;   // 1.5 * 2^52
-    return (unsigned long long)(__double_as_longlong((double)v + kMagic) -
-                                __double_as_longlong(kMagic));
+// exponent k with mx * 2^k < 2^18 (0 for an empty, zero or non-finite slice)
+__device__ __forceinline__ int slice_exponent(float mx) {
+    int e = 0;
+    const bool ok = mx > 0.f && mx <= 3.4e38f;
+    if (ok) (void)frexpf(mx, &e);   // mx < 2^e
+    return ok ? 18 - e : 0;
 }
 
 template <int W>
 __device__ __forceinline__ void spread_point(float xt, float ws, const GridGeom& g,
-                                             const WindowArgs& win,
-                                             unsigned long long* lds64) {
+                                             const WindowArgs& win, int* lds32) {
     float sp;
     const int base = grid_position(xt, g, W / 2 - 1, sp);
     float wt[W];
     window_weights<W>(sp, win, wt);
 #pragma unroll
-    for (int t = 0; t < W; ++t) atomicAdd(&lds64[base + t], to_fixed(ws * wt[t]));
+    for (int t = 0; t < W; ++t) atomicAdd(&lds32[base + t], __float2int_rn(ws * wt[t]));
 }
 
 template <int W>
 __device__ __forceinline__ void spread_tile(
-    unsigned long long* lds64, const float* __restrict__ proj, int64_t ld,
+    void* lds_raw, const float* __restrict__ proj, int64_t ld,
     const float* __restrict__ w, int64_t N, int P, const GridGeom& g, int64_t chunk_len,
-    const int* __restrict__ chunk_exp, const WindowArgs& win, float* __restrict__ partial,
+    const float* __restrict__ slice_max, const WindowArgs& win, float* __restrict__ partial,
     int p, int c) {
+    double* acc = reinterpret_cast<double*>(lds_raw);          // nr doubles
+    int* lds32 = reinterpret_cast<int*>(acc + g.nr);          // nr ints
     __syncthreads();               // LDS may still be read by a previous tile
-    for (int j = threadIdx.x; j < g.nr; j += kBlock) lds64[j] = 0ull;
+    for (int j = threadIdx.x; j < g.nr; j += kBlock) {
+        acc[j] = 0.0;
+        lds32[j] = 0;
+    }
     __syncthreads();
-    const int k = chunk_exp[c];
-    const float scale = ldexpf(1.f, k);
-    const int64_t i0 = (int64_t)c * chunk_len;          // multiple of 4
+    const int64_t i0 = (int64_t)c * chunk_len;          // multiple of kSlice
     const int64_t i1 = min(N, i0 + chunk_len);
     const float* __restrict__ row = proj + (int64_t)p * ld;
-    // four consecutive sources per thread and step; the projection row is
-    // padded to a multiple of 64 floats, weights past the chunk count as 0
-    int64_t i = i0 + 4 * threadIdx.x;
-    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f), wv = xv;
-    if (i < i1) {
-        xv = *reinterpret_cast<const float4*>(row + i);
-        wv.x = w[i];
-        wv.y = (i + 1 < i1) ? w[i + 1] : 0.f;
-        wv.z = (i + 2 < i1) ? w[i + 2] : 0.f;
-        wv.w = (i + 3 < i1) ? w[i + 3] : 0.f;
-    }
-    for (; i < i1; i += 4 * kBlock) {
-        const int64_t inext = i + 4 * kBlock;
-        float4 xn = xv, wn = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (inext < i1) {
-            xn = *reinterpret_cast<const float4*>(row + inext);
-            wn.x = w[inext];
-            wn.y = (inext + 1 < i1) ? w[inext + 1] : 0.f;
-            wn.z = (inext + 2 < i1) ? w[inext + 2] : 0.f;
-            wn.w = (inext + 3 < i1) ? w[inext + 3] : 0.f;
+    for (int64_t s0 = i0; s0 < i1; s0 += kSlice) {
+        const int k = slice_exponent(slice_max[s0 / kSlice]);
+        const float scale = ldexpf(1.f, k);
+        // issue all loads of the slice first; rows are padded to 64 floats
+        float4 xv[kSliceSteps];
+        float wv[kSliceSteps][4];
+#pragma unroll
+        for (int q = 0; q < kSliceSteps; ++q) {
+            const int64_t i = s0 + 4 * threadIdx.x + (int64_t)q * 4 * kBlock;
+            xv[q] = (i < i1) ? *reinterpret_cast<const float4*>(row + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wv[q][r] = (i + r < i1) ? w[i + r] : 0.f;
         }
-        spread_point<W>(xv.x, wv.x * scale, g, win, lds64);
-        spread_point<W>(xv.y, wv.y * scale, g, win, lds64);
-        spread_point<W>(xv.z, wv.z * scale, g, win, lds64);
-        spread_point<W>(xv.w, wv.w * scale, g, win, lds64);
-        xv = xn;
-        wv = wn;
+#pragma unroll
+        for (int q = 0; q < kSliceSteps; ++q) {
+            spread_point<W>(xv[q].x, wv[q][0] * scale, g, win, lds32);
+            spread_point<W>(xv[q].y, wv[q][1] * scale, g, win, lds32);
+            spread_point<W>(xv[q].z, wv[q][2] * scale, g, win, lds32);
+            spread_point<W>(xv[q].w, wv[q][3] * scale, g, win, lds32);
+        }
+        __syncthreads();
+        const double unscale = ldexp(1.0, -k);
+        for (int j = threadIdx.x; j < g.nr; j += kBlock) {
+            acc[j] += (double)lds32[j] * unscale;
+            lds32[j] = 0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const double unscale = ldexp(1.0, -k);
     float* __restrict__ dst = partial + ((int64_t)c * P + p) * g.nr;
-    for (int j = threadIdx.x; j < g.nr; j += kBlock)
-        dst[j] = (float)((double)(long long)lds64[j] * unscale);
+    for (int j = threadIdx.x; j < g.nr; j += kBlock) dst[j] = (float)acc[j];
 }
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void spread_kernel(
     const float* __restrict__ proj, int64_t ld, const float* __restrict__ w,
-    int64_t N, int P, GridGeom g, int64_t chunk_len, const int* __restrict__ chunk_exp,
+    int64_t N, int P, GridGeom g, int64_t chunk_len, const float* __restrict__ slice_max,
     WindowArgs win, float* __restrict__ partial) {
-    extern __shared__ unsigned long long lds64[];
-    spread_tile<W>(lds64, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial,
+    extern __shared__ double lds_spread[];
+    spread_tile<W>(lds_spread, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial,
                    blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
                          int64_t N, int P, GridGeom g, int nchunk,
-                         int64_t chunk_len, int* chunk_exp, const WindowArgs& win,
+                         int64_t chunk_len, float* slice_max, const WindowArgs& win,
                          float* partial, hipStream_t stream) {
-    hipLaunchKernelGGL(chunk_scale_kernel, dim3((unsigned)nchunk), dim3(kBlock), 0, stream, w, N,
-                       chunk_len, chunk_exp);
+    hipLaunchKernelGGL(slice_max_kernel, dim3((unsigned)((N + kSlice - 1) / kSlice)), dim3(kBlock),
+                       0, stream, w, N, slice_max);
     dim3 grid((unsigned)P, (unsigned)nchunk);
-    const size_t lds = (size_t)g.nr * sizeof(unsigned long long);
+    const size_t lds = (size_t)g.nr * (sizeof(double) + sizeof(int));
     switch (W) {
-        case 4: hipLaunchKernelGGL(spread_kernel<4>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial); break;
-        case 6: hipLaunchKernelGGL(spread_kernel<6>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial); break;
-        case 8: hipLaunchKernelGGL(spread_kernel<8>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, chunk_exp, win, partial); break;
+        case 4: hipLaunchKernelGGL(spread_kernel<4>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial); break;
+        case 6: hipLaunchKernelGGL(spread_kernel<6>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial); break;
+        case 8: hipLaunchKernelGGL(spread_kernel<8>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -726,7 +836,7 @@ __global__ __launch_bounds__(kBlock) void batch_scale_kernel(
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const BatchTask tk = tasks[t];
         const BatchProblem& pr = probs[tk.prob];
-        chunk_scale_tile(red, pr.w, pr.N, pr.chunk_len, tk.a, pr.chunk_exp);
+        slice_max_tile(red, pr.w, pr.N, tk.a, pr.slice_max);
     }
 }
 
@@ -734,12 +844,12 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void batch_spread_kernel(
     const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
     int P, WindowArgs win) {
-    extern __shared__ unsigned long long lds64[];
+    extern __shared__ double lds_bspread[];
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const BatchTask tk = tasks[t];
         const BatchProblem& pr = probs[tk.prob];
-        spread_tile<W>(lds64, pr.xproj, pr.ldx, pr.w, pr.N, P, pr.g, pr.chunk_len,
-                       pr.chunk_exp, win, pr.partial, tk.a, tk.b);
+        spread_tile<W>(lds_bspread, pr.xproj, pr.ldx, pr.w, pr.N, P, pr.g, pr.chunk_len,
+                       pr.slice_max, win, pr.partial, tk.a, tk.b);
     }
 }
 

@@ -326,7 +326,7 @@ struct fastsum_plan_s {
     float2* mult_d = nullptr;
     float2* tw = nullptr;
     int* flag = nullptr;
-    int* chunk_exp = nullptr;      // per-chunk fixed-point exponents
+    float* slice_max = nullptr;    // per-slice max |w| (fixed-point scaling)
     // last exec
     bool have_exec = false, last_same = false;
     const float* last_x = nullptr;
@@ -350,7 +350,7 @@ void free_plan(fastsum_plan_s* p) {
     for (auto e : p->pool) (void)hipEventDestroy(e);
     void* bufs[] = {p->A, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
-                    p->chunk_exp};
+                    p->slice_max};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -411,7 +411,7 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
         FS_TRY(launch_spread(pl->W, src_proj, ld_src, wts, Nsrc, P, pl->geom, nchunk, chunk_len,
-                             pl->chunk_exp, pl->win_args, pl->partial, st));
+                             pl->slice_max, pl->win_args, pl->partial, st));
     }
     {
         PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
@@ -528,7 +528,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
               dev_alloc(&pl->grid, (size_t)P * nr) &&
               dev_alloc(&pl->spart, (size_t)pl->ngroup_cap * pl->ldm) &&
               dev_alloc(&pl->mult, (size_t)n) && dev_alloc(&pl->tw, (size_t)n) &&
-              dev_alloc(&pl->flag, 1) && dev_alloc(&pl->chunk_exp, (size_t)pl->nchunk_cap);
+              dev_alloc(&pl->flag, 1) && dev_alloc(&pl->slice_max, (size_t)((cap + kSliceLen - 1) / kSliceLen));
     if (ok && grad)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
              dev_alloc(&pl->mult_d, (size_t)n) && dev_alloc(&pl->tprime, (size_t)P * pl->ld_y);
