@@ -35,10 +35,12 @@ struct GridGeom {
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 
 // out[p*ld + j] = sum_i A[p*dpad + i] * X[j*d + i] for p < P, j < N, with
-// A = tau * Xi^T zero-padded to (P_pad x dpad).  Sets *flag if |out| > bound.
+// A = tau * Xi^T (P x dpad).  A64 (may be null; used when d <= 64) is the same
+// matrix zero-padded to round_up(P, 64) x 64.  Sets *flag if |out| > bound.
+constexpr int kA64Cols = 64;
 hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
-                              const float* A, int P, float* out, int64_t ld,
-                              float bound, int* flag, hipStream_t stream);
+                              const float* A, const float* A64, int P, float* out,
+                              int64_t ld, float bound, int* flag, hipStream_t stream);
 hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
                                const uint16_t* A, int P, float* out, int64_t ld,
                                float bound, int* flag, hipStream_t stream);

@@ -239,79 +239,137 @@ __device__ __forceinline__ void project_tile_bf16(
 
 // d <= 64: the block keeps its 128-point X tile in LDS for its whole life
 // and walks a range of 64-direction tiles, so X is read from memory once per
-// direction range instead of once per direction tile.  The next A tile is
-// loaded into registers while the current one feeds the MFMAs.
+// direction range instead of once per direction tile.  A64 is tau * Xi^T
+// zero-padded to 64 columns and to a multiple of 64 rows, so the next A tile
+// is fetched with unconditional 16-byte loads into registers while the
+// current one feeds the MFMAs.  Full tiles store without branches, which
+// lets the wait for the prefetched A tile skip the tile's own stores.
 constexpr int kXresMaxD = 64;
 constexpr int kXresLd = kXresMaxD + 1;
-constexpr int kXresQA = kProjBM * kXresMaxD / kBlock;   // A floats per thread and tile
+constexpr int kXresQ4 = kProjBM * kXresMaxD / (4 * kBlock);   // float4 per thread and tile
 
 struct ProjSmemXres {
     float Xs[kProjBN][kXresLd];
     float As[kProjBM][kXresLd];
 };
 
-__device__ __forceinline__ void xres_load_a(float (&va)[kXresQA], const float* __restrict__ A,
-                                            int P, int d, int dpad, int p0) {
+__device__ __forceinline__ void xres_load_a(float4 (&va)[kXresQ4], const float* __restrict__ A64,
+                                            int p0) {
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(A64 + (int64_t)p0 * kXresMaxD);
 #pragma unroll
-    for (int q = 0; q < kXresQA; ++q) {
-        const int e = threadIdx.x + q * kBlock, r = e / kXresMaxD, k = e % kXresMaxD;
-        va[q] = (k < d && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k] : 0.f;
+    for (int q = 0; q < kXresQ4; ++q) va[q] = src[threadIdx.x + q * kBlock];
+}
+
+__device__ __forceinline__ void project_store_full(const f32x4 (&acc)[4][2], int p0, int64_t n0,
+                                                   float* __restrict__ out, int64_t ld,
+                                                   float bound, bool& bad) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float* __restrict__ base = out + (int64_t)(p0 + (lane & 15)) * ld + n0 + wave * 32 + 4 * (lane >> 4);
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const f32x4 v = acc[bi][bj];
+            *reinterpret_cast<float4*>(base + (int64_t)bi * 16 * ld + bj * 16) =
+                make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bad |= !(fabsf(v[r]) <= bound);
+        }
+}
+
+template <int KS>   // number of k-steps of 4 (fully unrolled)
+__device__ __forceinline__ void xres_mfma(const ProjSmemXres& sm, f32x4 (&acc)[4][2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4 * KS; ks += 4) {
+        float a[4], b[2];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) a[bi] = sm.As[bi * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+            b[bj] = sm.Xs[wave * 32 + bj * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
     }
 }
 
+__device__ __forceinline__ void xres_put_a(ProjSmemXres& sm, const float4 (&va)[kXresQ4]) {
+#pragma unroll
+    for (int q = 0; q < kXresQ4; ++q) {
+        const int e4 = threadIdx.x + q * kBlock, r = e4 >> 4, c = (e4 & 15) * 4;
+        sm.As[r][c] = va[q].x;
+        sm.As[r][c + 1] = va[q].y;
+        sm.As[r][c + 2] = va[q].z;
+        sm.As[r][c + 3] = va[q].w;
+    }
+}
+
+template <int KS>
 __device__ __forceinline__ void project_tile_f32_xres(
-    ProjSmemXres& sm, const float* __restrict__ X, int64_t N, int d, int dpad,
-    const float* __restrict__ A, int P, float* __restrict__ out, int64_t ld, float bound,
+    ProjSmemXres& sm, const float* __restrict__ X, int64_t N, int d,
+    const float* __restrict__ A64, int P, float* __restrict__ out, int64_t ld, float bound,
     int* __restrict__ flag, int p_begin, int p_end, int64_t n0) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int kend = (d + 3) & ~3;                  // MFMA k-steps of 4, zero padded
-    float va[kXresQA];
-    xres_load_a(va, A, P, d, dpad, p_begin);
+    const int tid = threadIdx.x;
+    float4 va[kXresQ4];
+    xres_load_a(va, A64, p_begin);
     __syncthreads();                                // LDS may still be read by a previous tile
     // X tile: rows n0..n0+127 are contiguous in memory (row length d)
     for (int e = tid; e < kProjBN * kXresLd; e += kBlock) {
         const int r = e / kXresLd, k = e % kXresLd;
         sm.Xs[r][k] = (k < d && n0 + r < N) ? X[(n0 + r) * d + k] : 0.f;
     }
-    for (int p0 = p_begin; p0 < p_end; p0 += kProjBM) {
+    // steady state: whole 64 x 128 tiles, straight-line code so the wait
+    // for the prefetched A tile does not include this tile's stores
+    const int p_full = (n0 + kProjBN <= N) ? p_begin + ((p_end - p_begin) / kProjBM) * kProjBM
+                                           : p_begin;
+    const int p_last = p_begin + ((p_end - p_begin - 1) / kProjBM) * kProjBM;
+    bool bad = false;
+    f32x4 acc[4][2];
+    int p0 = p_begin;
+    for (; p0 < p_full; p0 += kProjBM) {
         __syncthreads();                            // previous tile's MFMAs are done with As
-#pragma unroll
-        for (int q = 0; q < kXresQA; ++q) {
-            const int e = tid + q * kBlock;
-            sm.As[e / kXresMaxD][e % kXresMaxD] = va[q];
-        }
+        xres_put_a(sm, va);
         __syncthreads();
-        if (p0 + kProjBM < p_end) xres_load_a(va, A, P, d, dpad, p0 + kProjBM);   // prefetch
-        f32x4 acc[4][2];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < kend; ks += 4) {
-            float a[4], b[2];
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi) a[bi] = sm.As[bi * 16 + (lane & 15)][ks + (lane >> 4)];
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-                b[bj] = sm.Xs[wave * 32 + bj * 16 + (lane & 15)][ks + (lane >> 4)];
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
-        }
+        xres_load_a(va, A64, min(p0 + kProjBM, p_last));   // prefetch (last tile re-read)
+        xres_mfma<KS>(sm, acc);
+        project_store_full(acc, p0, n0, out, ld, bound, bad);
+    }
+    // ragged tail: a partial direction tile and/or the last point tile
+    for (; p0 < p_end; p0 += kProjBM) {
+        __syncthreads();
+        xres_put_a(sm, va);
+        __syncthreads();
+        if (p0 + kProjBM < p_end) xres_load_a(va, A64, p0 + kProjBM);
+        xres_mfma<KS>(sm, acc);
         project_store(acc, p0, n0, P, N, out, ld, bound, flag);
     }
+    if (bad) atomicOr(flag, 1);
 }
 
+template <int KS>
 __global__ __launch_bounds__(kBlock) void project_f32_xres_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad, const float* __restrict__ A,
+    const float* __restrict__ X, int64_t N, int d, const float* __restrict__ A64,
     int P, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag,
     int prange) {
     __shared__ ProjSmemXres sm;
     const int p_begin = blockIdx.y * prange;
-    project_tile_f32_xres(sm, X, N, d, dpad, A, P, out, ld, bound, flag, p_begin,
-                          min(P, p_begin + prange), (int64_t)blockIdx.x * kProjBN);
+    project_tile_f32_xres<KS>(sm, X, N, d, A64, P, out, ld, bound, flag, p_begin,
+                              min(P, p_begin + prange), (int64_t)blockIdx.x * kProjBN);
+}
+
+template <int KS>
+void launch_xres(dim3 grid, hipStream_t stream, const float* X, int64_t N, int d,
+                 const float* A64, int P, float* out, int64_t ld, float bound, int* flag,
+                 int prange) {
+    hipLaunchKernelGGL(project_f32_xres_kernel<KS>, grid, dim3(kBlock), 0, stream, X, N, d, A64,
+                       P, out, ld, bound, flag, prange);
 }
 
 __global__ __launch_bounds__(kBlock) void project_f32_kernel(
@@ -339,13 +397,19 @@ int project_xres_range(int64_t N, int P) {
 }
 
 hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
-                              const float* A, int P, float* out, int64_t ld,
+                              const float* A, const float* A64, int P, float* out, int64_t ld,
                               float bound, int* flag, hipStream_t stream) {
-    if (d <= kXresMaxD) {
+    if (d <= kXresMaxD && A64 != nullptr) {
         const int prange = project_xres_range(N, P);
         dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + prange - 1) / prange));
-        hipLaunchKernelGGL(project_f32_xres_kernel, grid, dim3(kBlock), 0, stream, X, N, d, dpad,
-                           A, P, out, ld, bound, flag, prange);
+        using L = void (*)(dim3, hipStream_t, const float*, int64_t, int, const float*, int,
+                           float*, int64_t, float, int*, int);
+        static const L table[16] = {
+            launch_xres<1>, launch_xres<2>, launch_xres<3>, launch_xres<4>,
+            launch_xres<5>, launch_xres<6>, launch_xres<7>, launch_xres<8>,
+            launch_xres<9>, launch_xres<10>, launch_xres<11>, launch_xres<12>,
+            launch_xres<13>, launch_xres<14>, launch_xres<15>, launch_xres<16>};
+        table[(d + 3) / 4 - 1](grid, stream, X, N, d, A64, P, out, ld, bound, flag, prange);
         return hipGetLastError();
     }
     dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + kProjBM - 1) / kProjBM));

@@ -313,6 +313,7 @@ struct fastsum_plan_s {
     int device = 0;
     // device buffers
     float* A = nullptr;            // tau * Xi^T, P x dpad
+    float* A64 = nullptr;          // the same, zero-padded to round_up(P, 64) x 64 (d <= 64)
     uint16_t* A16 = nullptr;       // BF16 copy
     float* xproj = nullptr;
     float* yproj = nullptr;
@@ -348,7 +349,7 @@ void free_plan(fastsum_plan_s* p) {
     if (!p) return;
     for (auto& r : p->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    void* bufs[] = {p->A, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
+    void* bufs[] = {p->A, p->A64, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max};
     for (void* b : bufs)
@@ -438,8 +439,8 @@ fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out
     if (pl->r.p.proj == FASTSUM_PROJ_BF16)
         return check(launch_project_bf16(X, N, pl->d, pl->dpad, pl->A16, pl->P, out, ld,
                                          pl->bound, pl->flag, st));
-    return check(launch_project_f32(X, N, pl->d, pl->dpad, pl->A, pl->P, out, ld, pl->bound,
-                                    pl->flag, st));
+    return check(launch_project_f32(X, N, pl->d, pl->dpad, pl->A, pl->A64, pl->P, out, ld,
+                                    pl->bound, pl->flag, st));
 }
 
 }  // namespace
@@ -529,6 +530,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
               dev_alloc(&pl->spart, (size_t)pl->ngroup_cap * pl->ldm) &&
               dev_alloc(&pl->mult, (size_t)n) && dev_alloc(&pl->tw, (size_t)n) &&
               dev_alloc(&pl->flag, 1) && dev_alloc(&pl->slice_max, (size_t)((cap + kSliceLen - 1) / kSliceLen));
+    const int64_t p64 = round_up(P, 64);
+    if (ok && pl->d <= kA64Cols) ok = dev_alloc(&pl->A64, (size_t)p64 * kA64Cols);
     if (ok && grad)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
              dev_alloc(&pl->mult_d, (size_t)n) && dev_alloc(&pl->tprime, (size_t)P * pl->ld_y);
@@ -545,7 +548,15 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
             A[(size_t)p * pl->dpad + i] = v;
             A16[(size_t)p * pl->dpad + i] = f32_to_bf16_host(v);
         }
+    std::vector<float> A64;
+    if (pl->A64) {
+        A64.assign((size_t)p64 * kA64Cols, 0.f);
+        for (int p = 0; p < P; ++p)
+            for (int i = 0; i < pl->d; ++i) A64[(size_t)p * kA64Cols + i] = A[(size_t)p * pl->dpad + i];
+    }
     hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->A64)
+        e = hipMemcpyAsync(pl->A64, A64.data(), A64.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->A16, A16.data(), A16.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->mult, mult.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
