@@ -65,18 +65,28 @@ def timed_steps(fn, steps, warmup):
 
 def algorithmic(phase, info, N, M, d, P, proj):
     """Bytes (and flops) one launch of a phase must move in this design,
-    inputs and outputs counted once (model with materialised projections)."""
+    inputs and outputs counted once.  A fused plan (d <= 64) computes the
+    projections inside spread and gather: those read the points (N x d,
+    M x d) and do the projection flops 2 N d P, 2 M d P instead of reading
+    stored P x N projections."""
     nr = info["grid_nr"]
+    fused = info.get("fused", 0) == 1
     if phase == "project":         # average of the x and y launches
         pts = (N + M) / 2.0
         byts = pts * d * 4 + P * d * 4 + P * pts * 4
         return byts, 2.0 * pts * d * P
     if phase == "spread":
-        return P * N * 4 + N * 4 + info["last_spread_chunks"] * P * nr * 4, 0.0
+        out = info["last_spread_chunks"] * P * nr * 4
+        if fused:
+            return N * d * 4 + N * 4 + P * d * 4 + out, 2.0 * N * d * P
+        return P * N * 4 + N * 4 + out, 0.0
     if phase == "fftconv":
         return info["last_spread_chunks"] * P * nr * 4 + P * nr * 4, 0.0
     if phase == "gather":
-        return P * M * 4 + P * nr * 4 + info["last_gather_groups"] * M * 8, 0.0
+        out = info["last_gather_groups"] * M * 8
+        if fused:
+            return M * d * 4 + P * d * 4 + P * nr * 4 + out, 2.0 * M * d * P
+        return P * M * 4 + P * nr * 4 + out, 0.0
     if phase == "reduce":
         return info["last_gather_groups"] * M * 8 + M * 4, 0.0
     return 0.0, 0.0

@@ -71,6 +71,12 @@ typedef enum {
 
 /* fastsum_params.flags */
 #define FASTSUM_FLAG_GRAD 1u /* keep what fastsum_grad needs (derivative grids) */
+/* Write the projections tau <xi_p, x_n> to device memory (needed for
+ * fastsum_debug_read of which = 0, 1).  Without it, and without
+ * FASTSUM_FLAG_GRAD, plans with d <= 64, FP32 projections and
+ * 16 * grid_nr <= 16384 compute the projections inside the spreading and
+ * gathering kernels and never store them (fastsum_plan_info.fused = 1). */
+#define FASTSUM_FLAG_MATERIALIZE 2u
 
 /*
  * Plan parameters.  Zero in an optional field selects the default.
@@ -121,6 +127,7 @@ typedef struct {
     int32_t grid_nr;     /* number of such cells (stored grids hold these)    */
     int32_t last_spread_chunks;  /* source chunks of the last exec's spread   */
     int32_t last_gather_groups;  /* direction groups of the last exec's gather */
+    int32_t fused;       /* 1: projections are computed inside spread/gather  */
 } fastsum_plan_info;
 
 typedef struct fastsum_plan_s* fastsum_plan;
@@ -199,10 +206,24 @@ FASTSUM_API fastsum_status fastsum_host_tables(const fastsum_params* prm, double
  * 1: projections of y (P x M); 2: convolved grids (P x grid_nr, cells
  * grid_lo .. grid_lo+grid_nr-1 of each direction's grid of n cells, which
  * holds the grid at position (j - n/2)/n).  count must equal the buffer's
- * element count.  Errors: EINVAL, ESTATE, EDEVICE.
+ * element count.  Errors: EINVAL, ESTATE (no exec yet, or which = 0, 1 on a
+ * fused plan, which stores no projections), EDEVICE.
  */
 FASTSUM_API fastsum_status fastsum_debug_read(fastsum_plan plan, int32_t which,
                                   float* host_out, int64_t count);
+
+/*
+ * Launch shape of later execs (results do not depend on it beyond FP32
+ * rounding of the per-chunk partial grids):
+ *   chunk_len   sources per spreading workgroup, a multiple of 4096, or 0
+ *               for the plan's rule; raised if N / chunk_len would exceed
+ *               the workspace sized at plan time
+ *   dir_range   directions per gathering workgroup of a fused plan, a
+ *               multiple of 16, or 0 for the plan's rule
+ * Errors: EINVAL (NULL plan, negative or misaligned values).
+ */
+FASTSUM_API fastsum_status fastsum_set_launch(fastsum_plan plan, int64_t chunk_len,
+                                              int32_t dir_range);
 
 /*
  * Batched form: many independent kernel-sum problems that share the kernel

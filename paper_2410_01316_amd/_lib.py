@@ -9,6 +9,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EUNSUPPORTED, ESTATE = range(7)
 KERNELS = {"gauss": 0, "laplace": 1, "energy": 2}
 PROJ = {"fp32": 0, "bf16": 1}
 FLAG_GRAD = 1
+FLAG_MATERIALIZE = 2
 PHASES = ("project", "spread", "fftconv", "gather", "reduce", "backproject")
 
 
@@ -31,6 +32,7 @@ class PlanInfo(ctypes.Structure):
         ("proj", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("grid_lo", ctypes.c_int32), ("grid_nr", ctypes.c_int32),
         ("last_spread_chunks", ctypes.c_int32), ("last_gather_groups", ctypes.c_int32),
+        ("fused", ctypes.c_int32),
     ]
 
 
@@ -65,6 +67,7 @@ SIGNATURES = {
     "fastsum_debug_read": (_st, [_vp, ctypes.c_int32, _vp, _i64]),
     "fastsum_status_string": (ctypes.c_char_p, [_st]),
     "fastsum_profile": (_st, [_vp, ctypes.c_int32]),
+    "fastsum_set_launch": (_st, [_vp, _i64, ctypes.c_int32]),
     "fastsum_batch_create": (_st, [ctypes.POINTER(Params), ctypes.POINTER(ProblemDesc), ctypes.c_int32,
                                    ctypes.POINTER(BatchTuning), _vp, ctypes.POINTER(_vp)]),
     "fastsum_batch_set_tuning": (_st, [_vp, ctypes.POINTER(BatchTuning)]),

@@ -34,8 +34,8 @@ class Plan:
     targets on one GPU.  See include/fastsum.h for every parameter."""
 
     def __init__(self, xi, *, kernel, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0,
-                 window_w=0, oversample=0, proj="fp32", grad=False, n_max, m_max,
-                 device=None):
+                 window_w=0, oversample=0, proj="fp32", grad=False, materialize=False,
+                 n_max, m_max, device=None):
         lib = L.load()
         xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float32))
         if xi.ndim != 2:
@@ -48,7 +48,8 @@ class Plan:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.kernel = kernel
         self.prm = L.Params(self.d, self.P, int(n_ft), int(window_w), int(oversample),
-                            L.KERNELS[kernel], L.PROJ[proj], L.FLAG_GRAD if grad else 0,
+                            L.KERNELS[kernel], L.PROJ[proj],
+                            (L.FLAG_GRAD if grad else 0) | (L.FLAG_MATERIALIZE if materialize else 0),
                             float(scale), float(T), float(gmax_factor), float(R))
         self.n_max, self.m_max = int(n_max), int(m_max)
         self._h = ctypes.c_void_p()
@@ -119,6 +120,13 @@ class Plan:
                                               out.size)
         L.check(st, "fastsum_debug_read")
         return out
+
+    def set_launch(self, chunk_len=0, dir_range=0):
+        """Launch shape of later calls (0 = the plan's rule): sources per
+        spreading workgroup (multiple of 4096), directions per fused
+        gathering workgroup (multiple of 16)."""
+        L.check(self._lib.fastsum_set_launch(self._h, int(chunk_len), int(dir_range)),
+                "fastsum_set_launch")
 
     def profile(self, enable=True):
         """Record HIP events around every kernel launch of later calls."""

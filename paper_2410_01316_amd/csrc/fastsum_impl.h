@@ -22,14 +22,11 @@ struct WindowArgs {
 
 // Grid geometry: n cells, position u = x~ * n + n/2 for x~ in [-1/2, 1/2).
 // Only cells [lo, lo + nr) can receive or serve weight for points inside the
-// plan's bound; positions are clamped to [u_min, u_max] so that every tap of
-// every (even out-of-bound) point stays inside that range.
+// plan's bound; the kernels clamp every point's taps into that range.
 struct GridGeom {
     int n;
     int lo;
     int nr;
-    float u_min;
-    float u_max;
 };
 
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
@@ -82,6 +79,31 @@ hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
                               int P, int d, const float* A, int dpad,
                               float coef, const float* v, float* grad_y,
                               hipStream_t stream);
+
+// ---- fused projection + spread / gather (d <= kA64Cols, FP32) ----
+
+constexpr int kFuseDirs = 16;   // directions per fused workgroup
+
+// true if the fused kernels handle dimension d and grids of nr cells
+bool fused_supported(int d, int nr);
+// targets per fused gather workgroup
+int64_t fused_gather_tile();
+// resident workgroups per CU of the fused spread and gather kernels
+void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_blocks);
+
+// As launch_spread, with proj replaced by tau * Xi^T (A64) applied to X
+// (N x d) inside the kernel; sets *flag if a projection exceeds bound.
+hipError_t launch_spread_fused(int W, const float* X, int64_t N, int d, const float* A64,
+                               const float* w, int P, GridGeom g, int nchunk, int64_t chunk_len,
+                               float* slice_max, const WindowArgs& win, float* partial,
+                               float bound, int* flag, hipStream_t stream);
+
+// spart[b*ldm + m] = sum over directions p of range b (prange per range, a
+// multiple of kFuseDirs) of the interpolated grid at tau <xi_p, y_m>, FP64.
+hipError_t launch_gather_fused(int W, const float* Y, int64_t M, int d, const float* A64,
+                               int P, GridGeom g, const float* grid, int prange,
+                               const WindowArgs& win, double* spart, int64_t ldm,
+                               float bound, int* flag, hipStream_t stream);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

@@ -13,7 +13,8 @@ namespace host {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int64_t kChunkAlign = kSliceLen;       // spread chunks start on fixed-point slices
-constexpr int64_t kMaxChunk = (int64_t)1 << 20;   // keeps the 64-bit fixed-point sums exact
+constexpr int64_t kMaxChunk = (int64_t)1 << 20;   // sources per spreading workgroup, at most
+constexpr int64_t kFusedMaxChunks = 16;           // fused spreading: source chunks, at most (rule)
 
 // Exponential-of-semicircle window phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
 // |z| <= 1, z = (cell - u) / (W/2).  Tap t of a point with sp = frac(u) - 1/2
@@ -58,6 +59,8 @@ void build_tables(int kernel, int d, double scale, double tau, int n_ft, int n,
 int spread_chunks(int64_t N, int P);
 int64_t spread_chunk_len(int64_t N, int nchunk);
 int gather_group(int64_t M, int P, int pstage);
+int fused_chunks(int64_t N, int P, int64_t slots);
+int fused_dir_range(int64_t M, int P, int64_t slots);
 int64_t round_up(int64_t v, int64_t m);
 fastsum_status status_of(hipError_t e);
 

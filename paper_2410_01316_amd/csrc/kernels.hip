@@ -33,34 +33,69 @@ template <> struct WinShape<4> { static constexpr int NE = 3, NO = 2; };  // deg
 template <> struct WinShape<6> { static constexpr int NE = 3, NO = 3; };  // degree 5
 template <> struct WinShape<8> { static constexpr int NE = 4, NO = 4; };  // degree 7
 
+// Per-thread constants of window evaluation on one grid.  The leading
+// Horner coefficients live in VGPRs: a VALU instruction reads at most one
+// scalar register and the first Horner step would otherwise need two.
+template <int W>
+struct WinEval {
+    float n, half_n;
+    int off;                      // W/2 - 1 + lo: first tap of cell 0, relative to lo
+    int maxb;                     // nr - W: largest first tap
+    float e_lead[W / 2], o_lead[W / 2];
+    __device__ __forceinline__ WinEval(const GridGeom& g, const WindowArgs& win) {
+        constexpr int NE = WinShape<W>::NE, NO = WinShape<W>::NO;
+        n = (float)g.n;
+        half_n = 0.5f * (float)g.n;
+        off = W / 2 - 1 + g.lo;
+        maxb = g.nr - W;
+#pragma unroll
+        for (int t = 0; t < W / 2; ++t) {
+            e_lead[t] = win.even[t][NE - 1];
+            o_lead[t] = win.odd[t][NO - 1];
+            asm volatile("" : "+v"(e_lead[t]));
+            asm volatile("" : "+v"(o_lead[t]));
+        }
+    }
+};
+
+// Even and odd parts of the taps of window pair t at offset sp (q = sp^2).
+template <int W>
+__device__ __forceinline__ void window_pair(float q, int t, const WindowArgs& win,
+                                            const WinEval<W>& ev, float& e, float& o) {
+    constexpr int NE = WinShape<W>::NE, NO = WinShape<W>::NO;
+    e = ev.e_lead[t];
+#pragma unroll
+    for (int j = NE - 2; j >= 0; --j) e = fmaf(e, q, win.even[t][j]);
+    o = ev.o_lead[t];
+#pragma unroll
+    for (int j = NO - 2; j >= 0; --j) o = fmaf(o, q, win.odd[t][j]);
+}
+
 template <int W>
 __device__ __forceinline__ void window_weights(float sp, const WindowArgs& win,
-                                               float (&wt)[W]) {
-    constexpr int NE = WinShape<W>::NE, NO = WinShape<W>::NO;
+                                               const WinEval<W>& ev, float (&wt)[W]) {
     const float q = sp * sp;
 #pragma unroll
     for (int t = 0; t < W / 2; ++t) {
-        float e = win.even[t][NE - 1];
-#pragma unroll
-        for (int j = NE - 2; j >= 0; --j) e = fmaf(e, q, win.even[t][j]);
-        float o = win.odd[t][NO - 1];
-#pragma unroll
-        for (int j = NO - 2; j >= 0; --j) o = fmaf(o, q, win.odd[t][j]);
-        o *= sp;
-        wt[t] = e + o;
-        wt[W - 1 - t] = e - o;
+        float e, o;
+        window_pair<W>(q, t, win, ev, e, o);
+        wt[t] = fmaf(o, sp, e);
+        wt[W - 1 - t] = fmaf(-o, sp, e);
     }
 }
 
-// Position of a rescaled projection in grid cells, clamped so that all W
-// taps fall in [lo, lo + nr).  Returns the first tap relative to lo.
-__device__ __forceinline__ int grid_position(float xt, const GridGeom& g,
-                                             int half_w_m1, float& sp) {
-    float u = fmaf(xt, (float)g.n, 0.5f * (float)g.n);
-    u = fminf(fmaxf(u, g.u_min), g.u_max);   // NaN maps to u_min
-    const float fl = floorf(u);
-    sp = u - fl - 0.5f;
-    return (int)fl - half_w_m1 - g.lo;
+// Position u = x~ n + n/2 of a rescaled projection in grid cells: returns
+// the first tap floor(u) - (W/2 - 1) - lo, clamped to [0, nr - W] so that no
+// point (outside the bound, infinite or NaN) addresses a cell outside the
+// stored range, and sets sp = frac(u) - 1/2.  Points inside the bound are
+// never clamped (the stored range has a margin of a cell on each side).
+template <int W>
+__device__ __forceinline__ int tap0(float xt, const WinEval<W>& ev, float& sp) {
+    const float u = fmaf(xt, ev.n, ev.half_n);
+    sp = __builtin_amdgcn_fractf(u) - 0.5f;
+    int j;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(j) : "v"(u));
+    return min(max(j - ev.off, 0), ev.maxb);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,15 +515,25 @@ __device__ __forceinline__ int slice_exponent(float mx) {
     return ok ? 18 - e : 0;
 }
 
+// Adds ws * weight_t, rounded to the nearest integer (ties to even), to the
+// W cells of a point.  The rounding must be unbiased: ws * weight_t has only
+// a few fraction bits at the top of the fixed-point range, so exact halves
+// are common and rounding them up would add a bias that grows with the
+// number of sources.
 template <int W>
-__device__ __forceinline__ void spread_point(float xt, float ws, const GridGeom& g,
+__device__ __forceinline__ void spread_point(float xt, float ws, const WinEval<W>& ev,
                                              const WindowArgs& win, int* lds32) {
     float sp;
-    const int base = grid_position(xt, g, W / 2 - 1, sp);
-    float wt[W];
-    window_weights<W>(sp, win, wt);
+    int* __restrict__ c = lds32 + tap0<W>(xt, ev, sp);
+    const float q = sp * sp, spw = sp * ws;
 #pragma unroll
-    for (int t = 0; t < W; ++t) atomicAdd(&lds32[base + t], __float2int_rn(ws * wt[t]));
+    for (int t = 0; t < W / 2; ++t) {
+        float e, o;
+        window_pair<W>(q, t, win, ev, e, o);
+        e *= ws;
+        atomicAdd(c + t, __float2int_rn(fmaf(o, spw, e)));
+        atomicAdd(c + W - 1 - t, __float2int_rn(fmaf(-o, spw, e)));
+    }
 }
 
 template <int W>
@@ -499,6 +544,7 @@ __device__ __forceinline__ void spread_tile(
     int p, int c) {
     double* acc = reinterpret_cast<double*>(lds_raw);          // nr doubles
     int* lds32 = reinterpret_cast<int*>(acc + g.nr);          // nr ints
+    const WinEval<W> ev(g, win);
     __syncthreads();               // LDS may still be read by a previous tile
     for (int j = threadIdx.x; j < g.nr; j += kBlock) {
         acc[j] = 0.0;
@@ -523,10 +569,10 @@ __device__ __forceinline__ void spread_tile(
         }
 #pragma unroll
         for (int q = 0; q < kSliceSteps; ++q) {
-            spread_point<W>(xv[q].x, wv[q][0] * scale, g, win, lds32);
-            spread_point<W>(xv[q].y, wv[q][1] * scale, g, win, lds32);
-            spread_point<W>(xv[q].z, wv[q][2] * scale, g, win, lds32);
-            spread_point<W>(xv[q].w, wv[q][3] * scale, g, win, lds32);
+            spread_point<W>(xv[q].x, wv[q][0] * scale, ev, win, lds32);
+            spread_point<W>(xv[q].y, wv[q][1] * scale, ev, win, lds32);
+            spread_point<W>(xv[q].z, wv[q][2] * scale, ev, win, lds32);
+            spread_point<W>(xv[q].w, wv[q][3] * scale, ev, win, lds32);
         }
         __syncthreads();
         const double unscale = ldexp(1.0, -k);
@@ -693,15 +739,15 @@ hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
 constexpr int kGatherTPT = 4;   // consecutive targets per thread (one float4)
 
 template <int W>
-__device__ __forceinline__ float interp(float xt, const float* gl, const GridGeom& g,
+__device__ __forceinline__ float interp(float xt, const float* gl, const WinEval<W>& ev,
                                         const WindowArgs& win) {
     float sp;
-    const int base = grid_position(xt, g, W / 2 - 1, sp);
+    const float* __restrict__ c = gl + tap0<W>(xt, ev, sp);
     float wt[W];
-    window_weights<W>(sp, win, wt);
+    window_weights<W>(sp, win, ev, wt);
     float t = 0.f;
 #pragma unroll
-    for (int k = 0; k < W; ++k) t = fmaf(gl[base + k], wt[k], t);
+    for (int k = 0; k < W; ++k) t = fmaf(c[k], wt[k], t);
     return t;
 }
 
@@ -716,6 +762,7 @@ __device__ __forceinline__ void gather_tile(
     const bool active = m < M;
     const int p_begin = group * pg;
     const int p_end = min(P, p_begin + pg);
+    const WinEval<W> ev(g, win);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int ps = p_begin; ps < p_end; ps += pstage) {
         const int np = min(pstage, p_end - ps);
@@ -744,10 +791,10 @@ __device__ __forceinline__ void gather_tile(
                 float4 nxt = cur;
                 if (pp + 1 < np) nxt = *reinterpret_cast<const float4*>(rowp + (int64_t)(pp + 1) * ld);
                 const float* gl = lds + pp * g.nr;
-                const float t0 = interp<W>(cur.x, gl, g, win);
-                const float t1 = interp<W>(cur.y, gl, g, win);
-                const float t2 = interp<W>(cur.z, gl, g, win);
-                const float t3 = interp<W>(cur.w, gl, g, win);
+                const float t0 = interp<W>(cur.x, gl, ev, win);
+                const float t1 = interp<W>(cur.y, gl, ev, win);
+                const float t2 = interp<W>(cur.z, gl, ev, win);
+                const float t3 = interp<W>(cur.w, gl, ev, win);
                 if (WRITE_T) {
                     *reinterpret_cast<float4*>(tout + (int64_t)(ps + pp) * ld_t + m) =
                         make_float4(t0, t1, t2, t3);
@@ -875,6 +922,416 @@ hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
                        P, d, A, dpad, coef, v, grad_y);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// fused projection + spread / gather (d <= 64, FP32 projections)
+//
+// The projections x~ = tau <xi_p, x_n> never reach memory: a workgroup owns
+// 16 directions, computes 16 x 16 projection blocks of its points with
+// v_mfma_f32_16x16x4f32 and spreads or interpolates them from registers.
+// This removes the write and re-read of the P x N projection matrices, the
+// dominant memory traffic for small d.
+// ---------------------------------------------------------------------------
+
+constexpr int kSpreadBlock = 512;                          // 8 waves
+constexpr int kSpreadWaves = kSpreadBlock / 64;
+constexpr int kFuseAcc = 32;                               // FP32 cell accumulators per thread
+constexpr int kFuseMaxCells = kFuseAcc * kSpreadBlock;     // kFuseDirs * nr <= this
+constexpr int kGatherBlock = 512;                          // 8 waves, one workgroup per CU
+constexpr int kGatherWaves = kGatherBlock / 64;
+constexpr int kGatherNB = 8;                                // 16-target batches per wave
+constexpr int kGatherTargets = kGatherWaves * kGatherNB * 16;
+constexpr int kDmaBytes = 64 * 16;                         // one wave's 16-byte LDS-direct loads
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Raw buffer resource over [p, p + bytes) (bytes < 2^31): loads outside
+// it return zero without touching memory, which pads ragged tiles with no
+// branches.  Third descriptor word: 32-bit data format, no swizzle (gfx9).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ __forceinline__ float buffer_load_f32(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0));
+}
+
+__device__ __forceinline__ f32x4 buffer_load_f32x4(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0));
+}
+
+// Spread operands.  Lane (c, r) = (lane % 16, lane / 16) holds columns
+// 16t + 4r .. 16t + 4r + 3 of its row for t < T: one 16-byte load each, and
+// MFMA k-step 4t + j takes element j.  Steps whose columns are all >= d are
+// skipped (their direction operand is zero).  Columns >= d of a row read the
+// next row's first elements, which A64's zero columns cancel; the buffer
+// range check is per dword, so a load straddling the end of X returns its
+// in-range elements and zeros.  The batch's four weights come with it.
+template <int T>
+__device__ __forceinline__ void spread_load(f32x4 (&xv)[T], float (&wv)[4],
+                                            __amdgpu_buffer_rsrc_t xs, __amdgpu_buffer_rsrc_t ws,
+                                            int n0, int d, int c, int r) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) wv[i] = buffer_load_f32(ws, (n0 + 4 * r + i) * 4);
+    const int base = ((n0 + c) * d + 4 * r) * 4;
+#pragma unroll
+    for (int t = 0; t < T; ++t) xv[t] = buffer_load_f32x4(xs, base + 64 * t);
+}
+
+template <int T>
+__device__ __forceinline__ void spread_load_dirs(f32x4 (&dv)[T], const float* __restrict__ A64,
+                                                 int p, int r) {
+    const f32x4* __restrict__ src = reinterpret_cast<const f32x4*>(A64 + (int64_t)p * kA64Cols) + r;
+#pragma unroll
+    for (int t = 0; t < T; ++t) dv[t] = src[4 * t];
+}
+
+// C[point][dir]: lane (c, r) receives points 4r .. 4r+3 of direction c
+template <int T>
+__device__ __forceinline__ f32x4 spread_project(const f32x4 (&xv)[T], const f32x4 (&dv)[T], int d) {
+    f32x4 pr = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (t < T - 1 || 16 * t + j < d)
+                pr = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[t][j], dv[t][j], pr, 0, 0, 0);
+    return pr;
+}
+
+// Spread with projections computed in registers.  Workgroup (x, y) owns the
+// 16 directions 16x .. 16x+15 and the sources of chunk y; grids are
+// kFuseDirs x nr int32 cells in LDS (fixed point per slice as in
+// spread_tile) flushed after every slice into per-thread FP32 accumulators.
+template <int W, int T>
+__global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
+    const float* __restrict__ X, int64_t N, int d, const float* __restrict__ A64,
+    const float* __restrict__ w, int P, GridGeom g, int64_t chunk_len,
+    const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial,
+    float bound, int* __restrict__ flag) {
+    extern __shared__ int cells[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, r = lane >> 4;
+    const int p0 = blockIdx.x * kFuseDirs;
+    const int ncell = kFuseDirs * g.nr;
+    f32x4 dv[T];
+    spread_load_dirs<T>(dv, A64, p0 + c, r);
+    float acc[kFuseAcc];
+#pragma unroll
+    for (int q = 0; q < kFuseAcc; ++q) acc[q] = 0.f;
+    for (int j = tid; j < ncell; j += kSpreadBlock) cells[j] = 0;
+    __syncthreads();
+    int* gcol = cells + c * g.nr;                     // grid of direction p0 + c
+    const WinEval<W> ev(g, win);
+    const int64_t i0 = (int64_t)blockIdx.y * chunk_len;   // multiple of kSlice
+    const int len = (int)min(N - i0, chunk_len);           // <= 2^20 sources
+    // the chunk's rows and the next one (a 16-byte operand load of the
+    // chunk's last row reaches into it); every other row reads as zero
+    const int xrows = (int)min(N - i0, (int64_t)len + 1);
+    const __amdgpu_buffer_rsrc_t xs = buffer_rsrc(X + i0 * d, (int64_t)xrows * d * 4);
+    const __amdgpu_buffer_rsrc_t ws = buffer_rsrc(w + i0, (int64_t)len * 4);
+    bool bad = false;
+    // projects one batch of 16 sources on the 16 directions and spreads it
+    auto batch = [&](const f32x4 (&xv)[T], const float (&wv)[4], float scale) {
+        const f32x4 pr = spread_project<T>(xv, dv, d);   // points 4r + i, direction c
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bad |= !(fabsf(pr[i]) <= bound);
+            spread_point<W>(pr[i], wv[i] * scale, ev, win, gcol);
+        }
+    };
+    for (int s0 = 0; s0 < len; s0 += kSlice) {
+        const int k = slice_exponent(slice_max[(i0 + s0) / kSlice]);
+        const float scale = ldexpf(1.f, k);
+        const int s1 = min(len, s0 + kSlice);
+        // batches of 16 sources, wave-strided, two in flight: while one is
+        // spread the other's operands load.  Each buffer is reloaded only
+        // after its batch is done, so loads land in place (no copies that
+        // would wait on them).  The last loads of a slice fetch the next
+        // slice's first rows, harmlessly (loaded again at its start).
+        constexpr int stride = kSpreadWaves * 16;
+        int n0 = s0 + wave * 16;
+        f32x4 xa[T], xb[T];
+        float wa[4], wb[4];
+        spread_load<T>(xa, wa, xs, ws, n0, d, c, r);
+        for (; n0 < s1; n0 += 2 * stride) {
+            spread_load<T>(xb, wb, xs, ws, n0 + stride, d, c, r);
+            batch(xa, wa, scale);
+            spread_load<T>(xa, wa, xs, ws, n0 + 2 * stride, d, c, r);
+            if (n0 + stride < s1) batch(xb, wb, scale);
+        }
+        __syncthreads();
+        const float unscale = ldexpf(1.f, -k);
+#pragma unroll
+        for (int q = 0; q < kFuseAcc; ++q) {
+            const int j = tid + q * kSpreadBlock;
+            if (j < ncell) {
+                acc[q] = fmaf((float)cells[j], unscale, acc[q]);
+                cells[j] = 0;
+            }
+        }
+        __syncthreads();
+    }
+    // cells j = dir * nr + (cell - lo): the block's rows of partial are contiguous
+    const int nvalid = min(kFuseDirs, P - p0) * g.nr;
+    float* __restrict__ dst = partial + ((int64_t)blockIdx.y * P + p0) * g.nr;
+#pragma unroll
+    for (int q = 0; q < kFuseAcc; ++q) {
+        const int j = tid + q * kSpreadBlock;
+        if (j < nvalid) dst[j] = acc[q];
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// Gather operands (loaded once per workgroup): lane (c, r) supplies element
+// [c][4s + r] of k-step s from the rows of a buffer of row length d.  Rows
+// past the buffer read as zero; columns k >= d read a neighbouring element,
+// which the zero columns of A64 cancel.
+template <int KS>
+__device__ __forceinline__ void fused_load_points(float (&op)[KS], __amdgpu_buffer_rsrc_t rs,
+                                                  int row, int d, int r) {
+    const int base = (row * d + r) * 4;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) op[s] = buffer_load_f32(rs, base + 16 * s);
+}
+
+// A64 rows are zero-padded to 64 columns and to a multiple of 64 rows, so
+// every direction operand load is in bounds and needs no guard.
+template <int KS>
+__device__ __forceinline__ void fused_load_dirs(float (&op)[KS], const float* __restrict__ A64,
+                                                int p, int r) {
+    const float* __restrict__ src = A64 + (int64_t)p * kA64Cols + r;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) op[s] = src[4 * s];
+}
+
+// Copies the grids of directions p0 .. p0+np-1 (contiguous, np * nr floats)
+// into LDS with 16-byte LDS-direct loads, 1 KB per wave instruction.  Lanes
+// past the end re-read the group's first bytes (in bounds) and write into
+// the buffer's padding.  Completion is tracked by vmcnt.
+__device__ __forceinline__ void gather_stage(const float* __restrict__ grid, int p0, int np,
+                                             int nr, float* buf, int wave, int lane) {
+    const int nbytes = np * nr * 4;
+    const char* src = reinterpret_cast<const char*>(grid + (int64_t)p0 * nr);
+    for (int piece = wave; piece * kDmaBytes < nbytes; piece += kGatherWaves) {
+        int off = piece * kDmaBytes + lane * 16;
+        off = off < nbytes ? off : 0;
+        __builtin_amdgcn_global_load_lds(src + off, (lds_void*)(buf + piece * (kDmaBytes / 4)),
+                                         16, 0, 0);
+    }
+}
+
+// Gather with projections computed in registers.  Workgroup (x, y) owns the
+// kGatherTargets targets of tile x and the direction range y (prange
+// directions, a multiple of kFuseDirs).  The grids of each group of 16
+// directions are staged in one of two LDS buffers while the previous group
+// is interpolated; lane (c, r) holds directions 4r .. 4r+3 of target c of
+// each batch.  Per target the four directions are summed in FP32, the
+// groups in FP64.
+template <int W, int KS>
+__global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
+    const float* __restrict__ Y, int64_t M, int d, const float* __restrict__ A64, int P,
+    GridGeom g, const float* __restrict__ grid, int prange, int stage, WindowArgs win,
+    double* __restrict__ spart, int64_t ldm, float bound, int* __restrict__ flag) {
+    extern __shared__ float gls[];                    // 2 x stage floats
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, r = lane >> 4;
+    const int64_t mb = (int64_t)blockIdx.x * kGatherTargets;
+    const int mw = wave * (kGatherNB * 16);           // wave's first target in the tile
+    const int p_begin = blockIdx.y * prange;
+    const int p_end = min(P, p_begin + prange);
+    gather_stage(grid, p_begin, min(kFuseDirs, p_end - p_begin), g.nr, gls, wave, lane);
+    const __amdgpu_buffer_rsrc_t ys =
+        buffer_rsrc(Y + mb * d, min((int64_t)kGatherTargets, M - mb) * d * 4);
+    float yop[kGatherNB][KS];
+#pragma unroll
+    for (int b = 0; b < kGatherNB; ++b) fused_load_points<KS>(yop[b], ys, mw + 16 * b + c, d, r);
+    double accd[kGatherNB];
+#pragma unroll
+    for (int b = 0; b < kGatherNB; ++b) accd[b] = 0.0;
+    const WinEval<W> ev(g, win);
+    bool bad = false;
+    // interpolates the targets on the group of directions p0 .. p0+np-1
+    // whose grids are in gb and whose operand is dop
+    // Branch-free: a direction past np (ragged last group) reads direction
+    // 0's grid and contributes zero.  The projections of all batches are
+    // computed first, k-step by k-step across the batches: the kGatherNB
+    // accumulations are independent, so each MFMA issues while the previous
+    // ones are still in the pipeline.
+    auto group = [&](int np, const float* gb, const float (&dop)[KS]) {
+        f32x4 pr[kGatherNB];
+#pragma unroll
+        for (int b = 0; b < kGatherNB; ++b) pr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int b = 0; b < kGatherNB; ++b)
+                // C[dir][target]: lane holds directions p0 + 4r + i of target c
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(dop[s], yop[b][s], pr[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < kGatherNB; ++b) {
+            float t = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int dir = 4 * r + i;
+                const bool ok = dir < np;
+                const float v = interp<W>(pr[b][i], gb + (ok ? dir : 0) * g.nr, ev, win);
+                bad |= ok && !(fabsf(pr[b][i]) <= bound);
+                t += ok ? v : 0.f;
+            }
+            accd[b] += (double)t;
+        }
+    };
+    // Two groups per iteration, ping-ponging buffers and direction
+    // operands: a group's grids and operand are fetched while the previous
+    // group is interpolated.  Before a group starts, this wave's fetches have
+    // landed (vmcnt) and, after the barrier, every wave's have and no wave
+    // still reads the buffer about to be refilled.
+    float da[KS], db[KS];
+    fused_load_dirs<KS>(da, A64, p_begin + c, r);
+    float* buf0 = gls;
+    float* buf1 = gls + stage;
+    for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const int p1 = p0 + kFuseDirs;
+        if (p1 < p_end) {
+            gather_stage(grid, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
+            fused_load_dirs<KS>(db, A64, p1 + c, r);
+        }
+        group(min(kFuseDirs, p_end - p0), buf0, da);
+        if (p1 >= p_end) break;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const int p2 = p1 + kFuseDirs;
+        if (p2 < p_end) {
+            gather_stage(grid, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
+            fused_load_dirs<KS>(da, A64, p2 + c, r);
+        }
+        group(min(kFuseDirs, p_end - p1), buf1, db);
+    }
+    // sum the four lane groups r holding the same targets
+#pragma unroll
+    for (int b = 0; b < kGatherNB; ++b) {
+        double v = accd[b];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        const int64_t m = mb + mw + 16 * b + c;
+        if (r == 0 && m < M) spart[(int64_t)blockIdx.y * ldm + m] = v;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+template <int W, int T>
+void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const float* X, int64_t N,
+                           int d, const float* A64, const float* w, int P, const GridGeom& g,
+                           int64_t chunk_len, const float* slice_max, const WindowArgs& win,
+                           float* partial, float bound, int* flag) {
+    hipLaunchKernelGGL((spread_fused_kernel<W, T>), grid, dim3(kSpreadBlock), lds, stream, X, N,
+                       d, A64, w, P, g, chunk_len, slice_max, win, partial, bound, flag);
+}
+
+template <int W, int KS>
+void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const float* Y, int64_t M,
+                           int d, const float* A64, int P, const GridGeom& g, const float* gridv,
+                           int prange, int stage, const WindowArgs& win, double* spart,
+                           int64_t ldm, float bound, int* flag) {
+    static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_fused_kernel<W, KS>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  2 * kFuseMaxCells * (int)sizeof(float));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((gather_fused_kernel<W, KS>), grid, dim3(kGatherBlock), lds, stream, Y, M,
+                       d, A64, P, g, gridv, prange, stage, win, spart, ldm, bound, flag);
+}
+
+#define FS_T_TABLE(F, W) {F<W, 1>, F<W, 2>, F<W, 3>, F<W, 4>}
+#define FS_KS_TABLE(F, W)                                                                  \
+    {F<W, 1>, F<W, 2>, F<W, 3>, F<W, 4>, F<W, 5>, F<W, 6>, F<W, 7>, F<W, 8>, F<W, 9>,     \
+     F<W, 10>, F<W, 11>, F<W, 12>, F<W, 13>, F<W, 14>, F<W, 15>, F<W, 16>}
+
+bool fused_supported(int d, int nr) {
+    return d >= 1 && d <= kA64Cols && kFuseDirs * nr <= kFuseMaxCells;
+}
+
+int64_t fused_gather_tile() { return kGatherTargets; }
+
+void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_blocks) {
+    *spread_blocks = 1;
+    *gather_blocks = 1;
+    if (!fused_supported(d, nr)) return;
+    const void* sk = nullptr;
+    const void* gk = nullptr;
+    const int T = (d + 15) / 16, KS = (d + 3) / 4;
+    // occupancy is set by LDS and registers, which T and KS barely move:
+    // take the largest operand shapes as representative
+    (void)T;
+    (void)KS;
+    switch (W) {
+        case 4: sk = (const void*)&spread_fused_kernel<4, 4>; gk = (const void*)&gather_fused_kernel<4, 16>; break;
+        case 6: sk = (const void*)&spread_fused_kernel<6, 4>; gk = (const void*)&gather_fused_kernel<6, 16>; break;
+        default: sk = (const void*)&spread_fused_kernel<8, 4>; gk = (const void*)&gather_fused_kernel<8, 16>; break;
+    }
+    const int stage = (kFuseDirs * nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
+    (void)hipFuncSetAttribute(gk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * kFuseMaxCells * (int)sizeof(float));
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, sk, kSpreadBlock,
+                                                     (size_t)kFuseDirs * nr * sizeof(int)) == hipSuccess && b > 0)
+        *spread_blocks = b;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gk, kGatherBlock,
+                                                     (size_t)2 * stage * sizeof(float)) == hipSuccess && b > 0)
+        *gather_blocks = b;
+}
+
+hipError_t launch_spread_fused(int W, const float* X, int64_t N, int d, const float* A64,
+                               const float* w, int P, GridGeom g, int nchunk, int64_t chunk_len,
+                               float* slice_max, const WindowArgs& win, float* partial,
+                               float bound, int* flag, hipStream_t stream) {
+    if (!fused_supported(d, g.nr) || chunk_len % kSlice != 0) return hipErrorInvalidValue;
+    using L = void (*)(dim3, size_t, hipStream_t, const float*, int64_t, int, const float*,
+                       const float*, int, const GridGeom&, int64_t, const float*,
+                       const WindowArgs&, float*, float, int*);
+    static const L t4[4] = FS_T_TABLE(launch_spread_fused_t, 4);
+    static const L t6[4] = FS_T_TABLE(launch_spread_fused_t, 6);
+    static const L t8[4] = FS_T_TABLE(launch_spread_fused_t, 8);
+    const L* t = W == 4 ? t4 : W == 6 ? t6 : W == 8 ? t8 : nullptr;
+    if (!t) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(slice_max_kernel, dim3((unsigned)((N + kSlice - 1) / kSlice)), dim3(kBlock),
+                       0, stream, w, N, slice_max);
+    dim3 grid((unsigned)((P + kFuseDirs - 1) / kFuseDirs), (unsigned)nchunk);
+    t[(d + 15) / 16 - 1](grid, (size_t)kFuseDirs * g.nr * sizeof(int), stream, X, N, d, A64, w,
+                         P, g, chunk_len, slice_max, win, partial, bound, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_fused(int W, const float* Y, int64_t M, int d, const float* A64,
+                               int P, GridGeom g, const float* grid, int prange,
+                               const WindowArgs& win, double* spart, int64_t ldm,
+                               float bound, int* flag, hipStream_t stream) {
+    if (!fused_supported(d, g.nr) || prange % kFuseDirs != 0) return hipErrorInvalidValue;
+    using L = void (*)(dim3, size_t, hipStream_t, const float*, int64_t, int, const float*, int,
+                       const GridGeom&, const float*, int, int, const WindowArgs&, double*,
+                       int64_t, float, int*);
+    static const L t4[16] = FS_KS_TABLE(launch_gather_fused_t, 4);
+    static const L t6[16] = FS_KS_TABLE(launch_gather_fused_t, 6);
+    static const L t8[16] = FS_KS_TABLE(launch_gather_fused_t, 8);
+    const L* t = W == 4 ? t4 : W == 6 ? t6 : W == 8 ? t8 : nullptr;
+    if (!t) return hipErrorInvalidValue;
+    // one staging buffer: the group's grids rounded up to whole 1 KB pieces
+    const int stage = (kFuseDirs * g.nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
+    dim3 gd((unsigned)((M + kGatherTargets - 1) / kGatherTargets),
+            (unsigned)((P + prange - 1) / prange));
+    t[(d + 3) / 4 - 1](gd, (size_t)2 * stage * sizeof(float), stream, Y, M, d, A64, P, g, grid,
+                       prange, stage, win, spart, ldm, bound, flag);
+    return hipGetLastError();
+}
+#undef FS_KS_TABLE
+#undef FS_T_TABLE
+
 
 // ---------------------------------------------------------------------------
 // batched form: persistent kernels walking task lists

@@ -186,7 +186,7 @@ fastsum_status resolve_params(const fastsum_params* in, Resolved& r) {
     if (p.oversample == 0) p.oversample = 2;
     if (p.oversample != 2 && p.oversample != 4) return FASTSUM_EINVAL;
     if (p.proj != FASTSUM_PROJ_FP32 && p.proj != FASTSUM_PROJ_BF16) return FASTSUM_EINVAL;
-    if (p.flags & ~FASTSUM_FLAG_GRAD) return FASTSUM_EINVAL;
+    if (p.flags & ~(FASTSUM_FLAG_GRAD | FASTSUM_FLAG_MATERIALIZE)) return FASTSUM_EINVAL;
     if (p.T == 0.0) p.T = p.kernel == FASTSUM_GAUSS ? 0.3 : (p.kernel == FASTSUM_LAPLACE ? 0.1 : 0.45);
     if (p.gmax_factor == 0.0) p.gmax_factor = 5.0;
     if (!(p.R > 0.0) || !std::isfinite(p.R)) return FASTSUM_EINVAL;
@@ -212,8 +212,6 @@ GridGeom make_geom(int n, int W, double tauR) {
     lo &= ~3;
     g.lo = lo;
     g.nr = n - 2 * lo;
-    g.u_min = (float)(lo + W / 2 - 1);
-    g.u_max = (float)(n - lo - W / 2 - 1);
     return g;
 }
 
@@ -275,6 +273,52 @@ int64_t spread_chunk_len(int64_t N, int nchunk) {
     return round_up((N + nchunk - 1) / nchunk, kChunkAlign);
 }
 
+// Fraction of the last round of workgroups that is busy when `blocks`
+// workgroups run `slots` at a time (1 = every round full).
+static double round_efficiency(int64_t blocks, int64_t slots) {
+    const int64_t rounds = (blocks + slots - 1) / slots;
+    return (double)blocks / (double)(rounds * slots);
+}
+
+int fused_chunks(int64_t N, int P, int64_t slots) {
+    // whole slices per chunk; at least two rounds of workgroups, then the
+    // chunk count whose rounds are fullest (fewest chunks among near ties)
+    const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
+    const int64_t slices = (N + kSliceLen - 1) / kSliceLen;
+    const int64_t cmin = std::max<int64_t>(1, (N + kMaxChunk - 1) / kMaxChunk);
+    int64_t best = cmin;
+    double best_eff = -1.0;
+    const int64_t cmax = std::max(cmin, std::min<int64_t>(slices, kFusedMaxChunks));
+    for (int64_t nc = cmin; nc <= cmax; ++nc) {
+        const int64_t actual = (N + spread_chunk_len(N, (int)nc) - 1) / spread_chunk_len(N, (int)nc);
+        const int64_t blocks = groups * actual;
+        if (blocks < 2 * slots && nc < cmax) continue;
+        const double eff = round_efficiency(blocks, slots);
+        if (eff > best_eff + 0.02) { best_eff = eff; best = actual; }
+    }
+    return (int)best;
+}
+
+int fused_dir_range(int64_t M, int P, int64_t slots) {
+    // ranges of whole 16-direction groups; at least three rounds of
+    // workgroups when P allows, then the fullest rounds (fewest ranges
+    // among near ties: each range re-reads the targets)
+    const int64_t tiles = (M + fused_gather_tile() - 1) / fused_gather_tile();
+    const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
+    int64_t best_pr = groups * kFuseDirs;
+    double best_eff = -1.0;
+    for (int64_t r = 1; r <= groups; ++r) {
+        const int64_t pr = round_up((P + r - 1) / r, kFuseDirs);
+        const int64_t ranges = (P + pr - 1) / pr;
+        if (ranges != r) continue;
+        const int64_t blocks = tiles * ranges;
+        if (blocks < 3 * slots && r < groups) continue;
+        const double eff = round_efficiency(blocks, slots);
+        if (eff > best_eff + 0.02) { best_eff = eff; best_pr = pr; }
+    }
+    return (int)best_pr;
+}
+
 int gather_group(int64_t M, int P, int pstage) {
     // aim for about 1024 workgroups; group size a multiple of pstage, <= 128
     const int64_t tiles = (M + kGatherTile - 1) / kGatherTile;
@@ -309,6 +353,11 @@ struct fastsum_plan_s {
     int d = 0, P = 0, dpad = 0, W = 4;
     int64_t n_max = 0, m_max = 0, ld_x = 0, ld_y = 0, ldm = 0;
     int nchunk_cap = 1, pstage = 8, ngroup_cap = 1;
+    bool fused = false;               // projections inside spread / gather
+    bool have_proj = false;           // last exec stored its projections
+    int64_t tune_chunk_len = 0;       // fastsum_set_launch overrides (0: rule)
+    int64_t spread_slots = 1, gather_slots = 1;   // resident fused workgroups on the device
+    int tune_dir_range = 0;
     float bound = 0.f;
     int device = 0;
     // device buffers
@@ -400,6 +449,15 @@ fastsum_status check(hipError_t e) { return status_of(e); }
         if (_st != FASTSUM_OK) return _st;            \
     } while (0)
 
+// Spreading chunks: the plan's rule (rule_chunks) unless fastsum_set_launch
+// gave a chunk length; never more chunks than the workspace holds.
+int chunk_plan(const fastsum_plan_s* pl, int64_t N, int rule_chunks, int64_t& chunk_len) {
+    chunk_len = pl->tune_chunk_len > 0 ? pl->tune_chunk_len : spread_chunk_len(N, rule_chunks);
+    const int64_t min_len = spread_chunk_len(N, pl->nchunk_cap);
+    chunk_len = std::max(chunk_len, min_len);
+    return (int)((N + chunk_len - 1) / chunk_len);
+}
+
 // One 1-D Fourier summation pass for every direction:
 // spread (sources) -> fftconv -> gather (targets) into s.
 fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_src,
@@ -407,8 +465,8 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
                         int64_t ld_tgt, int64_t Mtgt, float* out, float* grid,
                         float* grid_d, hipStream_t st) {
     const int P = pl->P;
-    const int nchunk = spread_chunks(Nsrc, P);
-    const int64_t chunk_len = spread_chunk_len(Nsrc, nchunk);
+    int64_t chunk_len = 0;
+    const int nchunk = chunk_plan(pl, Nsrc, spread_chunks(Nsrc, P), chunk_len);
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
         FS_TRY(launch_spread(pl->W, src_proj, ld_src, wts, Nsrc, P, pl->geom, nchunk, chunk_len,
@@ -430,6 +488,39 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
     }
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
     FS_TRY(launch_reduce(pl->spart, ng, pl->ldm, Mtgt, 1.0 / P, out, st));
+    return FASTSUM_OK;
+}
+
+// Fused path: projections are computed inside the spreading and gathering
+// kernels (d <= 64, FP32).  spread(x, w) -> fftconv -> gather(y) -> reduce.
+fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, int64_t N,
+                          const float* y, int64_t M, float* out, hipStream_t st) {
+    const int P = pl->P;
+    int64_t chunk_len = 0;
+    const int nchunk = chunk_plan(pl, N, fused_chunks(N, P, pl->spread_slots), chunk_len);
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
+        FS_TRY(launch_spread_fused(pl->W, x, N, pl->d, pl->A64, w, P, pl->geom, nchunk,
+                                   chunk_len, pl->slice_max, pl->win_args, pl->partial,
+                                   pl->bound, pl->flag, st));
+    }
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
+        FS_TRY(launch_fftconv(pl->partial, nchunk, P, pl->geom, pl->tw, pl->mult, nullptr,
+                              pl->grid, nullptr, st));
+    }
+    const int prange = pl->tune_dir_range > 0 ? pl->tune_dir_range
+                                              : fused_dir_range(M, P, pl->gather_slots);
+    const int nrange = (P + prange - 1) / prange;
+    pl->last_nchunk = nchunk;
+    pl->last_ngroup = nrange;
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
+        FS_TRY(launch_gather_fused(pl->W, y, M, pl->d, pl->A64, P, pl->geom, pl->grid, prange,
+                                   pl->win_args, pl->spart, pl->ldm, pl->bound, pl->flag, st));
+    }
+    PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
+    FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, st));
     return FASTSUM_OK;
 }
 
@@ -520,6 +611,19 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     // spreads the targets: size for the larger of the two roles
     pl->nchunk_cap = spread_chunks(cap, P);
     const bool grad = (r.p.flags & FASTSUM_FLAG_GRAD) != 0;
+    pl->fused = !grad && !(r.p.flags & FASTSUM_FLAG_MATERIALIZE) &&
+                r.p.proj == FASTSUM_PROJ_FP32 && fused_supported(pl->d, nr);
+    if (pl->fused) {
+        int ncu = 0, sb = 1, gb = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess || ncu < 1)
+            ncu = 1;
+        fused_occupancy(pl->W, pl->d, nr, &sb, &gb);
+        pl->spread_slots = (int64_t)ncu * sb;
+        pl->gather_slots = (int64_t)ncu * gb;
+        // the rule never takes more than kFusedMaxChunks (or N / 2^20) chunks
+        pl->nchunk_cap = std::max<int>(pl->nchunk_cap, (int)std::max<int64_t>(
+                                           kFusedMaxChunks, (cap + kMaxChunk - 1) / kMaxChunk));
+    }
 
     bool ok = dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
               dev_alloc(&pl->A16, (size_t)P * pl->dpad) &&
@@ -582,6 +686,20 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
     const bool same = (x == y);
     if (same && N != M) return FASTSUM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    if (pl->fused) {
+        fastsum_status r = fused_pass(pl, x, w, N, y, M, s, st);
+        if (r != FASTSUM_OK) return r;
+        pl->have_exec = true;
+        pl->have_proj = false;
+        pl->last_same = same;
+        pl->last_x = x;
+        pl->last_w = w;
+        pl->last_y = y;
+        pl->last_N = N;
+        pl->last_M = M;
+        pl->last_stream = st;
+        return FASTSUM_OK;
+    }
     fastsum_status r = project(pl, x, N, pl->xproj, pl->ld_x, st);
     if (r != FASTSUM_OK) return r;
     const float* yp = pl->xproj;
@@ -596,6 +714,7 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
                  (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, st);
     if (r != FASTSUM_OK) return r;
     pl->have_exec = true;
+    pl->have_proj = true;
     pl->last_same = same;
     pl->last_x = x;
     pl->last_w = w;
@@ -662,6 +781,7 @@ fastsum_status fastsum_get_info(fastsum_plan pl, fastsum_plan_info* info) {
     info->grid_nr = pl->geom.nr;
     info->last_spread_chunks = pl->last_nchunk;
     info->last_gather_groups = pl->last_ngroup;
+    info->fused = pl->fused ? 1 : 0;
     return FASTSUM_OK;
 }
 
@@ -671,6 +791,7 @@ fastsum_status fastsum_debug_read(fastsum_plan pl, int32_t which, float* host_ou
     if (!pl->have_exec) return FASTSUM_ESTATE;
     const float* src = nullptr;
     int64_t rows = pl->P, cols = 0, ld = 0;
+    if ((which == 0 || which == 1) && !pl->have_proj) return FASTSUM_ESTATE;
     if (which == 0) { src = pl->xproj; cols = pl->last_N; ld = pl->ld_x; }
     else if (which == 1) {
         src = pl->last_same ? pl->xproj : pl->yproj;
@@ -683,6 +804,15 @@ fastsum_status fastsum_debug_read(fastsum_plan pl, int32_t which, float* host_ou
     if (hipMemcpy2D(host_out, cols * sizeof(float), src, ld * sizeof(float), cols * sizeof(float),
                     rows, hipMemcpyDeviceToHost) != hipSuccess)
         return FASTSUM_EDEVICE;
+    return FASTSUM_OK;
+}
+
+fastsum_status fastsum_set_launch(fastsum_plan pl, int64_t chunk_len, int32_t dir_range) {
+    if (!pl || chunk_len < 0 || chunk_len % kChunkAlign != 0 || chunk_len > kMaxChunk ||
+        dir_range < 0 || dir_range % kFuseDirs != 0)
+        return FASTSUM_EINVAL;
+    pl->tune_chunk_len = chunk_len;
+    pl->tune_dir_range = dir_range;
     return FASTSUM_OK;
 }
 

@@ -19,12 +19,12 @@ def err_scale(a, b, s_abs):
 
 
 def gpu_plan(cfg, n_ft=None, proj="fp32", grad=False, window_w=0, oversample=0, xi=None,
-             n_max=None, m_max=None, R=None):
+             n_max=None, m_max=None, R=None, materialize=False):
     import paper_2410_01316_amd as F
     xi = cfg["xi"] if xi is None else xi
     return F.Plan(xi, kernel=cfg["kernel"], n_ft=n_ft or cfg["n_ft"], scale=cfg["scale"],
                   R=R or cfg["R"], T=DEFAULT_T[cfg["kernel"]], window_w=window_w,
-                  oversample=oversample, proj=proj, grad=grad,
+                  oversample=oversample, proj=proj, grad=grad, materialize=materialize,
                   n_max=n_max or cfg["x"].shape[0], m_max=m_max or cfg["y"].shape[0])
 
 

@@ -1,0 +1,121 @@
+"""GPU parity of the fused path (projections computed inside the spreading
+and gathering kernels, d <= 64) against the path that stores projections,
+and against the FP64 oracle, over the launch shapes and edge sizes.
+
+The two paths differ only in FP32 rounding order: the fused spread sums the
+coordinates of each projection in another order (16-byte operand groups),
+keeps per-slice cell sums in FP32 instead of FP64, and sums four directions
+in FP32 before the FP64 sum over directions.  Measured relative to
+s_abs = sum_n |w_n| |F(||x_n - y_m||)| (err_scale) that is ~1e-7: bar 1e-6.
+
+Against the oracle O3 the weights are signed, so s cancels (in d = 50 all
+pair distances are close to the median and s is a small difference of
+nearly equal sums): the window error is measured relative to
+s_abs = sum_n |w_n| F(||x_n - y_m||) (err_scale), W = 4 bar 2e-5."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import make_config, directions
+from workloads.points import median_rule_sigma
+from helpers import rel_l2, err_scale, gpu_plan, to_dev, oracle_inputs, DEFAULT_T
+
+pytestmark = pytest.mark.gpu
+
+
+def _o3(cfg):
+    x, y, w, xi = oracle_inputs(cfg)
+    tau = O.rescale_tau(cfg["kernel"], cfg["R"], cfg["scale"], DEFAULT_T[cfg["kernel"]])
+    return O.kernel_sum_fourier(cfg["kernel"], x, y, w, xi, cfg["scale"], cfg["n_ft"], tau)
+
+
+def _err3(cfg, s):
+    x, y, w, xi = oracle_inputs(cfg)
+    return err_scale(s, _o3(cfg), _sabs(cfg))
+
+
+def _sabs(cfg):
+    x, y, w, xi = oracle_inputs(cfg)
+    return np.abs(O.kernel_sum_direct(cfg["kernel"], x, y, np.abs(w), cfg["scale"]))
+
+
+def _both(cfg, **kw):
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    out = []
+    for mat in (False, True):
+        plan = gpu_plan(cfg, materialize=mat, **kw)
+        assert plan.info()["fused"] == (0 if mat else 1)
+        out.append(plan(x, w, y).cpu().numpy())
+        plan.check()
+    return out
+
+
+def _ragged(d, N, M, P, seed, n_ft=128, kernel="gauss", scale=None):
+    # scale None: the median rule (Sec. 4.1), which keeps the sliced spectrum
+    # well inside the N_ft band in any dimension
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((N, d))
+    y = rng.standard_normal((M, d)) * 0.8
+    w = rng.standard_normal(N)
+    R = float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max())
+    if scale is None:
+        scale = 1.3 if d < 10 else median_rule_sigma(x, y, np.random.default_rng(0))
+    return dict(x=x, y=y, w=w, xi=directions("distance", d, P, seed), kernel=kernel,
+                scale=scale, n_ft=n_ft, R=R)
+
+
+@pytest.mark.parametrize("d,N,M,P", [(1, 5000, 3001, 16), (3, 4097, 515, 17), (7, 777, 1333, 37),
+                                     (50, 9000, 1025, 70), (64, 8191, 600, 33)])
+def test_fused_equals_stored_projections(d, N, M, P):
+    cfg = _ragged(d, N, M, P, seed=d)
+    s_f, s_m = _both(cfg)
+    e3 = _err3(cfg, s_f)
+    em = err_scale(s_f, s_m, _sabs(cfg))
+    print("d=%d fused-stored %.2e fused-O3 %.2e (err_scale)" % (d, em, e3))
+    assert em < 1e-6
+    assert e3 < 2e-5
+
+
+def test_fused_scale_workload_sample():
+    # d = 50 mixture with signed weights, full grid (n_ft = 1024)
+    cfg = make_config("scale", frac=0.05, P=48)
+    s_f, s_m = _both(cfg)
+    assert err_scale(s_f, s_m, _sabs(cfg)) < 1e-6
+    assert rel_l2(s_f, _o3(cfg)) < 1e-4         # mixture data: little cancellation
+
+
+@pytest.mark.parametrize("chunk_len,dir_range", [(4096, 16), (8192, 32), (4096 * 3, 48), (0, 0)])
+def test_fused_launch_shapes(chunk_len, dir_range):
+    cfg = _ragged(20, 20000, 3000, 100, seed=9, n_ft=256)
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    plan = gpu_plan(cfg)
+    ref = plan(x, w, y).cpu().numpy()
+    plan.set_launch(chunk_len, dir_range)
+    s = plan(x, w, y).cpu().numpy()
+    info = plan.info()
+    if chunk_len:
+        assert info["last_spread_chunks"] == -(-20000 // chunk_len)
+    if dir_range:
+        assert info["last_gather_groups"] == -(-100 // dir_range)
+    assert err_scale(s, ref, _sabs(cfg)) < 1e-6
+    assert _err3(cfg, s) < 2e-5
+
+
+def test_fused_plan_stores_no_projections():
+    import paper_2410_01316_amd as F
+    cfg = make_config("tiny", frac=0.1)
+    plan = gpu_plan(cfg)
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    plan(x, w, y)
+    with pytest.raises(F.FastSumError) as e:
+        plan.debug_read(0)
+    assert e.value.status == 6            # ESTATE
+    assert plan.debug_read(2).shape[0] == cfg["xi"].shape[1]
+
+
+def test_fused_energy_and_laplace():
+    for kernel, n_ft in [("energy", 256), ("laplace", 512)]:
+        cfg = _ragged(10, 6000, 2000, 40, seed=11, n_ft=n_ft, kernel=kernel)
+        s_f, s_m = _both(cfg)
+        assert err_scale(s_f, s_m, _sabs(cfg)) < 1e-6
+        assert _err3(cfg, s_f) < 2e-5
