@@ -80,9 +80,19 @@ hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
                               float coef, const float* v, float* grad_y,
                               hipStream_t stream);
 
-// ---- fused projection + spread / gather (d <= kA64Cols, FP32) ----
+// ---- fused projection + spread / gather (d <= kSplitMaxD) ----
+//
+// Split-f16 operand tiles: a value v (points scaled by 1/R, directions as
+// they are) is held as hi = f16(v), lo = f16(v - hi).  Tile t (16 rows),
+// k-block kb (32 columns), part q (0 hi, 1 lo) is 1 KB: 64 lanes x 8 halves,
+// lane l = c + 16 j holding row 16t + c, columns 32kb + 8j .. +7, zero past
+// the rows and columns; byte offset ((t * KB + kb) * 2 + q) * 1024 + 16 l
+// with KB = ceil(d / 32).
 
-constexpr int kFuseDirs = 16;   // directions per fused workgroup
+constexpr int kFuseDirs = 16;        // directions per fused workgroup
+constexpr int kSplitMaxD = 64;       // d handled by the fused kernels
+constexpr int kSplitTileBytes = 1024;
+inline int split_kblocks(int d) { return (d + 31) / 32; }
 
 // true if the fused kernels handle dimension d and grids of nr cells
 bool fused_supported(int d, int nr);
@@ -90,20 +100,27 @@ bool fused_supported(int d, int nr);
 int64_t fused_gather_tile();
 // resident workgroups per CU of the fused spread and gather kernels
 void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_blocks);
+// bytes of the split tiles of `rows` rows of dimension d
+int64_t split_tiles_bytes(int64_t rows, int d);
 
-// As launch_spread, with proj replaced by tau * Xi^T (A64) applied to X
-// (N x d) inside the kernel; sets *flag if a projection exceeds bound.
-hipError_t launch_spread_fused(int W, const float* X, int64_t N, int d, const float* A64,
-                               const float* w, int P, GridGeom g, int nchunk, int64_t chunk_len,
-                               float* slice_max, const WindowArgs& win, float* partial,
-                               float bound, int* flag, hipStream_t stream);
+// tiles of Z * scale (Z: N x d row-major)
+hipError_t launch_split_points(const float* Z, int64_t N, int d, float scale, uint16_t* tiles,
+                               hipStream_t stream);
+
+// As launch_spread, with the projections computed in the kernel from the
+// split tiles of the sources (Xt, scale 1/R) and of the directions (At):
+// x~ = pscale * <xi, x / R>, pscale = tau R.  Sets *flag if |x~| > pscale * vbound.
+hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, const uint16_t* At,
+                               const float* w, int P, GridGeom g, float pscale, int nchunk,
+                               int64_t chunk_len, float* slice_max, const WindowArgs& win,
+                               float* partial, float vbound, int* flag, hipStream_t stream);
 
 // spart[b*ldm + m] = sum over directions p of range b (prange per range, a
 // multiple of kFuseDirs) of the interpolated grid at tau <xi_p, y_m>, FP64.
-hipError_t launch_gather_fused(int W, const float* Y, int64_t M, int d, const float* A64,
-                               int P, GridGeom g, const float* grid, int prange,
-                               const WindowArgs& win, double* spart, int64_t ldm,
-                               float bound, int* flag, hipStream_t stream);
+hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, const uint16_t* At,
+                               int P, GridGeom g, float pscale, const float* grid, int prange,
+                               const WindowArgs& win, double* spart, int64_t ldm, float vbound,
+                               int* flag, hipStream_t stream);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

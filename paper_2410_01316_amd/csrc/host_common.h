@@ -59,6 +59,7 @@ void build_tables(int kernel, int d, double scale, double tau, int n_ft, int n,
 int spread_chunks(int64_t N, int P);
 int64_t spread_chunk_len(int64_t N, int nchunk);
 int gather_group(int64_t M, int P, int pstage);
+void split_dirs_host(const float* xi, int d, int P, std::vector<uint16_t>& out);
 int fused_chunks(int64_t N, int P, int64_t slots);
 int fused_dir_range(int64_t M, int P, int64_t slots);
 int64_t round_up(int64_t v, int64_t m);

@@ -42,9 +42,11 @@ struct WinEval {
     int off;                      // W/2 - 1 + lo: first tap of cell 0, relative to lo
     int maxb;                     // nr - W: largest first tap
     float e_lead[W / 2], o_lead[W / 2];
-    __device__ __forceinline__ WinEval(const GridGeom& g, const WindowArgs& win) {
+    // pscale: the kernel's projection values are x~ / pscale
+    __device__ __forceinline__ WinEval(const GridGeom& g, const WindowArgs& win,
+                                       float pscale = 1.f) {
         constexpr int NE = WinShape<W>::NE, NO = WinShape<W>::NO;
-        n = (float)g.n;
+        n = (float)g.n * pscale;
         half_n = 0.5f * (float)g.n;
         off = W / 2 - 1 + g.lo;
         maxb = g.nr - W;
@@ -924,13 +926,25 @@ hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
 }
 
 // ---------------------------------------------------------------------------
-// fused projection + spread / gather (d <= 64, FP32 projections)
+// fused projection + spread / gather (d <= 64)
 //
 // The projections x~ = tau <xi_p, x_n> never reach memory: a workgroup owns
 // 16 directions, computes 16 x 16 projection blocks of its points with
-// v_mfma_f32_16x16x4f32 and spreads or interpolates them from registers.
-// This removes the write and re-read of the P x N projection matrices, the
-// dominant memory traffic for small d.
+// v_mfma_f32_16x16x32_f16 on split-f16 operands and spreads or interpolates
+// them from registers.  This removes the write and re-read of the P x N
+// projection matrices, the dominant memory traffic for small d.
+//
+// Split-f16 operands: a value v (points scaled by 1/R, directions as they
+// are, so |v| <= 1) is held as hi = f16(v) and lo = f16(v - hi); then
+// |v - hi - lo| <= 2^-22 |v| (lo may be subnormal: the MFMA keeps f16
+// subnormals), and hi_a hi_b + hi_a lo_b + lo_a hi_b, each product exact in
+// the FP32 accumulation, misses a.b by about 2^-21 |a||b| per term: FP32
+// accuracy at three f16 MFMAs per 32 columns instead of eight FP32 MFMAs.
+// Operand tiles (split_points_kernel, and on the host for directions): tile t
+// (16 rows), k-block kb (32 columns), part q (0 hi, 1 lo) is 64 lanes x 8
+// halves, lane l = c + 16 j holding row 16t + c, columns 32kb + 8j .. +7 —
+// exactly the MFMA operand layout, so each operand load is one contiguous
+// 1 KB wave access.
 // ---------------------------------------------------------------------------
 
 constexpr int kSpreadBlock = 512;                          // 8 waves
@@ -939,15 +953,17 @@ constexpr int kFuseAcc = 32;                               // FP32 cell accumula
 constexpr int kFuseMaxCells = kFuseAcc * kSpreadBlock;     // kFuseDirs * nr <= this
 constexpr int kGatherBlock = 512;                          // 8 waves, one workgroup per CU
 constexpr int kGatherWaves = kGatherBlock / 64;
-constexpr int kGatherNB = 8;                                // 16-target batches per wave
+constexpr int kGatherNB = 8;                               // 16-target batches per wave
 constexpr int kGatherTargets = kGatherWaves * kGatherNB * 16;
 constexpr int kDmaBytes = 64 * 16;                         // one wave's 16-byte LDS-direct loads
 
 typedef __attribute__((address_space(3))) void lds_void;
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Raw buffer resource over [p, p + bytes) (bytes < 2^31): loads outside
-// it return zero without touching memory, which pads ragged tiles with no
-// branches.  Third descriptor word: 32-bit data format, no swizzle (gfx9).
+// Raw buffer resource over [p, p + bytes) (bytes < 2^31): loads outside it
+// return zero without touching memory (checked per dword).  Third
+// descriptor word: 32-bit data format, no swizzle (gfx9).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, int64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
                                              0x00020000);
@@ -957,89 +973,130 @@ __device__ __forceinline__ float buffer_load_f32(__amdgpu_buffer_rsrc_t rs, int 
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0));
 }
 
-__device__ __forceinline__ f32x4 buffer_load_f32x4(__amdgpu_buffer_rsrc_t rs, int byte_off) {
-    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0));
+__device__ __forceinline__ h8 buffer_load_h8(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+    return __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0));
 }
 
-// Spread operands.  Lane (c, r) = (lane % 16, lane / 16) holds columns
-// 16t + 4r .. 16t + 4r + 3 of its row for t < T: one 16-byte load each, and
-// MFMA k-step 4t + j takes element j.  Steps whose columns are all >= d are
-// skipped (their direction operand is zero).  Columns >= d of a row read the
-// next row's first elements, which A64's zero columns cancel; the buffer
-// range check is per dword, so a load straddling the end of X returns its
-// in-range elements and zeros.  The batch's four weights come with it.
-template <int T>
-__device__ __forceinline__ void spread_load(f32x4 (&xv)[T], float (&wv)[4],
-                                            __amdgpu_buffer_rsrc_t xs, __amdgpu_buffer_rsrc_t ws,
-                                            int n0, int d, int c, int r) {
+// split_points_kernel: one thread per (tile, k-block, lane); rows >= N and
+// columns >= d are zero.
+__global__ __launch_bounds__(kBlock) void split_points_kernel(
+    const float* __restrict__ Z, int64_t N, int d, float scale, int KB, int64_t ntiles,
+    u32x4* __restrict__ tiles) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id >= ntiles * KB * 64) return;
+    const int lane = (int)(id & 63);
+    const int64_t rest = id >> 6;
+    const int kb = (int)(rest % KB);
+    const int64_t t = rest / KB;
+    const int64_t row = 16 * t + (lane & 15);
+    const int col0 = 32 * kb + 8 * (lane >> 4);
+    h8 hi, lo;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) wv[i] = buffer_load_f32(ws, (n0 + 4 * r + i) * 4);
-    const int base = ((n0 + c) * d + 4 * r) * 4;
-#pragma unroll
-    for (int t = 0; t < T; ++t) xv[t] = buffer_load_f32x4(xs, base + 64 * t);
+    for (int e = 0; e < 8; ++e) {
+        const int col = col0 + e;
+        const float v = (row < N && col < d) ? Z[row * d + col] * scale : 0.f;
+        const _Float16 h = (_Float16)v;
+        hi[e] = h;
+        lo[e] = (_Float16)(v - (float)h);
+    }
+    const int64_t base = (t * KB + kb) * 2 * 64 + lane;   // in 16-byte units
+    tiles[base] = __builtin_bit_cast(u32x4, hi);
+    tiles[base + 64] = __builtin_bit_cast(u32x4, lo);
 }
 
-template <int T>
-__device__ __forceinline__ void spread_load_dirs(f32x4 (&dv)[T], const float* __restrict__ A64,
-                                                 int p, int r) {
-    const f32x4* __restrict__ src = reinterpret_cast<const f32x4*>(A64 + (int64_t)p * kA64Cols) + r;
+// operand of one tile: hi and lo parts of each k-block
+template <int KB>
+struct SplitOp {
+    h8 hi[KB], lo[KB];
+};
+
+template <int KB>
+__device__ __forceinline__ void load_split(SplitOp<KB>& op, __amdgpu_buffer_rsrc_t rs,
+                                           int64_t tile_rel, int lane) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) dv[t] = src[4 * t];
+    for (int kb = 0; kb < KB; ++kb) {
+        const int off = (int)(((tile_rel * KB + kb) * 2) * kSplitTileBytes) + 16 * lane;
+        op.hi[kb] = buffer_load_h8(rs, off);
+        op.lo[kb] = buffer_load_h8(rs, off + kSplitTileBytes);
+    }
 }
 
-// C[point][dir]: lane (c, r) receives points 4r .. 4r+3 of direction c
-template <int T>
-__device__ __forceinline__ f32x4 spread_project(const f32x4 (&xv)[T], const f32x4 (&dv)[T], int d) {
-    f32x4 pr = f32x4{0.f, 0.f, 0.f, 0.f};
+template <int KB>
+__device__ __forceinline__ void load_split(SplitOp<KB>& op, const uint16_t* __restrict__ tiles,
+                                           int64_t tile, int lane) {
+    const h8* __restrict__ src = reinterpret_cast<const h8*>(tiles);
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int kb = 0; kb < KB; ++kb) {
+        const int64_t base = (tile * KB + kb) * 2 * 64 + lane;
+        op.hi[kb] = src[base];
+        op.lo[kb] = src[base + 64];
+    }
+}
+
+// C += A B^T over the tile's columns: the two small cross terms first
+template <int KB>
+__device__ __forceinline__ f32x4 split_mfma(const SplitOp<KB>& a, const SplitOp<KB>& b, f32x4 acc) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (t < T - 1 || 16 * t + j < d)
-                pr = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[t][j], dv[t][j], pr, 0, 0, 0);
-    return pr;
+    for (int kb = 0; kb < KB; ++kb) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi[kb], b.lo[kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo[kb], b.hi[kb], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi[kb], b.hi[kb], acc, 0, 0, 0);
+    return acc;
 }
 
 // Spread with projections computed in registers.  Workgroup (x, y) owns the
 // 16 directions 16x .. 16x+15 and the sources of chunk y; grids are
 // kFuseDirs x nr int32 cells in LDS (fixed point per slice as in
 // spread_tile) flushed after every slice into per-thread FP32 accumulators.
-template <int W, int T>
+// v = <xi_p, x_n / R>; x~ = pscale v with pscale = tau R; |v| <= vbound.
+template <int W, int KB>
 __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
-    const float* __restrict__ X, int64_t N, int d, const float* __restrict__ A64,
-    const float* __restrict__ w, int P, GridGeom g, int64_t chunk_len,
+    const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
+    const float* __restrict__ w, int P, GridGeom g, float pscale, int64_t chunk_len,
     const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial,
-    float bound, int* __restrict__ flag) {
+    float vbound, int* __restrict__ flag) {
     extern __shared__ int cells[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
     const int p0 = blockIdx.x * kFuseDirs;
     const int ncell = kFuseDirs * g.nr;
-    f32x4 dv[T];
-    spread_load_dirs<T>(dv, A64, p0 + c, r);
+    SplitOp<KB> dop;
+    load_split<KB>(dop, At, blockIdx.x, lane);
     float acc[kFuseAcc];
 #pragma unroll
     for (int q = 0; q < kFuseAcc; ++q) acc[q] = 0.f;
     for (int j = tid; j < ncell; j += kSpreadBlock) cells[j] = 0;
     __syncthreads();
     int* gcol = cells + c * g.nr;                     // grid of direction p0 + c
-    const WinEval<W> ev(g, win);
+    const WinEval<W> ev(g, win, pscale);
     const int64_t i0 = (int64_t)blockIdx.y * chunk_len;   // multiple of kSlice
     const int len = (int)min(N - i0, chunk_len);           // <= 2^20 sources
-    // the chunk's rows and the next one (a 16-byte operand load of the
-    // chunk's last row reaches into it); every other row reads as zero
-    const int xrows = (int)min(N - i0, (int64_t)len + 1);
-    const __amdgpu_buffer_rsrc_t xs = buffer_rsrc(X + i0 * d, (int64_t)xrows * d * 4);
+    // the chunk's tiles and a few beyond (prefetch), within the tile array;
+    // the weights of the chunk only, so sources past it spread nothing
+    const int64_t t0 = i0 / 16;
+    const int64_t ntiles = (N + 15) / 16;
+    const int64_t trange = min(ntiles - t0, (int64_t)(len + 15) / 16 + 2 * kSpreadWaves);
+    const __amdgpu_buffer_rsrc_t xs =
+        buffer_rsrc(Xt + t0 * KB * 2 * (kSplitTileBytes / 2), trange * KB * 2 * kSplitTileBytes);
     const __amdgpu_buffer_rsrc_t ws = buffer_rsrc(w + i0, (int64_t)len * 4);
     bool bad = false;
     // projects one batch of 16 sources on the 16 directions and spreads it
-    auto batch = [&](const f32x4 (&xv)[T], const float (&wv)[4], float scale) {
-        const f32x4 pr = spread_project<T>(xv, dv, d);   // points 4r + i, direction c
+    auto batch = [&](const SplitOp<KB>& xo, const float (&wv)[4], float scale) {
+        // C[point][dir]: lane holds points 4r + i of direction c
+        const f32x4 pr = split_mfma<KB>(xo, dop, f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            bad |= !(fabsf(pr[i]) <= bound);
+            bad |= !(fabsf(pr[i]) <= vbound);
             spread_point<W>(pr[i], wv[i] * scale, ev, win, gcol);
         }
+    };
+    auto load = [&](SplitOp<KB>& xo, float (&wv)[4], int n0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wv[i] = buffer_load_f32(ws, (n0 + 4 * r + i) * 4);
+        load_split<KB>(xo, xs, n0 / 16, lane);
     };
     for (int s0 = 0; s0 < len; s0 += kSlice) {
         const int k = slice_exponent(slice_max[(i0 + s0) / kSlice]);
@@ -1049,16 +1106,16 @@ __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
         // spread the other's operands load.  Each buffer is reloaded only
         // after its batch is done, so loads land in place (no copies that
         // would wait on them).  The last loads of a slice fetch the next
-        // slice's first rows, harmlessly (loaded again at its start).
+        // slice's first tiles, harmlessly (loaded again at its start).
         constexpr int stride = kSpreadWaves * 16;
         int n0 = s0 + wave * 16;
-        f32x4 xa[T], xb[T];
+        SplitOp<KB> xa, xb;
         float wa[4], wb[4];
-        spread_load<T>(xa, wa, xs, ws, n0, d, c, r);
+        load(xa, wa, n0);
         for (; n0 < s1; n0 += 2 * stride) {
-            spread_load<T>(xb, wb, xs, ws, n0 + stride, d, c, r);
+            load(xb, wb, n0 + stride);
             batch(xa, wa, scale);
-            spread_load<T>(xa, wa, xs, ws, n0 + 2 * stride, d, c, r);
+            load(xa, wa, n0 + 2 * stride);
             if (n0 + stride < s1) batch(xb, wb, scale);
         }
         __syncthreads();
@@ -1084,28 +1141,6 @@ __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
     if (bad) atomicOr(flag, 1);
 }
 
-// Gather operands (loaded once per workgroup): lane (c, r) supplies element
-// [c][4s + r] of k-step s from the rows of a buffer of row length d.  Rows
-// past the buffer read as zero; columns k >= d read a neighbouring element,
-// which the zero columns of A64 cancel.
-template <int KS>
-__device__ __forceinline__ void fused_load_points(float (&op)[KS], __amdgpu_buffer_rsrc_t rs,
-                                                  int row, int d, int r) {
-    const int base = (row * d + r) * 4;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) op[s] = buffer_load_f32(rs, base + 16 * s);
-}
-
-// A64 rows are zero-padded to 64 columns and to a multiple of 64 rows, so
-// every direction operand load is in bounds and needs no guard.
-template <int KS>
-__device__ __forceinline__ void fused_load_dirs(float (&op)[KS], const float* __restrict__ A64,
-                                                int p, int r) {
-    const float* __restrict__ src = A64 + (int64_t)p * kA64Cols + r;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) op[s] = src[4 * s];
-}
-
 // Copies the grids of directions p0 .. p0+np-1 (contiguous, np * nr floats)
 // into LDS with 16-byte LDS-direct loads, 1 KB per wave instruction.  Lanes
 // past the end re-read the group's first bytes (in bounds) and write into
@@ -1129,56 +1164,67 @@ __device__ __forceinline__ void gather_stage(const float* __restrict__ grid, int
 // is interpolated; lane (c, r) holds directions 4r .. 4r+3 of target c of
 // each batch.  Per target the four directions are summed in FP32, the
 // groups in FP64.
-template <int W, int KS>
+template <int W, int KB>
 __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
-    const float* __restrict__ Y, int64_t M, int d, const float* __restrict__ A64, int P,
-    GridGeom g, const float* __restrict__ grid, int prange, int stage, WindowArgs win,
-    double* __restrict__ spart, int64_t ldm, float bound, int* __restrict__ flag) {
+    const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At, int P,
+    GridGeom g, float pscale, const float* __restrict__ grid, int prange, int stage,
+    WindowArgs win, double* __restrict__ spart, int64_t ldm, float vbound,
+    int* __restrict__ flag) {
     extern __shared__ float gls[];                    // 2 x stage floats
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
     const int64_t mb = (int64_t)blockIdx.x * kGatherTargets;
-    const int mw = wave * (kGatherNB * 16);           // wave's first target in the tile
+    const int64_t tw = (mb + wave * (kGatherNB * 16)) / 16;   // wave's first target tile
     const int p_begin = blockIdx.y * prange;
     const int p_end = min(P, p_begin + prange);
     gather_stage(grid, p_begin, min(kFuseDirs, p_end - p_begin), g.nr, gls, wave, lane);
+    // target tiles past the last one read as zero
+    const int64_t ntiles = (M + 15) / 16;
     const __amdgpu_buffer_rsrc_t ys =
-        buffer_rsrc(Y + mb * d, min((int64_t)kGatherTargets, M - mb) * d * 4);
-    float yop[kGatherNB][KS];
+        buffer_rsrc(Yt + tw * KB * 2 * (kSplitTileBytes / 2),
+                    max((int64_t)0, min((int64_t)kGatherNB, ntiles - tw)) * KB * 2 * kSplitTileBytes);
+    SplitOp<KB> yop[kGatherNB];
 #pragma unroll
-    for (int b = 0; b < kGatherNB; ++b) fused_load_points<KS>(yop[b], ys, mw + 16 * b + c, d, r);
+    for (int b = 0; b < kGatherNB; ++b) load_split<KB>(yop[b], ys, b, lane);
     double accd[kGatherNB];
 #pragma unroll
     for (int b = 0; b < kGatherNB; ++b) accd[b] = 0.0;
-    const WinEval<W> ev(g, win);
+    const WinEval<W> ev(g, win, pscale);
     bool bad = false;
-    // interpolates the targets on the group of directions p0 .. p0+np-1
-    // whose grids are in gb and whose operand is dop
-    // Branch-free: a direction past np (ragged last group) reads direction
-    // 0's grid and contributes zero.  The projections of all batches are
-    // computed first, k-step by k-step across the batches: the kGatherNB
-    // accumulations are independent, so each MFMA issues while the previous
-    // ones are still in the pipeline.
-    auto group = [&](int np, const float* gb, const float (&dop)[KS]) {
+    // Projections of all batches on one group, k-block by k-block across
+    // the batches (independent accumulations), then the interpolation.
+    // Branch-free: a direction past np (ragged last group) interpolates
+    // whatever its LDS row holds and the result is masked to zero by bits
+    // (a select here would be turned into a branch around the LDS reads).
+    auto group = [&](int np, const float* gb, const SplitOp<KB>& dop) {
         f32x4 pr[kGatherNB];
 #pragma unroll
         for (int b = 0; b < kGatherNB; ++b) pr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
             for (int b = 0; b < kGatherNB; ++b)
-                // C[dir][target]: lane holds directions p0 + 4r + i of target c
-                pr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(dop[s], yop[b][s], pr[b], 0, 0, 0);
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.hi[kb], yop[b].lo[kb], pr[b], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < kGatherNB; ++b)
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.lo[kb], yop[b].hi[kb], pr[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int b = 0; b < kGatherNB; ++b)
+                // C[dir][target]: lane holds directions 4r + i of target c
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.hi[kb], yop[b].hi[kb], pr[b], 0, 0, 0);
 #pragma unroll
         for (int b = 0; b < kGatherNB; ++b) {
             float t = 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int dir = 4 * r + i;
-                const bool ok = dir < np;
-                const float v = interp<W>(pr[b][i], gb + (ok ? dir : 0) * g.nr, ev, win);
-                bad |= ok && !(fabsf(pr[b][i]) <= bound);
-                t += ok ? v : 0.f;
+                const float v = interp<W>(pr[b][i], gb + dir * g.nr, ev, win);
+                const unsigned keep = 0u - (unsigned)(dir < np);
+                bad |= (dir < np) & !(fabsf(pr[b][i]) <= vbound);
+                t += __uint_as_float(__float_as_uint(v) & keep);
             }
             accd[b] += (double)t;
         }
@@ -1188,8 +1234,8 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
     // group is interpolated.  Before a group starts, this wave's fetches have
     // landed (vmcnt) and, after the barrier, every wave's have and no wave
     // still reads the buffer about to be refilled.
-    float da[KS], db[KS];
-    fused_load_dirs<KS>(da, A64, p_begin + c, r);
+    SplitOp<KB> da, db;
+    load_split<KB>(da, At, p_begin / kFuseDirs, lane);
     float* buf0 = gls;
     float* buf1 = gls + stage;
     for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
@@ -1198,7 +1244,7 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
         const int p1 = p0 + kFuseDirs;
         if (p1 < p_end) {
             gather_stage(grid, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
-            fused_load_dirs<KS>(db, A64, p1 + c, r);
+            load_split<KB>(db, At, p1 / kFuseDirs, lane);
         }
         group(min(kFuseDirs, p_end - p0), buf0, da);
         if (p1 >= p_end) break;
@@ -1207,7 +1253,7 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
         const int p2 = p1 + kFuseDirs;
         if (p2 < p_end) {
             gather_stage(grid, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
-            fused_load_dirs<KS>(da, A64, p2 + c, r);
+            load_split<KB>(da, At, p2 / kFuseDirs, lane);
         }
         group(min(kFuseDirs, p_end - p1), buf1, db);
     }
@@ -1217,47 +1263,58 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
         double v = accd[b];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
-        const int64_t m = mb + mw + 16 * b + c;
+        const int64_t m = mb + wave * (kGatherNB * 16) + 16 * b + c;
         if (r == 0 && m < M) spart[(int64_t)blockIdx.y * ldm + m] = v;
     }
     if (bad) atomicOr(flag, 1);
 }
 
-template <int W, int T>
-void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const float* X, int64_t N,
-                           int d, const float* A64, const float* w, int P, const GridGeom& g,
-                           int64_t chunk_len, const float* slice_max, const WindowArgs& win,
-                           float* partial, float bound, int* flag) {
-    hipLaunchKernelGGL((spread_fused_kernel<W, T>), grid, dim3(kSpreadBlock), lds, stream, X, N,
-                       d, A64, w, P, g, chunk_len, slice_max, win, partial, bound, flag);
+template <int W, int KB>
+void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Xt,
+                           int64_t N, const uint16_t* At, const float* w, int P,
+                           const GridGeom& g, float pscale, int64_t chunk_len,
+                           const float* slice_max, const WindowArgs& win, float* partial,
+                           float vbound, int* flag) {
+    hipLaunchKernelGGL((spread_fused_kernel<W, KB>), grid, dim3(kSpreadBlock), lds, stream, Xt, N,
+                       At, w, P, g, pscale, chunk_len, slice_max, win, partial, vbound, flag);
 }
 
-template <int W, int KS>
-void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const float* Y, int64_t M,
-                           int d, const float* A64, int P, const GridGeom& g, const float* gridv,
-                           int prange, int stage, const WindowArgs& win, double* spart,
-                           int64_t ldm, float bound, int* flag) {
+template <int W, int KB>
+void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Yt,
+                           int64_t M, const uint16_t* At, int P, const GridGeom& g, float pscale,
+                           const float* gridv, int prange, int stage, const WindowArgs& win,
+                           double* spart, int64_t ldm, float vbound, int* flag) {
     static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_fused_kernel<W, KS>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_fused_kernel<W, KB>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   2 * kFuseMaxCells * (int)sizeof(float));
         attr_set = true;
     }
-    hipLaunchKernelGGL((gather_fused_kernel<W, KS>), grid, dim3(kGatherBlock), lds, stream, Y, M,
-                       d, A64, P, g, gridv, prange, stage, win, spart, ldm, bound, flag);
+    hipLaunchKernelGGL((gather_fused_kernel<W, KB>), grid, dim3(kGatherBlock), lds, stream, Yt,
+                       M, At, P, g, pscale, gridv, prange, stage, win, spart, ldm, vbound, flag);
 }
 
-#define FS_T_TABLE(F, W) {F<W, 1>, F<W, 2>, F<W, 3>, F<W, 4>}
-#define FS_KS_TABLE(F, W)                                                                  \
-    {F<W, 1>, F<W, 2>, F<W, 3>, F<W, 4>, F<W, 5>, F<W, 6>, F<W, 7>, F<W, 8>, F<W, 9>,     \
-     F<W, 10>, F<W, 11>, F<W, 12>, F<W, 13>, F<W, 14>, F<W, 15>, F<W, 16>}
-
 bool fused_supported(int d, int nr) {
-    return d >= 1 && d <= kA64Cols && kFuseDirs * nr <= kFuseMaxCells;
+    return d >= 1 && d <= kSplitMaxD && kFuseDirs * nr <= kFuseMaxCells;
 }
 
 int64_t fused_gather_tile() { return kGatherTargets; }
+
+int64_t split_tiles_bytes(int64_t rows, int d) {
+    return (rows + 15) / 16 * split_kblocks(d) * 2 * kSplitTileBytes;
+}
+
+hipError_t launch_split_points(const float* Z, int64_t N, int d, float scale, uint16_t* tiles,
+                               hipStream_t stream) {
+    const int KB = split_kblocks(d);
+    const int64_t ntiles = (N + 15) / 16;
+    const int64_t threads = ntiles * KB * 64;
+    hipLaunchKernelGGL(split_points_kernel, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, stream, Z, N, d, scale, KB, ntiles,
+                       reinterpret_cast<u32x4*>(tiles));
+    return hipGetLastError();
+}
 
 void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_blocks) {
     *spread_blocks = 1;
@@ -1265,15 +1322,12 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
     if (!fused_supported(d, nr)) return;
     const void* sk = nullptr;
     const void* gk = nullptr;
-    const int T = (d + 15) / 16, KS = (d + 3) / 4;
-    // occupancy is set by LDS and registers, which T and KS barely move:
-    // take the largest operand shapes as representative
-    (void)T;
-    (void)KS;
+    // occupancy is set by LDS and registers; the larger operand shape
+    // stands for both
     switch (W) {
-        case 4: sk = (const void*)&spread_fused_kernel<4, 4>; gk = (const void*)&gather_fused_kernel<4, 16>; break;
-        case 6: sk = (const void*)&spread_fused_kernel<6, 4>; gk = (const void*)&gather_fused_kernel<6, 16>; break;
-        default: sk = (const void*)&spread_fused_kernel<8, 4>; gk = (const void*)&gather_fused_kernel<8, 16>; break;
+        case 4: sk = (const void*)&spread_fused_kernel<4, 2>; gk = (const void*)&gather_fused_kernel<4, 2>; break;
+        case 6: sk = (const void*)&spread_fused_kernel<6, 2>; gk = (const void*)&gather_fused_kernel<6, 2>; break;
+        default: sk = (const void*)&spread_fused_kernel<8, 2>; gk = (const void*)&gather_fused_kernel<8, 2>; break;
     }
     const int stage = (kFuseDirs * nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
     (void)hipFuncSetAttribute(gk, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1287,50 +1341,49 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
         *gather_blocks = b;
 }
 
-hipError_t launch_spread_fused(int W, const float* X, int64_t N, int d, const float* A64,
-                               const float* w, int P, GridGeom g, int nchunk, int64_t chunk_len,
-                               float* slice_max, const WindowArgs& win, float* partial,
-                               float bound, int* flag, hipStream_t stream) {
+hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, const uint16_t* At,
+                               const float* w, int P, GridGeom g, float pscale, int nchunk,
+                               int64_t chunk_len, float* slice_max, const WindowArgs& win,
+                               float* partial, float vbound, int* flag, hipStream_t stream) {
     if (!fused_supported(d, g.nr) || chunk_len % kSlice != 0) return hipErrorInvalidValue;
-    using L = void (*)(dim3, size_t, hipStream_t, const float*, int64_t, int, const float*,
-                       const float*, int, const GridGeom&, int64_t, const float*,
+    using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*,
+                       const float*, int, const GridGeom&, float, int64_t, const float*,
                        const WindowArgs&, float*, float, int*);
-    static const L t4[4] = FS_T_TABLE(launch_spread_fused_t, 4);
-    static const L t6[4] = FS_T_TABLE(launch_spread_fused_t, 6);
-    static const L t8[4] = FS_T_TABLE(launch_spread_fused_t, 8);
-    const L* t = W == 4 ? t4 : W == 6 ? t6 : W == 8 ? t8 : nullptr;
-    if (!t) return hipErrorInvalidValue;
+    static const L t[3][2] = {{launch_spread_fused_t<4, 1>, launch_spread_fused_t<4, 2>},
+                              {launch_spread_fused_t<6, 1>, launch_spread_fused_t<6, 2>},
+                              {launch_spread_fused_t<8, 1>, launch_spread_fused_t<8, 2>}};
+    const int wi = W == 4 ? 0 : W == 6 ? 1 : W == 8 ? 2 : -1;
+    if (wi < 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(slice_max_kernel, dim3((unsigned)((N + kSlice - 1) / kSlice)), dim3(kBlock),
                        0, stream, w, N, slice_max);
     dim3 grid((unsigned)((P + kFuseDirs - 1) / kFuseDirs), (unsigned)nchunk);
-    t[(d + 15) / 16 - 1](grid, (size_t)kFuseDirs * g.nr * sizeof(int), stream, X, N, d, A64, w,
-                         P, g, chunk_len, slice_max, win, partial, bound, flag);
+    t[wi][split_kblocks(d) - 1](grid, (size_t)kFuseDirs * g.nr * sizeof(int), stream, Xt, N, At,
+                                w, P, g, pscale, chunk_len, slice_max, win, partial, vbound, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_fused(int W, const float* Y, int64_t M, int d, const float* A64,
-                               int P, GridGeom g, const float* grid, int prange,
-                               const WindowArgs& win, double* spart, int64_t ldm,
-                               float bound, int* flag, hipStream_t stream) {
+hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, const uint16_t* At,
+                               int P, GridGeom g, float pscale, const float* grid, int prange,
+                               const WindowArgs& win, double* spart, int64_t ldm, float vbound,
+                               int* flag, hipStream_t stream) {
     if (!fused_supported(d, g.nr) || prange % kFuseDirs != 0) return hipErrorInvalidValue;
-    using L = void (*)(dim3, size_t, hipStream_t, const float*, int64_t, int, const float*, int,
-                       const GridGeom&, const float*, int, int, const WindowArgs&, double*,
+    using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*, int,
+                       const GridGeom&, float, const float*, int, int, const WindowArgs&, double*,
                        int64_t, float, int*);
-    static const L t4[16] = FS_KS_TABLE(launch_gather_fused_t, 4);
-    static const L t6[16] = FS_KS_TABLE(launch_gather_fused_t, 6);
-    static const L t8[16] = FS_KS_TABLE(launch_gather_fused_t, 8);
-    const L* t = W == 4 ? t4 : W == 6 ? t6 : W == 8 ? t8 : nullptr;
-    if (!t) return hipErrorInvalidValue;
+    static const L t[3][2] = {{launch_gather_fused_t<4, 1>, launch_gather_fused_t<4, 2>},
+                              {launch_gather_fused_t<6, 1>, launch_gather_fused_t<6, 2>},
+                              {launch_gather_fused_t<8, 1>, launch_gather_fused_t<8, 2>}};
+    const int wi = W == 4 ? 0 : W == 6 ? 1 : W == 8 ? 2 : -1;
+    if (wi < 0) return hipErrorInvalidValue;
     // one staging buffer: the group's grids rounded up to whole 1 KB pieces
     const int stage = (kFuseDirs * g.nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
     dim3 gd((unsigned)((M + kGatherTargets - 1) / kGatherTargets),
             (unsigned)((P + prange - 1) / prange));
-    t[(d + 3) / 4 - 1](gd, (size_t)2 * stage * sizeof(float), stream, Y, M, d, A64, P, g, grid,
-                       prange, stage, win, spart, ldm, bound, flag);
+    t[wi][split_kblocks(d) - 1](gd, (size_t)2 * stage * sizeof(float), stream, Yt, M, At, P, g,
+                                pscale, grid, prange, stage, win, spart, ldm, vbound, flag);
     return hipGetLastError();
 }
-#undef FS_KS_TABLE
-#undef FS_T_TABLE
+
 
 
 // ---------------------------------------------------------------------------

@@ -332,6 +332,28 @@ int gather_group(int64_t M, int P, int pstage) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Split-f16 tiles of the directions (rows p = xi[:, p], d x P row-major on
+// the host), layout as the device's split_points_kernel; directions past P
+// and coordinates past d are zero.
+void split_dirs_host(const float* xi, int d, int P, std::vector<uint16_t>& out) {
+    const int KB = split_kblocks(d);
+    const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
+    out.assign((size_t)(groups * KB * 2 * kSplitTileBytes / 2), 0);
+    for (int64_t t = 0; t < groups; ++t)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t p = 16 * t + (lane & 15);
+                    const int i = 32 * kb + 8 * (lane >> 4) + e;
+                    const float v = (p < P && i < d) ? xi[(size_t)i * P + p] : 0.f;
+                    const _Float16 hi = (_Float16)v;
+                    const _Float16 lo = (_Float16)(v - (float)hi);
+                    const size_t base = (size_t)((t * KB + kb) * 2) * (kSplitTileBytes / 2) + 8 * lane + e;
+                    std::memcpy(&out[base], &hi, 2);
+                    std::memcpy(&out[base + kSplitTileBytes / 2], &lo, 2);
+                }
+}
+
 fastsum_status status_of(hipError_t e) {
     if (e == hipSuccess) return FASTSUM_OK;
     if (e == hipErrorOutOfMemory) return FASTSUM_ENOMEM;
@@ -363,6 +385,9 @@ struct fastsum_plan_s {
     // device buffers
     float* A = nullptr;            // tau * Xi^T, P x dpad
     float* A64 = nullptr;          // the same, zero-padded to round_up(P, 64) x 64 (d <= 64)
+    uint16_t* at = nullptr;        // split-f16 tiles of the directions (fused plans)
+    uint16_t* xt = nullptr;        // split-f16 tiles of the sources / targets (fused plans)
+    uint16_t* yt = nullptr;
     uint16_t* A16 = nullptr;       // BF16 copy
     float* xproj = nullptr;
     float* yproj = nullptr;
@@ -398,7 +423,7 @@ void free_plan(fastsum_plan_s* p) {
     if (!p) return;
     for (auto& r : p->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    void* bufs[] = {p->A, p->A64, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
+    void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max};
     for (void* b : bufs)
@@ -491,18 +516,33 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
     return FASTSUM_OK;
 }
 
-// Fused path: projections are computed inside the spreading and gathering
-// kernels (d <= 64, FP32).  spread(x, w) -> fftconv -> gather(y) -> reduce.
+// Fused path (d <= 64): the points are split into f16 operand tiles
+// (scaled by 1/R), then the projections tau R <xi, x / R> are computed inside
+// the spreading and gathering kernels.
+//   split(x), split(y) -> spread(x, w) -> fftconv -> gather(y) -> reduce
 fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, int64_t N,
                           const float* y, int64_t M, float* out, hipStream_t st) {
     const int P = pl->P;
+    const double tauR = pl->r.tau * pl->r.p.R;
+    const float pscale = (float)tauR;
+    const float vbound = (float)(pl->bound / tauR);
+    const float inv_r = (float)(1.0 / pl->r.p.R);
+    const uint16_t* yt = pl->xt;
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
+        FS_TRY(launch_split_points(x, N, pl->d, inv_r, pl->xt, st));
+        if (y != x) {
+            FS_TRY(launch_split_points(y, M, pl->d, inv_r, pl->yt, st));
+            yt = pl->yt;
+        }
+    }
     int64_t chunk_len = 0;
     const int nchunk = chunk_plan(pl, N, fused_chunks(N, P, pl->spread_slots), chunk_len);
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
-        FS_TRY(launch_spread_fused(pl->W, x, N, pl->d, pl->A64, w, P, pl->geom, nchunk,
-                                   chunk_len, pl->slice_max, pl->win_args, pl->partial,
-                                   pl->bound, pl->flag, st));
+        FS_TRY(launch_spread_fused(pl->W, pl->xt, N, pl->d, pl->at, w, P, pl->geom, pscale, nchunk,
+                                   chunk_len, pl->slice_max, pl->win_args, pl->partial, vbound,
+                                   pl->flag, st));
     }
     {
         PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
@@ -516,8 +556,9 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
     pl->last_ngroup = nrange;
     {
         PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
-        FS_TRY(launch_gather_fused(pl->W, y, M, pl->d, pl->A64, P, pl->geom, pl->grid, prange,
-                                   pl->win_args, pl->spart, pl->ldm, pl->bound, pl->flag, st));
+        FS_TRY(launch_gather_fused(pl->W, yt, M, pl->d, pl->at, P, pl->geom, pscale, pl->grid,
+                                   prange, pl->win_args, pl->spart, pl->ldm, vbound, pl->flag,
+                                   st));
     }
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
     FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, st));
@@ -625,10 +666,15 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
                                            kFusedMaxChunks, (cap + kMaxChunk - 1) / kMaxChunk));
     }
 
+    // fused plans store no projections; they keep split operand tiles
+    const int64_t gtiles = (P + kFuseDirs - 1) / kFuseDirs;
     bool ok = dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
               dev_alloc(&pl->A16, (size_t)P * pl->dpad) &&
-              dev_alloc(&pl->xproj, (size_t)P * pl->ld_x) &&
-              dev_alloc(&pl->yproj, (size_t)P * pl->ld_y) &&
+              (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
+                               dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&
+                               dev_alloc(&pl->at, (size_t)split_tiles_bytes(gtiles * kFuseDirs, pl->d) / 2)
+                         : dev_alloc(&pl->xproj, (size_t)P * pl->ld_x) &&
+                               dev_alloc(&pl->yproj, (size_t)P * pl->ld_y)) &&
               dev_alloc(&pl->partial, (size_t)pl->nchunk_cap * P * nr) &&
               dev_alloc(&pl->grid, (size_t)P * nr) &&
               dev_alloc(&pl->spart, (size_t)pl->ngroup_cap * pl->ldm) &&
@@ -658,7 +704,11 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         for (int p = 0; p < P; ++p)
             for (int i = 0; i < pl->d; ++i) A64[(size_t)p * kA64Cols + i] = A[(size_t)p * pl->dpad + i];
     }
+    std::vector<uint16_t> at;
+    if (pl->at) split_dirs_host(xi, pl->d, P, at);
     hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->at)
+        e = hipMemcpyAsync(pl->at, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->A64)
         e = hipMemcpyAsync(pl->A64, A64.data(), A64.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->A16, A16.data(), A16.size() * 2, hipMemcpyHostToDevice, hs);
