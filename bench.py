@@ -1,10 +1,12 @@
 #!/usr/bin/env python
 """Throughput of QMC-slicing fast kernel summation on one MI355X.
 
-One step = one full pass of the summation path (projection of sources and
-targets, window spreading, FFT convolution, window gather with the FP64
-reduction over directions) on the d=50, N=M=60000, N_ft=1024 Gaussian-mixture
-workload with signed weights, inputs resident in HBM.  P is the smallest
+One step = one full pass of the summation path on the d=50, N=M=60000,
+N_ft=1024 Gaussian-mixture workload with signed weights, inputs resident in
+HBM: split of sources and targets into f16 operand tiles, spreading with the
+source projections computed on the matrix cores, FFT convolution, gather
+with the target projections computed on the matrix cores and the FP64
+reduction over directions.  P is the smallest
 number of distance-QMC directions in a fixed ladder whose result is within
 1e-3 rel-L2 of the FP64 direct sum on 1000 seeded targets (the same direct
 sum, timed on the host, is the CPU baseline); the nominal P = 1000 point is
@@ -30,7 +32,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "N·M/s at 1e-3 rel err vs FP64 direct; plain FP32 vs BF16/batched; HBM %peak"
-PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TFs": 157.3, "bf16_mfma_TFs": 2500.0}
+# MI355X published peaks; fp32_valu is the non-packed FP32 vector rate
+# (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz): the kernels are built
+# without packed FP32 instructions
+PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TFs": 157.3, "f16_mfma_TFs": 2500.0,
+        "bf16_mfma_TFs": 2500.0, "fp32_valu_TFs": 78.6}
+# window work per (point, direction) with W = 4 and the degree-4 window
+# polynomials (even part 3 coefficients, odd part 2) counted as flops (an FMA
+# is 2): position 2, sp^2 1, per tap pair 2x2 (even Horner) + 1x2 (odd
+# Horner) + 2x2 (the two taps); spreading adds the W weight products, the
+# gather W interpolation FMAs
+WINDOW_FLOPS = {"spread": 2 + 1 + 2 * (4 + 2 + 4) + 4, "gather": 2 + 1 + 2 * (4 + 2 + 4) + 2 * 4}
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_01316_amd", "csrc", "kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -64,32 +76,51 @@ def timed_steps(fn, steps, warmup):
 
 
 def algorithmic(phase, info, N, M, d, P, proj):
-    """Bytes (and flops) one launch of a phase must move in this design,
-    inputs and outputs counted once.  A fused plan (d <= 64) computes the
-    projections inside spread and gather: those read the points (N x d,
-    M x d) and do the projection flops 2 N d P, 2 M d P instead of reading
-    stored P x N projections."""
+    """(bytes, flops, bound) that one launch of a phase must move or compute
+    in this design, inputs and outputs counted once.
+
+    Stored-projection plans: the projection is a GEMM (FP32 MFMA) writing
+    P x N projections that spread and gather read back (HBM bound).  Fused
+    plans (d <= 64): `project` only splits the points into f16 operand tiles
+    (HBM bound); spread and gather compute the projections on the matrix
+    cores (2 N d P, 2 M d P flops, reported beside) and are bound by the
+    vector ALU work of the window evaluation (WINDOW_FLOPS per point and
+    direction)."""
     nr = info["grid_nr"]
     fused = info.get("fused", 0) == 1
-    if phase == "project":         # average of the x and y launches
-        pts = (N + M) / 2.0
+    kb = -(-d // 32)
+    if phase == "project":
+        if fused:                  # split x and y: read f32, write hi/lo f16 tiles
+            tiles = lambda n: -(-n // 16) * kb * 2 * 1024
+            return N * d * 4 + M * d * 4 + tiles(N) + tiles(M), 0.0, "hbm"
+        pts = (N + M) / 2.0        # average of the x and y launches
         byts = pts * d * 4 + P * d * 4 + P * pts * 4
-        return byts, 2.0 * pts * d * P
+        return byts, 2.0 * pts * d * P, "mfma"
     if phase == "spread":
         out = info["last_spread_chunks"] * P * nr * 4
         if fused:
-            return N * d * 4 + N * 4 + P * d * 4 + out, 2.0 * N * d * P
-        return P * N * 4 + N * 4 + out, 0.0
+            return N * kb * 2048 / 16 + N * 4 + out, WINDOW_FLOPS["spread"] * N * P, "alu"
+        return P * N * 4 + N * 4 + out, 0.0, "hbm"
     if phase == "fftconv":
-        return info["last_spread_chunks"] * P * nr * 4 + P * nr * 4, 0.0
+        return info["last_spread_chunks"] * P * nr * 4 + P * nr * 4, 0.0, "hbm"
     if phase == "gather":
         out = info["last_gather_groups"] * M * 8
         if fused:
-            return M * d * 4 + P * d * 4 + P * nr * 4 + out, 2.0 * M * d * P
-        return P * M * 4 + P * nr * 4 + out, 0.0
+            return M * kb * 2048 / 16 + P * nr * 4 + out, WINDOW_FLOPS["gather"] * M * P, "alu"
+        return P * M * 4 + P * nr * 4 + out, 0.0, "hbm"
     if phase == "reduce":
-        return info["last_gather_groups"] * M * 8 + M * 4, 0.0
-    return 0.0, 0.0
+        return info["last_gather_groups"] * M * 8 + M * 4, 0.0, "hbm"
+    return 0.0, 0.0, "hbm"
+
+
+def roofline_of(bound, byts, flops, avg_s):
+    if bound == "mfma":
+        return dict(bound="mfma", achieved=flops / avg_s / 1e12, peak=PEAK["fp32_mfma_TFs"],
+                    unit="TFLOP/s")
+    if bound == "alu":
+        return dict(bound="alu", achieved=flops / avg_s / 1e12, peak=PEAK["fp32_valu_TFs"],
+                    unit="TFLOP/s")
+    return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
 
 
 def kernel_source_hash():
@@ -332,23 +363,27 @@ def main():
     dom = max((p for p in phases if phases[p][1] > 0), key=lambda p: phases[p][0])
     tot_ms, launches = phases[dom]
     avg_s = tot_ms / launches * 1e-3
-    byts, flops = algorithmic(dom, info, N, M, d, P, "fp32")
-    if flops > 0 and flops / byts > PEAK["fp32_mfma_TFs"] * 1e12 / (PEAK["hbm_GBs"] * 1e9):
-        roof = dict(bound="mfma", achieved=flops / avg_s / 1e12, peak=PEAK["fp32_mfma_TFs"],
-                    unit="TFLOP/s")
-    else:
-        roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
+    byts, flops, bound = algorithmic(dom, info, N, M, d, P, "fp32")
+    roof = roofline_of(bound, byts, flops, avg_s)
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["algorithmic_bytes_per_launch"] = byts
     roof["algorithmic_flops_per_launch"] = flops
     roof["traffic"] = measured_traffic(dom, P)
+    if info.get("fused", 0) == 1 and dom in ("spread", "gather"):
+        # the projections this kernel computes on the matrix cores
+        pf = 2.0 * (N if dom == "spread" else M) * d * P
+        roof["mfma_projection"] = dict(flops_per_launch=pf, achieved=pf / avg_s / 1e12,
+                                       unit="TFLOP/s", note="split-f16 operands, 3 f16 MFMAs "
+                                       "per FP32-equivalent product; f16 dense peak 2500")
     phase_report = {}
     for p, (t, c) in phases.items():
         if c:
-            b, fl = algorithmic(p, info, N, M, d, P, "fp32")
+            b, fl, bd = algorithmic(p, info, N, M, d, P, "fp32")
+            rl = roofline_of(bd, b, fl, t / c * 1e-3)
             phase_report[p] = dict(avg_us=t / c * 1e3, launches_per_step=c / args.steps,
+                                   bound=bd, frac=rl["achieved"] / rl["peak"],
                                    hbm_frac=(b / (t / c * 1e-3)) / (PEAK["hbm_GBs"] * 1e9))
 
     result = {
