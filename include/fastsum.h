@@ -181,8 +181,11 @@ FASTSUM_API fastsum_status fastsum_grad(fastsum_plan plan, const float* grad_s,
 
 /*
  * Synchronise the plan's last stream and report device-side conditions:
- * returns ERANGE if any projected point of an exec since the previous check
- * exceeded tau*R (results are then unreliable), OK otherwise; clears the flag.
+ * returns ERANGE if an exec since the previous check saw a point outside the
+ * plan's bound (results are then unreliable), OK otherwise; clears the flag.
+ * Plans that store projections test every projection against tau*R; fused
+ * plans test every point, |x| max_p|xi_p| <= R, which bounds all of its
+ * projections by tau*R (the slack is 1e-5 relative in both cases).
  */
 FASTSUM_API fastsum_status fastsum_check(fastsum_plan plan);
 

@@ -103,24 +103,25 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
 // bytes of the split tiles of `rows` rows of dimension d
 int64_t split_tiles_bytes(int64_t rows, int d);
 
-// tiles of Z * scale (Z: N x d row-major)
+// tiles of Z * scale (Z: N x d row-major); sets *flag if a row has
+// |Z_row * scale|^2 > norm2_max (or is not finite)
 hipError_t launch_split_points(const float* Z, int64_t N, int d, float scale, uint16_t* tiles,
-                               hipStream_t stream);
+                               float norm2_max, int* flag, hipStream_t stream);
 
 // As launch_spread, with the projections computed in the kernel from the
 // split tiles of the sources (Xt, scale 1/R) and of the directions (At):
-// x~ = pscale * <xi, x / R>, pscale = tau R.  Sets *flag if |x~| > pscale * vbound.
+// x~ = pscale * <xi, x / R>, pscale = tau R.
 hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, const uint16_t* At,
                                const float* w, int P, GridGeom g, float pscale, int nchunk,
                                int64_t chunk_len, float* slice_max, const WindowArgs& win,
-                               float* partial, float vbound, int* flag, hipStream_t stream);
+                               float* partial, hipStream_t stream);
 
 // spart[b*ldm + m] = sum over directions p of range b (prange per range, a
 // multiple of kFuseDirs) of the interpolated grid at tau <xi_p, y_m>, FP64.
 hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, const uint16_t* At,
                                int P, GridGeom g, float pscale, const float* grid, int prange,
-                               const WindowArgs& win, double* spart, int64_t ldm, float vbound,
-                               int* flag, hipStream_t stream);
+                               const WindowArgs& win, double* spart, int64_t ldm,
+                               hipStream_t stream);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

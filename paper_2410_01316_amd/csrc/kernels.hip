@@ -97,7 +97,9 @@ __device__ __forceinline__ int tap0(float xt, const WinEval<W>& ev, float& sp) {
     sp = __builtin_amdgcn_fractf(u) - 0.5f;
     int j;
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(j) : "v"(u));
-    return min(max(j - ev.off, 0), ev.maxb);
+    int b;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(b) : "v"(j - ev.off), "v"(ev.maxb));
+    return b;
 }
 
 // ---------------------------------------------------------------------------
@@ -977,31 +979,39 @@ __device__ __forceinline__ h8 buffer_load_h8(__amdgpu_buffer_rsrc_t rs, int byte
     return __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0));
 }
 
-// split_points_kernel: one thread per (tile, k-block, lane); rows >= N and
-// columns >= d are zero.
+// split_points_kernel: one thread per (tile, lane), all k-blocks; rows >= N
+// and columns >= d are zero.  Also the range check of the fused path: a
+// row with |z * scale|^2 > norm2_max sets *flag (z * scale is x / R, and
+// |<xi, x / R>| <= max|xi| |x| / R bounds every projection of the row).
 __global__ __launch_bounds__(kBlock) void split_points_kernel(
     const float* __restrict__ Z, int64_t N, int d, float scale, int KB, int64_t ntiles,
-    u32x4* __restrict__ tiles) {
+    u32x4* __restrict__ tiles, float norm2_max, int* __restrict__ flag) {
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (id >= ntiles * KB * 64) return;
+    if (id >= ntiles * 64) return;                    // whole waves
     const int lane = (int)(id & 63);
-    const int64_t rest = id >> 6;
-    const int kb = (int)(rest % KB);
-    const int64_t t = rest / KB;
+    const int64_t t = id >> 6;
     const int64_t row = 16 * t + (lane & 15);
-    const int col0 = 32 * kb + 8 * (lane >> 4);
-    h8 hi, lo;
+    float ss = 0.f;
+    for (int kb = 0; kb < KB; ++kb) {
+        const int col0 = 32 * kb + 8 * (lane >> 4);
+        h8 hi, lo;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int col = col0 + e;
-        const float v = (row < N && col < d) ? Z[row * d + col] * scale : 0.f;
-        const _Float16 h = (_Float16)v;
-        hi[e] = h;
-        lo[e] = (_Float16)(v - (float)h);
+        for (int e = 0; e < 8; ++e) {
+            const int col = col0 + e;
+            const float v = (row < N && col < d) ? Z[row * d + col] * scale : 0.f;
+            ss = fmaf(v, v, ss);
+            const _Float16 h = (_Float16)v;
+            hi[e] = h;
+            lo[e] = (_Float16)(v - (float)h);
+        }
+        const int64_t base = (t * KB + kb) * 2 * 64 + lane;   // in 16-byte units
+        tiles[base] = __builtin_bit_cast(u32x4, hi);
+        tiles[base + 64] = __builtin_bit_cast(u32x4, lo);
     }
-    const int64_t base = (t * KB + kb) * 2 * 64 + lane;   // in 16-byte units
-    tiles[base] = __builtin_bit_cast(u32x4, hi);
-    tiles[base + 64] = __builtin_bit_cast(u32x4, lo);
+    // the row's columns are spread over lanes c, c+16, c+32, c+48
+    ss += __shfl_xor(ss, 16);
+    ss += __shfl_xor(ss, 32);
+    if (!(ss <= norm2_max) && lane < 16) atomicOr(flag, 1);   // NaN also flags
 }
 
 // operand of one tile: hi and lo parts of each k-block
@@ -1051,13 +1061,13 @@ __device__ __forceinline__ f32x4 split_mfma(const SplitOp<KB>& a, const SplitOp<
 // 16 directions 16x .. 16x+15 and the sources of chunk y; grids are
 // kFuseDirs x nr int32 cells in LDS (fixed point per slice as in
 // spread_tile) flushed after every slice into per-thread FP32 accumulators.
-// v = <xi_p, x_n / R>; x~ = pscale v with pscale = tau R; |v| <= vbound.
+// v = <xi_p, x_n / R>; x~ = pscale v with pscale = tau R.  The range check
+// of these points was done when they were split.
 template <int W, int KB>
 __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
     const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
     const float* __restrict__ w, int P, GridGeom g, float pscale, int64_t chunk_len,
-    const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial,
-    float vbound, int* __restrict__ flag) {
+    const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial) {
     extern __shared__ int cells[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
@@ -1082,16 +1092,12 @@ __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
     const __amdgpu_buffer_rsrc_t xs =
         buffer_rsrc(Xt + t0 * KB * 2 * (kSplitTileBytes / 2), trange * KB * 2 * kSplitTileBytes);
     const __amdgpu_buffer_rsrc_t ws = buffer_rsrc(w + i0, (int64_t)len * 4);
-    bool bad = false;
     // projects one batch of 16 sources on the 16 directions and spreads it
     auto batch = [&](const SplitOp<KB>& xo, const float (&wv)[4], float scale) {
         // C[point][dir]: lane holds points 4r + i of direction c
         const f32x4 pr = split_mfma<KB>(xo, dop, f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            bad |= !(fabsf(pr[i]) <= vbound);
-            spread_point<W>(pr[i], wv[i] * scale, ev, win, gcol);
-        }
+        for (int i = 0; i < 4; ++i) spread_point<W>(pr[i], wv[i] * scale, ev, win, gcol);
     };
     auto load = [&](SplitOp<KB>& xo, float (&wv)[4], int n0) {
 #pragma unroll
@@ -1138,7 +1144,6 @@ __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
         const int j = tid + q * kSpreadBlock;
         if (j < nvalid) dst[j] = acc[q];
     }
-    if (bad) atomicOr(flag, 1);
 }
 
 // Copies the grids of directions p0 .. p0+np-1 (contiguous, np * nr floats)
@@ -1168,8 +1173,7 @@ template <int W, int KB>
 __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
     const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At, int P,
     GridGeom g, float pscale, const float* __restrict__ grid, int prange, int stage,
-    WindowArgs win, double* __restrict__ spart, int64_t ldm, float vbound,
-    int* __restrict__ flag) {
+    WindowArgs win, double* __restrict__ spart, int64_t ldm) {
     extern __shared__ float gls[];                    // 2 x stage floats
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
@@ -1190,7 +1194,6 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
 #pragma unroll
     for (int b = 0; b < kGatherNB; ++b) accd[b] = 0.0;
     const WinEval<W> ev(g, win, pscale);
-    bool bad = false;
     // Projections of all batches on one group, k-block by k-block across
     // the batches (independent accumulations), then the interpolation.
     // Branch-free: a direction past np (ragged last group) interpolates
@@ -1223,7 +1226,6 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
                 const int dir = 4 * r + i;
                 const float v = interp<W>(pr[b][i], gb + dir * g.nr, ev, win);
                 const unsigned keep = 0u - (unsigned)(dir < np);
-                bad |= (dir < np) & !(fabsf(pr[b][i]) <= vbound);
                 t += __uint_as_float(__float_as_uint(v) & keep);
             }
             accd[b] += (double)t;
@@ -1266,24 +1268,22 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
         const int64_t m = mb + wave * (kGatherNB * 16) + 16 * b + c;
         if (r == 0 && m < M) spart[(int64_t)blockIdx.y * ldm + m] = v;
     }
-    if (bad) atomicOr(flag, 1);
 }
 
 template <int W, int KB>
 void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Xt,
                            int64_t N, const uint16_t* At, const float* w, int P,
                            const GridGeom& g, float pscale, int64_t chunk_len,
-                           const float* slice_max, const WindowArgs& win, float* partial,
-                           float vbound, int* flag) {
+                           const float* slice_max, const WindowArgs& win, float* partial) {
     hipLaunchKernelGGL((spread_fused_kernel<W, KB>), grid, dim3(kSpreadBlock), lds, stream, Xt, N,
-                       At, w, P, g, pscale, chunk_len, slice_max, win, partial, vbound, flag);
+                       At, w, P, g, pscale, chunk_len, slice_max, win, partial);
 }
 
 template <int W, int KB>
 void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Yt,
                            int64_t M, const uint16_t* At, int P, const GridGeom& g, float pscale,
                            const float* gridv, int prange, int stage, const WindowArgs& win,
-                           double* spart, int64_t ldm, float vbound, int* flag) {
+                           double* spart, int64_t ldm) {
     static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
     if (!attr_set) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_fused_kernel<W, KB>),
@@ -1292,7 +1292,7 @@ void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint
         attr_set = true;
     }
     hipLaunchKernelGGL((gather_fused_kernel<W, KB>), grid, dim3(kGatherBlock), lds, stream, Yt,
-                       M, At, P, g, pscale, gridv, prange, stage, win, spart, ldm, vbound, flag);
+                       M, At, P, g, pscale, gridv, prange, stage, win, spart, ldm);
 }
 
 bool fused_supported(int d, int nr) {
@@ -1306,13 +1306,13 @@ int64_t split_tiles_bytes(int64_t rows, int d) {
 }
 
 hipError_t launch_split_points(const float* Z, int64_t N, int d, float scale, uint16_t* tiles,
-                               hipStream_t stream) {
+                               float norm2_max, int* flag, hipStream_t stream) {
     const int KB = split_kblocks(d);
     const int64_t ntiles = (N + 15) / 16;
-    const int64_t threads = ntiles * KB * 64;
+    const int64_t threads = ntiles * 64;
     hipLaunchKernelGGL(split_points_kernel, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, stream, Z, N, d, scale, KB, ntiles,
-                       reinterpret_cast<u32x4*>(tiles));
+                       reinterpret_cast<u32x4*>(tiles), norm2_max, flag);
     return hipGetLastError();
 }
 
@@ -1344,11 +1344,11 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
 hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, const uint16_t* At,
                                const float* w, int P, GridGeom g, float pscale, int nchunk,
                                int64_t chunk_len, float* slice_max, const WindowArgs& win,
-                               float* partial, float vbound, int* flag, hipStream_t stream) {
+                               float* partial, hipStream_t stream) {
     if (!fused_supported(d, g.nr) || chunk_len % kSlice != 0) return hipErrorInvalidValue;
     using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*,
                        const float*, int, const GridGeom&, float, int64_t, const float*,
-                       const WindowArgs&, float*, float, int*);
+                       const WindowArgs&, float*);
     static const L t[3][2] = {{launch_spread_fused_t<4, 1>, launch_spread_fused_t<4, 2>},
                               {launch_spread_fused_t<6, 1>, launch_spread_fused_t<6, 2>},
                               {launch_spread_fused_t<8, 1>, launch_spread_fused_t<8, 2>}};
@@ -1358,18 +1358,18 @@ hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, cons
                        0, stream, w, N, slice_max);
     dim3 grid((unsigned)((P + kFuseDirs - 1) / kFuseDirs), (unsigned)nchunk);
     t[wi][split_kblocks(d) - 1](grid, (size_t)kFuseDirs * g.nr * sizeof(int), stream, Xt, N, At,
-                                w, P, g, pscale, chunk_len, slice_max, win, partial, vbound, flag);
+                                w, P, g, pscale, chunk_len, slice_max, win, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, const uint16_t* At,
                                int P, GridGeom g, float pscale, const float* grid, int prange,
-                               const WindowArgs& win, double* spart, int64_t ldm, float vbound,
-                               int* flag, hipStream_t stream) {
+                               const WindowArgs& win, double* spart, int64_t ldm,
+                               hipStream_t stream) {
     if (!fused_supported(d, g.nr) || prange % kFuseDirs != 0) return hipErrorInvalidValue;
     using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*, int,
                        const GridGeom&, float, const float*, int, int, const WindowArgs&, double*,
-                       int64_t, float, int*);
+                       int64_t);
     static const L t[3][2] = {{launch_gather_fused_t<4, 1>, launch_gather_fused_t<4, 2>},
                               {launch_gather_fused_t<6, 1>, launch_gather_fused_t<6, 2>},
                               {launch_gather_fused_t<8, 1>, launch_gather_fused_t<8, 2>}};
@@ -1380,7 +1380,7 @@ hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, cons
     dim3 gd((unsigned)((M + kGatherTargets - 1) / kGatherTargets),
             (unsigned)((P + prange - 1) / prange));
     t[wi][split_kblocks(d) - 1](gd, (size_t)2 * stage * sizeof(float), stream, Yt, M, At, P, g,
-                                pscale, grid, prange, stage, win, spart, ldm, vbound, flag);
+                                pscale, grid, prange, stage, win, spart, ldm);
     return hipGetLastError();
 }
 

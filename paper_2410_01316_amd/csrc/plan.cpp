@@ -388,6 +388,7 @@ struct fastsum_plan_s {
     uint16_t* at = nullptr;        // split-f16 tiles of the directions (fused plans)
     uint16_t* xt = nullptr;        // split-f16 tiles of the sources / targets (fused plans)
     uint16_t* yt = nullptr;
+    double xi_norm_max = 1.0;      // max_p |xi_p| (range check of the fused path)
     uint16_t* A16 = nullptr;       // BF16 copy
     float* xproj = nullptr;
     float* yproj = nullptr;
@@ -525,14 +526,17 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
     const int P = pl->P;
     const double tauR = pl->r.tau * pl->r.p.R;
     const float pscale = (float)tauR;
-    const float vbound = (float)(pl->bound / tauR);
     const float inv_r = (float)(1.0 / pl->r.p.R);
+    // |x~| <= tau R for every direction when |x| max|xi| <= R (same slack as
+    // the stored path's check of each projection)
+    const double lim = (1.0 + 1e-5) / pl->xi_norm_max;
+    const float norm2_max = (float)(lim * lim);
     const uint16_t* yt = pl->xt;
     {
         PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
-        FS_TRY(launch_split_points(x, N, pl->d, inv_r, pl->xt, st));
+        FS_TRY(launch_split_points(x, N, pl->d, inv_r, pl->xt, norm2_max, pl->flag, st));
         if (y != x) {
-            FS_TRY(launch_split_points(y, M, pl->d, inv_r, pl->yt, st));
+            FS_TRY(launch_split_points(y, M, pl->d, inv_r, pl->yt, norm2_max, pl->flag, st));
             yt = pl->yt;
         }
     }
@@ -541,8 +545,7 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
         FS_TRY(launch_spread_fused(pl->W, pl->xt, N, pl->d, pl->at, w, P, pl->geom, pscale, nchunk,
-                                   chunk_len, pl->slice_max, pl->win_args, pl->partial, vbound,
-                                   pl->flag, st));
+                                   chunk_len, pl->slice_max, pl->win_args, pl->partial, st));
     }
     {
         PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
@@ -557,8 +560,7 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
     {
         PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
         FS_TRY(launch_gather_fused(pl->W, yt, M, pl->d, pl->at, P, pl->geom, pscale, pl->grid,
-                                   prange, pl->win_args, pl->spart, pl->ldm, vbound, pl->flag,
-                                   st));
+                                   prange, pl->win_args, pl->spart, pl->ldm, st));
     }
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
     FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, st));
@@ -706,6 +708,13 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     }
     std::vector<uint16_t> at;
     if (pl->at) split_dirs_host(xi, pl->d, P, at);
+    pl->xi_norm_max = 0.0;
+    for (int p = 0; p < P; ++p) {
+        double ss = 0.0;
+        for (int i = 0; i < pl->d; ++i) ss += (double)xi[(size_t)i * P + p] * xi[(size_t)i * P + p];
+        pl->xi_norm_max = std::max(pl->xi_norm_max, std::sqrt(ss));
+    }
+    if (!(pl->xi_norm_max > 0.0)) pl->xi_norm_max = 1.0;
     hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->at)
         e = hipMemcpyAsync(pl->at, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs);

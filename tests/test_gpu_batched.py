@@ -61,10 +61,16 @@ def test_batched_equals_single_plans_and_replays():
     for a, s in zip(first, outs):
         assert np.array_equal(a, s.cpu().numpy())
     for p, a, x, w, y in zip(probs, first, xs, ws, ys):
+        # the batched kernels share the stored-projection path's arithmetic
+        # (FP32 MFMA projections): same results up to accumulation order
         plan = F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"],
-                      T=0.3, n_max=p["N"], m_max=p["M"])
-        single = plan(x, w, y).cpu().numpy()
-        assert rel_l2(a, single) < 1e-6
+                      T=0.3, n_max=p["N"], m_max=p["M"], materialize=True)
+        assert rel_l2(a, plan(x, w, y).cpu().numpy()) < 1e-6
+        # the default single plan projects with split-f16 MFMAs (FP32-level,
+        # different rounding)
+        fused = F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"],
+                       T=0.3, n_max=p["N"], m_max=p["M"])
+        assert rel_l2(a, fused(x, w, y).cpu().numpy()) < 1e-5
 
 
 def test_batched_size_change_recaptures_and_direct_mode():
