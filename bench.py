@@ -204,7 +204,8 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, e
     return res
 
 
-P_LADDER = (1000, 2000, 3000, 4000, 5000, 6000, 8000, 12000, 16000)
+P_LADDER = tuple(range(1000, 6001, 500)) + (8000, 12000, 16000)
+QMC_ITERS = 10000      # projected-Adam steps of the distance-QMC design (App. H)
 TARGET_ERR = 1e-3
 
 
@@ -300,15 +301,23 @@ def main():
         sg = out.cpu().numpy().astype(np.float64)[idx]
         return float(np.linalg.norm(sg - s1) / np.linalg.norm(s1))
 
+    dirs_mem = {}
+
     def plan_for(P):
-        path = os.path.join(args.dirs_cache, f"distance_d{d}_P{P}_s101.npy") if args.dirs_cache else ""
-        if path and os.path.exists(path):
+        # distance-QMC directions, built once per P (excluded from timing, as
+        # the paper excludes the QMC construction)
+        path = (os.path.join(args.dirs_cache, f"distance_d{d}_P{P}_s101_i{QMC_ITERS}.npy")
+                if args.dirs_cache else "")
+        if P in dirs_mem:
+            xi = dirs_mem[P]
+        elif path and os.path.exists(path):
             xi = np.load(path)
         else:
-            xi = directions("distance", d, P, 101, device="cuda")
+            xi = directions("distance", d, P, 101, device="cuda", iters=QMC_ITERS)
             if path:
                 os.makedirs(args.dirs_cache, exist_ok=True)
                 np.save(path, xi)
+        dirs_mem[P] = xi
         return make_plan(dict(cfg, xi=xi, P=P))
 
     ladder = []
@@ -392,8 +401,10 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "scale: d=50 N=M=60000 10-component Gaussian mixture, "
-                               "w~N(0,1), distance-QMC directions, N_ft=1024; P = smallest "
-                               "of the ladder with rel-L2 <= 1e-3 vs FP64 direct",
+                               "w~N(0,1), distance-QMC directions (%d projected-Adam steps), "
+                               "N_ft=1024; P = smallest of the ladder 1000, 1500, ..., 6000, "
+                               "8000, 12000, 16000 with rel-L2 <= 1e-3 vs FP64 direct on 1000 "
+                               "seeded targets" % QMC_ITERS,
                    "kernel": args.kernel, "N": N, "M": M, "d": d, "P": P,
                    "n_ft": cfg["n_ft"], "window_w": info["window_w"],
                    "n_grid": info["n_grid"], "sigma": cfg["scale"], "R": cfg["R"]},

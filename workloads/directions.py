@@ -98,10 +98,11 @@ def distance_qmc_directions(d, P, rng, iters=400, lr=None, device=None):
     return xi.T.copy()
 
 
-def directions(kind, d, P, seed, rotate=True, device=None):
+def directions(kind, d, P, seed, rotate=True, device=None, iters=400):
     """Direction set by name ('iid', 'sobol', 'orth', 'distance'); QMC sets
     get a seeded Haar rotation so the estimator is unbiased (App. E).
-    device: optional torch device for the distance-QMC construction."""
+    device: optional torch device for the distance-QMC construction;
+    iters: its number of projected-Adam steps."""
     rng = np.random.default_rng(seed)
     if kind == "iid":
         return iid_directions(d, P, rng)
@@ -110,7 +111,7 @@ def directions(kind, d, P, seed, rotate=True, device=None):
     elif kind == "orth":
         xi = orthogonal_directions(d, P, rng)
     elif kind == "distance":
-        xi = distance_qmc_directions(d, P, rng, device=device)
+        xi = distance_qmc_directions(d, P, rng, iters=iters, device=device)
     else:
         raise ValueError(f"unknown direction set {kind!r}")
     if rotate:
