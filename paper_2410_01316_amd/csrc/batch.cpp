@@ -314,7 +314,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     b->arena_bytes = off;
     b->task_cap = tasks;
     b->lds_spread = (size_t)max_nr * (sizeof(double) + sizeof(int));
-    b->lds_fft = (size_t)3 * max_n * sizeof(float2);
+    b->lds_fft = fftconv_lds_bytes(max_n, false);
     b->lds_gather = (size_t)b->pstage * max_nr * sizeof(float);
 
     hipError_t e = hipGetDevice(&b->device);

@@ -55,6 +55,8 @@ hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
 // Per pair of directions: sum the chunk partials, complex FFT of size n,
 // multiply by mult (and separately by mult_d when grid_d != nullptr),
 // inverse FFT, store the cells [lo, lo+nr) of the real grids.
+// LDS bytes of one FFT-convolution workgroup (grid size n, derivative grids)
+size_t fftconv_lds_bytes(int n, bool grad);
 hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
                           const float2* tw, const float2* mult,
                           const float2* mult_d, float* grid, float* grid_d,

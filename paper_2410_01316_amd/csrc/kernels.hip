@@ -627,52 +627,104 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// Stockham autosort FFT of length n (power of two) in LDS, radix-4 stages
-// and one radix-2 stage when log2(n) is odd.  tw[m] = exp(-2 pi i m / n).
-// Forward: X_k = sum_j x_j e^{-2 pi i jk/n}; inverse: conjugate kernel, no
-// 1/n.  Returns the buffer holding the result (a or b).
-__device__ float2* fft_lds(float2* a, float2* b, int n, const float2* __restrict__ tw,
-                           bool inverse) {
-    const float sgn = inverse ? -1.f : 1.f;
-    for (int Ls = 1; Ls < n;) {
-        const int r = (n / Ls >= 4) ? 4 : 2;
-        const int nb = n / r;
-        const int stride = n / (Ls * r);
-        for (int j = threadIdx.x; j < nb; j += kBlock) {
-            const int k = j & (Ls - 1);
-            const int base = (j - k) * r + k;
-            if (r == 4) {
-                float2 a0 = a[j], a1 = a[j + nb], a2 = a[j + 2 * nb], a3 = a[j + 3 * nb];
-                if (k) {
-                    float2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
-                    w1.y *= sgn; w2.y *= sgn; w3.y *= sgn;
-                    a1 = cmul(a1, w1); a2 = cmul(a2, w2); a3 = cmul(a3, w3);
-                }
-                const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
-                const float2 d13 = csub(a1, a3);
-                // forward: times -i ; inverse: times +i
-                const float2 t3 = make_float2(sgn * d13.y, -sgn * d13.x);
-                b[base] = cadd(t0, t2);
-                b[base + Ls] = cadd(t1, t3);
-                b[base + 2 * Ls] = csub(t0, t2);
-                b[base + 3 * Ls] = csub(t1, t3);
-            } else {
-                float2 a0 = a[j], a1 = a[j + nb];
-                if (k) {
-                    float2 w1 = tw[k * stride];
-                    w1.y *= sgn;
-                    a1 = cmul(a1, w1);
-                }
-                b[base] = cadd(a0, a1);
-                b[base + Ls] = csub(a0, a1);
+// Mixed-radix Stockham autosort FFT of length n (a power of two, 32..2048) in
+// LDS: radix-8 passes while n / L >= 8, then one radix-4 or radix-2 pass
+// (n = 2048: 8, 8, 8, 4).  Each thread keeps its R values in registers
+// through the twiddle and the butterfly.  tw[m] = exp(-2 pi i m / n) is the
+// LDS copy of the table; sgn = +1 forward, -1 inverse (exp(+2 pi i ...), no
+// 1/n: the multiplier table carries the normalisation).
+__device__ __forceinline__ void dft4(float2 (&c)[4], float sgn) {
+    const float2 t0 = cadd(c[0], c[2]), t1 = csub(c[0], c[2]), t2 = cadd(c[1], c[3]);
+    const float2 d13 = csub(c[1], c[3]);
+    const float2 t3 = make_float2(sgn * d13.y, -sgn * d13.x);     // d13 * (-i sgn)
+    c[0] = cadd(t0, t2);
+    c[1] = cadd(t1, t3);
+    c[2] = csub(t0, t2);
+    c[3] = csub(t1, t3);
+}
+
+__device__ __forceinline__ void dft8(float2 (&a)[8], float sgn) {
+    constexpr float s2 = 0.70710678118654752f;
+    float2 u[4], v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        u[j] = cadd(a[j], a[j + 4]);
+        v[j] = csub(a[j], a[j + 4]);
+    }
+    // v_j * exp(-2 pi i j sgn / 8)
+    v[1] = make_float2(s2 * (v[1].x + sgn * v[1].y), s2 * (v[1].y - sgn * v[1].x));
+    v[2] = make_float2(sgn * v[2].y, -sgn * v[2].x);
+    v[3] = make_float2(s2 * (-v[3].x + sgn * v[3].y), s2 * (-v[3].y - sgn * v[3].x));
+    dft4(u, sgn);
+    dft4(v, sgn);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        a[2 * m] = u[m];
+        a[2 * m + 1] = v[m];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void fft_pass(const float2* a, float2* b, int n, int L,
+                                         const float2* tw, float sgn) {
+    const int nb = n / R;
+    const int tstep = n / (R * L);
+    for (int t = threadIdx.x; t < nb; t += kBlock) {
+        const int k = t & (L - 1);
+        float2 v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) v[j] = a[t + j * nb];
+        if (k) {
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                float2 w = tw[j * k * tstep];
+                w.y *= sgn;
+                v[j] = cmul(v[j], w);
             }
         }
+        if constexpr (R == 8) {
+            dft8(v, sgn);
+        } else if constexpr (R == 4) {
+            dft4(v, sgn);
+        } else {
+            const float2 s = cadd(v[0], v[1]);
+            v[1] = csub(v[0], v[1]);
+            v[0] = s;
+        }
+        const int base = (t - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) b[base + q * L] = v[q];
+    }
+}
+
+// returns the buffer (a or b) that holds the transform
+__device__ float2* fft_lds(float2* a, float2* b, int n, const float2* tw, bool inverse) {
+    const float sgn = inverse ? -1.f : 1.f;
+    for (int L = 1; L < n;) {
+        const int rest = n / L;
+        int R;
+        if (rest >= 8) {
+            fft_pass<8>(a, b, n, L, tw, sgn);
+            R = 8;
+        } else if (rest == 4) {
+            fft_pass<4>(a, b, n, L, tw, sgn);
+            R = 4;
+        } else {
+            fft_pass<2>(a, b, n, L, tw, sgn);
+            R = 2;
+        }
         __syncthreads();
-        float2* t = a; a = b; b = t;
-        Ls *= r;
+        float2* t = a;
+        a = b;
+        b = t;
+        L *= R;
     }
     return a;
 }
+
+// LDS of one fftconv tile: the twiddle table and two (three with the
+// derivative grids) buffers of n complex values
+size_t fftconv_lds_bytes(int n, bool grad) { return (size_t)(grad ? 4 : 3) * n * sizeof(float2); }
 
 __device__ __forceinline__ void fftconv_tile(
     float2* cbuf, const float* __restrict__ partial, int nchunk, int P, const GridGeom& g,
@@ -680,13 +732,15 @@ __device__ __forceinline__ void fftconv_tile(
     const float2* __restrict__ mult_d, float* __restrict__ grid, float* __restrict__ grid_d,
     int pair) {
     const int n = g.n;
-    float2* b0 = cbuf;
-    float2* b1 = cbuf + n;
-    float2* b2 = cbuf + 2 * n;
+    float2* twl = cbuf;
+    float2* b0 = cbuf + n;
+    float2* b1 = cbuf + 2 * n;
+    float2* b2 = cbuf + 3 * n;            // only with derivative grids
     const int pa = 2 * pair, pb = pa + 1;
     const bool has_b = pb < P;
     __syncthreads();               // LDS may still be read by a previous tile
     for (int j = threadIdx.x; j < n; j += kBlock) {
+        twl[j] = tw[j];
         float re = 0.f, im = 0.f;
         const int r = j - g.lo;
         if (r >= 0 && r < g.nr) {
@@ -698,15 +752,19 @@ __device__ __forceinline__ void fftconv_tile(
         b0[j] = make_float2(re, im);
     }
     __syncthreads();
-    float2* spec = fft_lds(b0, b1, n, tw, false);
-    float2* wa = (spec == b0) ? b1 : b0;
+    float2* spec = fft_lds(b0, b1, n, twl, false);
+    float2* other = (spec == b0) ? b1 : b0;
     const int passes = grid_d ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
         const float2* __restrict__ m = pass ? mult_d : mult;
         float* __restrict__ out = pass ? grid_d : grid;
+        // with one pass the spectrum is multiplied in place; with two it is
+        // kept for the second multiplier
+        float2* wa = (passes == 1) ? spec : (pass == 0 ? other : spec);
+        float2* wb = (passes == 1) ? other : b2;
         for (int j = threadIdx.x; j < n; j += kBlock) wa[j] = cmul(spec[j], m[j]);
         __syncthreads();
-        const float2* res = fft_lds(wa, b2, n, tw, true);
+        const float2* res = fft_lds(wa, wb, n, twl, true);
         for (int r = threadIdx.x; r < g.nr; r += kBlock) {
             const float2 v = res[g.lo + r];
             out[(int64_t)pa * g.nr + r] = v.x;
@@ -730,7 +788,7 @@ hipError_t launch_fftconv(const float* partial, int nchunk, int P, GridGeom g,
                           const float2* mult_d, float* grid, float* grid_d,
                           hipStream_t stream) {
     dim3 grid_dim((unsigned)((P + 1) / 2));
-    const size_t lds = (size_t)3 * g.n * sizeof(float2);
+    const size_t lds = fftconv_lds_bytes(g.n, grid_d != nullptr);
     hipLaunchKernelGGL(fftconv_kernel, grid_dim, dim3(kBlock), lds, stream, partial,
                        nchunk, P, g, tw, mult, mult_d, grid, grid_d);
     return hipGetLastError();
