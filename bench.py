@@ -395,6 +395,30 @@ def main():
                                    bound=bd, frac=rl["achieved"] / rl["peak"],
                                    hbm_frac=(b / (t / c * 1e-3)) / (PEAK["hbm_GBs"] * 1e9))
 
+    # the same workload on the stored-projection path (projection GEMM,
+    # spread and gather reading P x N projections): its spread and gather are
+    # HBM-bound, so their fraction of the HBM roofline is reported here
+    stored = None
+    if not args.no_forms:
+        xi_p = dirs_mem.get(P)
+        sp = make_plan(dict(cfg, xi=xi_p, P=P), materialize=True)
+        sms = timed_steps(lambda: sp(x, w, y, out=s), max(5, args.steps // 2), 2) * 1e3
+        sp.profile(True)
+        sp.profile_read()
+        for _ in range(5):
+            sp(x, w, y, out=s)
+        sph = sp.profile_read()
+        sinfo = sp.info()
+        stored = dict(ms_per_step=sms, pairs_per_s=N * M / (sms * 1e-3), P=P, phases={})
+        for p, (t, c) in sph.items():
+            if c:
+                b, fl, bd = algorithmic(p, sinfo, N, M, d, P, "fp32")
+                rl = roofline_of(bd, b, fl, t / c * 1e-3)
+                stored["phases"][p] = dict(avg_us=t / c * 1e3, bound=bd,
+                                           achieved=rl["achieved"], unit=rl["unit"],
+                                           frac=rl["achieved"] / rl["peak"])
+        sp.close()
+
     result = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -423,6 +447,8 @@ def main():
                                       "and FP32 error of the GPU path <= 1e-4"}
         if nominal is not None:
             result["nominal_P1000"] = nominal
+    if stored is not None:
+        result["stored_projection_path"] = stored
     if not args.no_forms:
         forms = {}
         fsteps = max(3, args.steps // 4)

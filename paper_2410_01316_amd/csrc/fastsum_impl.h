@@ -32,13 +32,20 @@ struct GridGeom {
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 
 // out[p*ld + j] = sum_i A[p*dpad + i] * X[j*d + i] for p < P, j < N, with
-// A = tau * Xi^T (P x dpad).  A64 (may be null; used when d <= 64) is the same
-// matrix zero-padded to round_up(P, 64) x 64.  Sets *flag if |out| > bound.
+// A = tau * Xi^T.  Sets *flag if |out| > bound.
+// FP32 MFMA, d <= 64: A64 is A zero-padded to round_up(P, 64) x 64.
 constexpr int kA64Cols = 64;
-hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
-                              const float* A, const float* A64, int P, float* out,
-                              int64_t ld, float bound, int* flag, hipStream_t stream);
-hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
+hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64, int P,
+                              float* out, int64_t ld, float bound, int* flag, hipStream_t stream);
+// Split-f16 MFMA, any d: Ahi, Alo are Xi^T (P x dpad64, unscaled) split into f16
+// hi + lo; x is scaled by inv_r = 1/R while staged and out = pscale * v,
+// pscale = tau R.  FP32-level accuracy.
+hipError_t launch_project_split(const float* X, int64_t N, int d, int dpad64, const uint16_t* Ahi,
+                                const uint16_t* Alo, int P, float inv_r, float pscale, float* out,
+                                int64_t ld, float bound, int* flag, hipStream_t stream);
+// BF16 MFMA, any d: A is tau * Xi^T in BF16, P x dpad64 (d rounded up to 64,
+// zero padded).
+hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad64,
                                const uint16_t* A, int P, float* out, int64_t ld,
                                float bound, int* flag, hipStream_t stream);
 

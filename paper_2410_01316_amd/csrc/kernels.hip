@@ -23,6 +23,7 @@ namespace fastsum {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // window weights
@@ -175,11 +176,12 @@ __device__ __forceinline__ void project_tile_f32(
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < d; k0 += kProjKC) {
+    // software pipeline: chunk k0 + KC is loaded into registers while the
+    // MFMAs of chunk k0 run from LDS, so load latency is not exposed
+    constexpr int QA = kProjBM * kProjKC / kBlock, QX = kProjBN * kProjKC / kBlock;
+    float va[QA], vx[QX];
+    auto load = [&](int k0) {
         const int kc = min(kProjKC, d - k0);
-        // issue every load of the stage before touching LDS
-        constexpr int QA = kProjBM * kProjKC / kBlock, QX = kProjBN * kProjKC / kBlock;
-        float va[QA], vx[QX];
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + q * kBlock, r = e / kProjKC, k = e % kProjKC;
@@ -190,7 +192,11 @@ __device__ __forceinline__ void project_tile_f32(
             const int e = tid + q * kBlock, r = e / kProjKC, k = e % kProjKC;
             vx[q] = (k < kc && n0 + r < N) ? X[(n0 + r) * d + k0 + k] : 0.f;
         }
-        __syncthreads();
+    };
+    load(0);
+    for (int k0 = 0; k0 < d; k0 += kProjKC) {
+        const int kc = min(kProjKC, d - k0);
+        __syncthreads();                    // the previous chunk's MFMAs are done with LDS
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + q * kBlock;
@@ -202,6 +208,7 @@ __device__ __forceinline__ void project_tile_f32(
             sm.Xs[e / kProjKC][e % kProjKC] = vx[q];
         }
         __syncthreads();
+        if (k0 + kProjKC < d) load(k0 + kProjKC);
         for (int ks = 0; ks < kc; ks += 4) {
             float a[4], b[2];
 #pragma unroll
@@ -219,8 +226,40 @@ __device__ __forceinline__ void project_tile_f32(
     project_store(acc, p0, n0, P, N, out, ld, bound, flag);
 }
 
+// Buffer-resource loads shared by the staged projection kernels (the
+// helpers themselves are defined with the fused kernels below).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t proj_rsrc(const void* p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// Staging of one k-chunk (kProjKCh columns) of a 64-direction x 128-point
+// tile with 16-byte loads from buffer resources: rows past the tile's valid
+// rows read as zero; columns past d read the next row's first elements
+// (zero past the last row), which the zero columns of the direction matrix
+// (row stride dpad64, a multiple of kProjKCh) cancel.  No load is guarded,
+// so none becomes a branch.
+constexpr int kStageX4 = kProjBN * kProjKCh / 4 / kBlock;   // float4 of X per thread
+constexpr int kStageA8 = kProjBM * kProjKCh / 8 / kBlock;   // 8 halves of A per thread
+
+__device__ __forceinline__ void stage_load(f32x4 (&vx)[kStageX4], u16x8 (&va)[kStageA8],
+                                           __amdgpu_buffer_rsrc_t xs, int d,
+                                           __amdgpu_buffer_rsrc_t as, int dpad64, int k0) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kStageX4; ++q) {
+        const int e = tid + q * kBlock, r = e >> 4, k = (e & 15) * 4;
+        vx[q] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(xs, (r * d + k0 + k) * 4, 0, 0));
+    }
+#pragma unroll
+    for (int q = 0; q < kStageA8; ++q) {
+        const int e = tid + q * kBlock, r = e >> 3, k = (e & 7) * 8;
+        va[q] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(as, (r * dpad64 + k0 + k) * 2, 0, 0));
+    }
+}
+
 __device__ __forceinline__ void project_tile_bf16(
-    ProjSmemBF16& sm, const float* __restrict__ X, int64_t N, int d, int dpad,
+    ProjSmemBF16& sm, const float* __restrict__ X, int64_t N, int d, int dpad64,
     const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
     float bound, int* __restrict__ flag, int p0, int64_t n0) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -229,34 +268,32 @@ __device__ __forceinline__ void project_tile_bf16(
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
+    const __amdgpu_buffer_rsrc_t xs = proj_rsrc(X + n0 * d, min((int64_t)kProjBN, N - n0) * d * 4);
+    const __amdgpu_buffer_rsrc_t as =
+        proj_rsrc(A + (int64_t)p0 * dpad64, (int64_t)min(kProjBM, P - p0) * dpad64 * 2);
+    // software pipeline: chunk k0 + KC loads into registers while the MFMAs
+    // of chunk k0 run from LDS
+    f32x4 vx[kStageX4];
+    u16x8 va[kStageA8];
+    stage_load(vx, va, xs, d, as, dpad64, 0);
     for (int k0 = 0; k0 < d; k0 += kProjKCh) {
         const int kc = min(kProjKCh, d - k0);
-        constexpr int QA = kProjBM * kProjKCh / kBlock, QX = kProjBN * kProjKCh / kBlock;
-        unsigned short va[QA];
-        float vx[QX];
+        __syncthreads();                    // the previous chunk's MFMAs are done with LDS
 #pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            const int e = tid + q * kBlock, r = e / kProjKCh, k = e % kProjKCh;
-            va[q] = (k < kc && p0 + r < P) ? A[(int64_t)(p0 + r) * dpad + k0 + k] : (unsigned short)0;
+        for (int q = 0; q < kStageA8; ++q) {
+            const int e = tid + q * kBlock;
+            *reinterpret_cast<u16x8*>(&sm.As[e >> 3][(e & 7) * 8]) = va[q];
         }
 #pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int e = tid + q * kBlock, r = e / kProjKCh, k = e % kProjKCh;
-            vx[q] = (k < kc && n0 + r < N) ? X[(n0 + r) * d + k0 + k] : 0.f;
+        for (int q = 0; q < kStageX4; ++q) {
+            const int e = tid + q * kBlock;
+            u16x4 h;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) h[j] = f32_to_bf16_rne(vx[q][j]);
+            *reinterpret_cast<u16x4*>(&sm.Xs[e >> 4][(e & 15) * 4]) = h;
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            const int e = tid + q * kBlock;
-            sm.As[e / kProjKCh][e % kProjKCh] = va[q];
-        }
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int e = tid + q * kBlock;
-            sm.Xs[e / kProjKCh][e % kProjKCh] = f32_to_bf16_rne(vx[q]);
-        }
-        __syncthreads();
+        if (k0 + kProjKCh < d) stage_load(vx, va, xs, d, as, dpad64, k0 + kProjKCh);
         for (int ks = 0; ks < kc; ks += 32) {
             bf16x8 a[4], b[2];
             const int kk = ks + 8 * (lane >> 4);
@@ -275,6 +312,124 @@ __device__ __forceinline__ void project_tile_bf16(
     }
     project_store(acc, p0, n0, P, N, out, ld, bound, flag);
 }
+
+// Split-f16 projection for the stored path: v = <xi_p, x_n / R> with x / R
+// and xi held as f16 hi + lo (hi = f16(v), lo = f16(v - hi)), three
+// v_mfma_f32_16x16x32_f16 per 32 columns (hi hi + hi lo + lo hi, products
+// exact in the FP32 accumulation): FP32-level accuracy at about a fifth of
+// the FP32 MFMA time.  The directions come split from the host (Ahi, Alo:
+// P x dpad64 halves, zero padded); x is split while it is staged.  The stored
+// value is x~ = pscale v, pscale = tau R.
+struct ProjSmemSplit {
+    __attribute__((aligned(16))) unsigned short Ah[kProjBM][kProjKCh + 8];
+    __attribute__((aligned(16))) unsigned short Al[kProjBM][kProjKCh + 8];
+    __attribute__((aligned(16))) unsigned short Xh[kProjBN][kProjKCh + 8];
+    __attribute__((aligned(16))) unsigned short Xl[kProjBN][kProjKCh + 8];
+};
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void project_tile_split(
+    ProjSmemSplit& sm, const float* __restrict__ X, int64_t N, int d, int dpad64,
+    const unsigned short* __restrict__ Ahi, const unsigned short* __restrict__ Alo, int P,
+    float inv_r, float pscale, float* __restrict__ out, int64_t ld, float bound,
+    int* __restrict__ flag, int p0, int64_t n0) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __amdgpu_buffer_rsrc_t xs = proj_rsrc(X + n0 * d, min((int64_t)kProjBN, N - n0) * d * 4);
+    const int64_t abytes = (int64_t)min(kProjBM, P - p0) * dpad64 * 2;
+    const __amdgpu_buffer_rsrc_t ahs = proj_rsrc(Ahi + (int64_t)p0 * dpad64, abytes);
+    const __amdgpu_buffer_rsrc_t als = proj_rsrc(Alo + (int64_t)p0 * dpad64, abytes);
+    // software pipeline as in project_tile_bf16; the lo parts of A load
+    // through a second staging pass of the same shape
+    f32x4 vx[kStageX4];
+    u16x8 vah[kStageA8], val[kStageA8];
+    auto load = [&](int k0) {
+        stage_load(vx, vah, xs, d, ahs, dpad64, k0);
+#pragma unroll
+        for (int q = 0; q < kStageA8; ++q) {
+            const int e = tid + q * kBlock, r = e >> 3, k = (e & 7) * 8;
+            val[q] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(als, (r * dpad64 + k0 + k) * 2, 0, 0));
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < d; k0 += kProjKCh) {
+        const int kc = min(kProjKCh, d - k0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kStageA8; ++q) {
+            const int e = tid + q * kBlock;
+            *reinterpret_cast<u16x8*>(&sm.Ah[e >> 3][(e & 7) * 8]) = vah[q];
+            *reinterpret_cast<u16x8*>(&sm.Al[e >> 3][(e & 7) * 8]) = val[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kStageX4; ++q) {
+            const int e = tid + q * kBlock;
+            u16x4 hi, lo;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float v = vx[q][j] * inv_r;
+                const _Float16 h = (_Float16)v;
+                hi[j] = __builtin_bit_cast(unsigned short, h);
+                lo[j] = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)h));
+            }
+            *reinterpret_cast<u16x4*>(&sm.Xh[e >> 4][(e & 15) * 4]) = hi;
+            *reinterpret_cast<u16x4*>(&sm.Xl[e >> 4][(e & 15) * 4]) = lo;
+        }
+        __syncthreads();
+        if (k0 + kProjKCh < d) load(k0 + kProjKCh);
+        for (int ks = 0; ks < kc; ks += 32) {
+            f16x8 ah[4], al[4], xh[2], xl[2];
+            const int kk = ks + 8 * (lane >> 4);
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) {
+                ah[bi] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Ah[bi * 16 + (lane & 15)][kk]));
+                al[bi] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Al[bi * 16 + (lane & 15)][kk]));
+            }
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                xh[bj] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Xh[wave * 32 + bj * 16 + (lane & 15)][kk]));
+                xl[bj] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Xl[wave * 32 + bj * 16 + (lane & 15)][kk]));
+            }
+            // C[point][dir]: the small cross terms first
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[bj], al[bi], acc[bi][bj], 0, 0, 0);
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[bj], ah[bi], acc[bi][bj], 0, 0, 0);
+                }
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[bj], ah[bi], acc[bi][bj], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] *= pscale;
+    project_store(acc, p0, n0, P, N, out, ld, bound, flag);
+}
+
+// XCD-aware tile order for the stored projection grids: workgroups are
+// dispatched round-robin over the 8 XCDs, so block b runs on XCD b % 8.
+// Point tile pt and all direction tiles of it go to one XCD (its L2 keeps the
+// point tile while every direction tile reads it): b = 8 (g * ndt + dt) + x
+// with pt = 8 g + x.  Returns false for the padding blocks.
+__device__ __forceinline__ bool proj_tile_of_block(int b, int ndt, int npt, int& dt, int& pt) {
+    const int x = b & 7, j = b >> 3;
+    dt = j % ndt;
+    pt = (j / ndt) * 8 + x;
+    return pt < npt;
+}
+
+unsigned proj_grid_blocks(int ndt, int npt) { return (unsigned)(8 * ndt * ((npt + 7) / 8)); }
 
 // d <= 64: the block keeps its 128-point X tile in LDS for its whole life
 // and walks a range of 64-direction tiles, so X is read from memory once per
@@ -411,21 +566,27 @@ void launch_xres(dim3 grid, hipStream_t stream, const float* X, int64_t N, int d
                        P, out, ld, bound, flag, prange);
 }
 
-__global__ __launch_bounds__(kBlock) void project_f32_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad, const float* __restrict__ A,
-    int P, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag) {
-    __shared__ ProjSmemF32 sm;
-    project_tile_f32(sm, X, N, d, dpad, A, P, out, ld, bound, flag, blockIdx.y * kProjBM,
-                     (int64_t)blockIdx.x * kProjBN);
+__global__ __launch_bounds__(kBlock) void project_bf16_kernel(
+    const float* __restrict__ X, int64_t N, int d, int dpad64,
+    const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
+    float bound, int* __restrict__ flag, int ndt, int npt) {
+    __shared__ ProjSmemBF16 sm;
+    int dt, pt;
+    if (!proj_tile_of_block(blockIdx.x, ndt, npt, dt, pt)) return;
+    project_tile_bf16(sm, X, N, d, dpad64, A, P, out, ld, bound, flag, dt * kProjBM,
+                      (int64_t)pt * kProjBN);
 }
 
-__global__ __launch_bounds__(kBlock) void project_bf16_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad,
-    const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
-    float bound, int* __restrict__ flag) {
-    __shared__ ProjSmemBF16 sm;
-    project_tile_bf16(sm, X, N, d, dpad, A, P, out, ld, bound, flag, blockIdx.y * kProjBM,
-                      (int64_t)blockIdx.x * kProjBN);
+__global__ __launch_bounds__(kBlock) void project_split_kernel(
+    const float* __restrict__ X, int64_t N, int d, int dpad64,
+    const unsigned short* __restrict__ Ahi, const unsigned short* __restrict__ Alo, int P,
+    float inv_r, float pscale, float* __restrict__ out, int64_t ld, float bound,
+    int* __restrict__ flag, int ndt, int npt) {
+    __shared__ ProjSmemSplit sm;
+    int dt, pt;
+    if (!proj_tile_of_block(blockIdx.x, ndt, npt, dt, pt)) return;
+    project_tile_split(sm, X, N, d, dpad64, Ahi, Alo, P, inv_r, pscale, out, ld, bound, flag,
+                       dt * kProjBM, (int64_t)pt * kProjBN);
 }
 
 int project_xres_range(int64_t N, int P) {
@@ -435,35 +596,40 @@ int project_xres_range(int64_t N, int P) {
     return (int)(((pr + kProjBM - 1) / kProjBM) * kProjBM);
 }
 
-hipError_t launch_project_f32(const float* X, int64_t N, int d, int dpad,
-                              const float* A, const float* A64, int P, float* out, int64_t ld,
-                              float bound, int* flag, hipStream_t stream) {
-    if (d <= kXresMaxD && A64 != nullptr) {
-        const int prange = project_xres_range(N, P);
-        dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + prange - 1) / prange));
-        using L = void (*)(dim3, hipStream_t, const float*, int64_t, int, const float*, int,
-                           float*, int64_t, float, int*, int);
-        static const L table[16] = {
-            launch_xres<1>, launch_xres<2>, launch_xres<3>, launch_xres<4>,
-            launch_xres<5>, launch_xres<6>, launch_xres<7>, launch_xres<8>,
-            launch_xres<9>, launch_xres<10>, launch_xres<11>, launch_xres<12>,
-            launch_xres<13>, launch_xres<14>, launch_xres<15>, launch_xres<16>};
-        table[(d + 3) / 4 - 1](grid, stream, X, N, d, A64, P, out, ld, bound, flag, prange);
-        return hipGetLastError();
-    }
-    dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + kProjBM - 1) / kProjBM));
-    hipLaunchKernelGGL(project_f32_kernel, grid, dim3(kBlock), 0, stream, X, N, d,
-                       dpad, A, P, out, ld, bound, flag);
+hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64, int P,
+                              float* out, int64_t ld, float bound, int* flag, hipStream_t stream) {
+    if (d > kXresMaxD || A64 == nullptr) return hipErrorInvalidValue;
+    const int prange = project_xres_range(N, P);
+    dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + prange - 1) / prange));
+    using L = void (*)(dim3, hipStream_t, const float*, int64_t, int, const float*, int,
+                       float*, int64_t, float, int*, int);
+    static const L table[16] = {
+        launch_xres<1>, launch_xres<2>, launch_xres<3>, launch_xres<4>,
+        launch_xres<5>, launch_xres<6>, launch_xres<7>, launch_xres<8>,
+        launch_xres<9>, launch_xres<10>, launch_xres<11>, launch_xres<12>,
+        launch_xres<13>, launch_xres<14>, launch_xres<15>, launch_xres<16>};
+    table[(d + 3) / 4 - 1](grid, stream, X, N, d, A64, P, out, ld, bound, flag, prange);
     return hipGetLastError();
 }
 
-hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad,
+hipError_t launch_project_split(const float* X, int64_t N, int d, int dpad64, const uint16_t* Ahi,
+                                const uint16_t* Alo, int P, float inv_r, float pscale, float* out,
+                                int64_t ld, float bound, int* flag, hipStream_t stream) {
+    const int ndt = (P + kProjBM - 1) / kProjBM, npt = (int)((N + kProjBN - 1) / kProjBN);
+    hipLaunchKernelGGL(project_split_kernel, dim3(proj_grid_blocks(ndt, npt)), dim3(kBlock), 0,
+                       stream, X, N, d, dpad64, Ahi, Alo, P, inv_r, pscale, out, ld, bound, flag,
+                       ndt, npt);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad64,
                                const uint16_t* A, int P, float* out, int64_t ld,
                                float bound, int* flag, hipStream_t stream) {
-    dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + kProjBM - 1) / kProjBM));
+    const int ndt = (P + kProjBM - 1) / kProjBM, npt = (int)((N + kProjBN - 1) / kProjBN);
+    dim3 grid(proj_grid_blocks(ndt, npt));
     hipLaunchKernelGGL(project_bf16_kernel, grid, dim3(kBlock), 0, stream, X, N, d,
-                       dpad, reinterpret_cast<const unsigned short*>(A), P, out,
-                       ld, bound, flag);
+                       dpad64, reinterpret_cast<const unsigned short*>(A), P, out,
+                       ld, bound, flag, ndt, npt);
     return hipGetLastError();
 }
 

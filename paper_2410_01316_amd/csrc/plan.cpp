@@ -372,7 +372,7 @@ struct fastsum_plan_s {
     WindowPoly win;
     WindowArgs win_args;
     GridGeom geom;
-    int d = 0, P = 0, dpad = 0, W = 4;
+    int d = 0, P = 0, dpad = 0, dpad64 = 0, W = 4;
     int64_t n_max = 0, m_max = 0, ld_x = 0, ld_y = 0, ldm = 0;
     int nchunk_cap = 1, pstage = 8, ngroup_cap = 1;
     bool fused = false;               // projections inside spread / gather
@@ -389,7 +389,9 @@ struct fastsum_plan_s {
     uint16_t* xt = nullptr;        // split-f16 tiles of the sources / targets (fused plans)
     uint16_t* yt = nullptr;
     double xi_norm_max = 1.0;      // max_p |xi_p| (range check of the fused path)
-    uint16_t* A16 = nullptr;       // BF16 copy
+    uint16_t* A16 = nullptr;       // BF16 copy, P x dpad64 (zero padded)
+    uint16_t* Ahs = nullptr;       // Xi^T split into f16 hi + lo (P x dpad64; d > 64, FP32)
+    uint16_t* Als = nullptr;
     float* xproj = nullptr;
     float* yproj = nullptr;
     float* partial = nullptr;
@@ -424,7 +426,7 @@ void free_plan(fastsum_plan_s* p) {
     if (!p) return;
     for (auto& r : p->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->A16, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
+    void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->A16, p->Ahs, p->Als, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max};
     for (void* b : bufs)
@@ -571,10 +573,14 @@ fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out
                        hipStream_t st) {
     PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
     if (pl->r.p.proj == FASTSUM_PROJ_BF16)
-        return check(launch_project_bf16(X, N, pl->d, pl->dpad, pl->A16, pl->P, out, ld,
+        return check(launch_project_bf16(X, N, pl->d, pl->dpad64, pl->A16, pl->P, out, ld,
                                          pl->bound, pl->flag, st));
-    return check(launch_project_f32(X, N, pl->d, pl->dpad, pl->A, pl->A64, pl->P, out, ld,
-                                    pl->bound, pl->flag, st));
+    if (pl->A64)
+        return check(launch_project_f32(X, N, pl->d, pl->A64, pl->P, out, ld, pl->bound,
+                                        pl->flag, st));
+    return check(launch_project_split(X, N, pl->d, pl->dpad64, pl->Ahs, pl->Als, pl->P,
+                                      (float)(1.0 / pl->r.p.R), (float)(pl->r.tau * pl->r.p.R),
+                                      out, ld, pl->bound, pl->flag, st));
 }
 
 }  // namespace
@@ -634,6 +640,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     pl->P = r.p.P;
     pl->W = r.p.window_w;
     pl->dpad = (int)round_up(pl->d, 4);
+    pl->dpad64 = (int)round_up(pl->d, 64);
     pl->n_max = n_max;
     pl->m_max = m_max;
     if (!build_window(pl->W, pl->win)) { delete pl; return FASTSUM_EINVAL; }
@@ -671,7 +678,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     // fused plans store no projections; they keep split operand tiles
     const int64_t gtiles = (P + kFuseDirs - 1) / kFuseDirs;
     bool ok = dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
-              dev_alloc(&pl->A16, (size_t)P * pl->dpad) &&
+              dev_alloc(&pl->A16, (size_t)P * pl->dpad64) &&
               (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
                                dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&
                                dev_alloc(&pl->at, (size_t)split_tiles_bytes(gtiles * kFuseDirs, pl->d) / 2)
@@ -684,6 +691,9 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
               dev_alloc(&pl->flag, 1) && dev_alloc(&pl->slice_max, (size_t)((cap + kSliceLen - 1) / kSliceLen));
     const int64_t p64 = round_up(P, 64);
     if (ok && pl->d <= kA64Cols) ok = dev_alloc(&pl->A64, (size_t)p64 * kA64Cols);
+    const bool split_proj = !pl->fused && pl->d > kA64Cols && r.p.proj == FASTSUM_PROJ_FP32;
+    if (ok && split_proj)
+        ok = dev_alloc(&pl->Ahs, (size_t)P * pl->dpad64) && dev_alloc(&pl->Als, (size_t)P * pl->dpad64);
     if (ok && grad)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
              dev_alloc(&pl->mult_d, (size_t)n) && dev_alloc(&pl->tprime, (size_t)P * pl->ld_y);
@@ -693,12 +703,12 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     std::vector<float2> mult, mult_d, tw;
     build_tables(r.p.kernel, pl->d, r.p.scale, r.tau, r.p.n_ft, n, pl->win, mult, mult_d, tw);
     std::vector<float> A((size_t)P * pl->dpad, 0.f);
-    std::vector<uint16_t> A16((size_t)P * pl->dpad, 0);
+    std::vector<uint16_t> A16((size_t)P * pl->dpad64, 0);
     for (int p = 0; p < P; ++p)
         for (int i = 0; i < pl->d; ++i) {
             const float v = (float)(r.tau * (double)xi[(size_t)i * P + p]);
             A[(size_t)p * pl->dpad + i] = v;
-            A16[(size_t)p * pl->dpad + i] = f32_to_bf16_host(v);
+            A16[(size_t)p * pl->dpad64 + i] = f32_to_bf16_host(v);
         }
     std::vector<float> A64;
     if (pl->A64) {
@@ -706,8 +716,20 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         for (int p = 0; p < P; ++p)
             for (int i = 0; i < pl->d; ++i) A64[(size_t)p * kA64Cols + i] = A[(size_t)p * pl->dpad + i];
     }
-    std::vector<uint16_t> at;
+    std::vector<uint16_t> at, ahs, als;
     if (pl->at) split_dirs_host(xi, pl->d, P, at);
+    if (pl->Ahs) {
+        ahs.assign((size_t)P * pl->dpad64, 0);
+        als.assign((size_t)P * pl->dpad64, 0);
+        for (int p = 0; p < P; ++p)
+            for (int i = 0; i < pl->d; ++i) {
+                const float v = xi[(size_t)i * P + p];
+                const _Float16 hi = (_Float16)v;
+                const _Float16 lo = (_Float16)(v - (float)hi);
+                std::memcpy(&ahs[(size_t)p * pl->dpad64 + i], &hi, 2);
+                std::memcpy(&als[(size_t)p * pl->dpad64 + i], &lo, 2);
+            }
+    }
     pl->xi_norm_max = 0.0;
     for (int p = 0; p < P; ++p) {
         double ss = 0.0;
@@ -718,6 +740,10 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->at)
         e = hipMemcpyAsync(pl->at, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->Ahs)
+        e = hipMemcpyAsync(pl->Ahs, ahs.data(), ahs.size() * 2, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->Als)
+        e = hipMemcpyAsync(pl->Als, als.data(), als.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->A64)
         e = hipMemcpyAsync(pl->A64, A64.data(), A64.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->A16, A16.data(), A16.size() * 2, hipMemcpyHostToDevice, hs);
