@@ -905,17 +905,43 @@ __device__ __forceinline__ void fftconv_tile(
     const int pa = 2 * pair, pb = pa + 1;
     const bool has_b = pb < P;
     __syncthreads();               // LDS may still be read by a previous tile
+    // cells outside [lo, lo + nr) are zero; inside, the sum of the chunk
+    // partials of both directions, read as float4 (nr is a multiple of 4)
+    // with four chunks' loads in flight at a time
     for (int j = threadIdx.x; j < n; j += kBlock) {
         twl[j] = tw[j];
-        float re = 0.f, im = 0.f;
-        const int r = j - g.lo;
-        if (r >= 0 && r < g.nr) {
-            for (int c = 0; c < nchunk; ++c) {
-                re += partial[((int64_t)c * P + pa) * g.nr + r];
-                if (has_b) im += partial[((int64_t)c * P + pb) * g.nr + r];
+        if (j < g.lo || j >= g.lo + g.nr) b0[j] = make_float2(0.f, 0.f);
+    }
+    const float4* __restrict__ pa4 = reinterpret_cast<const float4*>(partial + (int64_t)pa * g.nr);
+    const float4* __restrict__ pb4 = reinterpret_cast<const float4*>(partial + (int64_t)(has_b ? pb : pa) * g.nr);
+    const int64_t cstride4 = (int64_t)P * g.nr / 4;
+    for (int r4 = threadIdx.x; r4 < g.nr / 4; r4 += kBlock) {
+        float4 sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa;
+        int c = 0;
+        for (; c + 4 <= nchunk; c += 4) {
+            float4 va[4], vb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                va[q] = pa4[(c + q) * cstride4 + r4];
+                vb[q] = pb4[(c + q) * cstride4 + r4];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sa.x += va[q].x; sa.y += va[q].y; sa.z += va[q].z; sa.w += va[q].w;
+                sb.x += vb[q].x; sb.y += vb[q].y; sb.z += vb[q].z; sb.w += vb[q].w;
             }
         }
-        b0[j] = make_float2(re, im);
+        for (; c < nchunk; ++c) {
+            const float4 va = pa4[c * cstride4 + r4], vb = pb4[c * cstride4 + r4];
+            sa.x += va.x; sa.y += va.y; sa.z += va.z; sa.w += va.w;
+            sb.x += vb.x; sb.y += vb.y; sb.z += vb.z; sb.w += vb.w;
+        }
+        if (!has_b) sb = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2* dst = b0 + g.lo + 4 * r4;
+        dst[0] = make_float2(sa.x, sb.x);
+        dst[1] = make_float2(sa.y, sb.y);
+        dst[2] = make_float2(sa.z, sb.z);
+        dst[3] = make_float2(sa.w, sb.w);
     }
     __syncthreads();
     float2* spec = fft_lds(b0, b1, n, twl, false);
