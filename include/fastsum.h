@@ -230,11 +230,19 @@ FASTSUM_API fastsum_status fastsum_set_launch(fastsum_plan plan, int64_t chunk_l
 
 /*
  * Batched form: many independent kernel-sum problems that share the kernel
- * type, P, the window and T, run by ONE persistent launch per phase
- * (projection, chunk scaling, spreading, FFT convolution, gather, reduction)
- * whose workgroups walk a task list of tiles drawn from every problem.  The
- * six launches are captured into a HIP graph on a private stream and the
- * graph is replayed while pointers and sizes repeat.
+ * type, P, the window and T, run by ONE launch per phase (projection or
+ * operand split, chunk scaling, spreading, FFT convolution, gather,
+ * reduction) whose workgroups walk a task list of tiles drawn from every
+ * problem.  The six launches are captured into a HIP graph on a private
+ * stream and the graph is replayed while pointers and sizes repeat.
+ *
+ * When every problem has d <= 64 (and FASTSUM_FLAG_MATERIALIZE is not
+ * given) the batch runs the fused kernels of the single plans: points are
+ * split into f16 operand tiles and the projections are computed inside the
+ * spreading and gathering workgroups, one workgroup per task (16 directions
+ * x a source chunk, or 1024 targets x a direction range), tasks ordered
+ * largest first.  Otherwise the projections are stored (P x N per problem)
+ * by an FP32 MFMA GEMM phase.
  *
  * Per problem at plan time: d_i, n_ft_i, scale_i, R_i, directions xi_i
  * (HOST, d_i x P row-major, as in fastsum_plan_create) and capacities.
@@ -260,9 +268,12 @@ typedef struct {
 
 /* Launch-shape knobs (chosen by an autotuner); 0 selects the default. */
 typedef struct {
-    int32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4)  */
-    int32_t spread_chunk;   /* sources per spread tile, multiple of 4096           */
-    int32_t gather_group;   /* directions per gather tile, multiple of 8            */
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4;  */
+                            /* fused batches: the split phase only)                */
+    int32_t spread_chunk;   /* sources per spread tile, multiple of 4096 (fused    */
+                            /* default 16384)                                      */
+    int32_t gather_group;   /* directions per gather tile, multiple of 8 (fused:   */
+                            /* rounded up to 16, default all P)                    */
     int32_t use_graph;      /* 0/1: capture and replay a HIP graph (default); -1:  */
                             /* launch the phases directly on the caller's stream  */
 } fastsum_batch_tuning;
@@ -271,9 +282,10 @@ typedef struct fastsum_batch_s* fastsum_batch;
 
 /*
  * common supplies kernel, P, window_w, oversample, T and gmax_factor; proj
- * must be FASTSUM_PROJ_FP32 and flags 0 (no adjoint in the batched form).
+ * must be FASTSUM_PROJ_FP32 and flags 0 or FASTSUM_FLAG_MATERIALIZE (stored
+ * projections; no adjoint in the batched form).
  * d, n_ft, scale and R of common are ignored.  tuning may be NULL.
- * Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED (BF16 or GRAD requested).
+ * Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED (BF16, GRAD or another flag).
  */
 FASTSUM_API fastsum_status fastsum_batch_create(const fastsum_params* common,
                                                 const fastsum_problem_desc* probs,

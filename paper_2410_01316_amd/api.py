@@ -205,15 +205,17 @@ def choose_nft(kernel, d, R, scale=1.0, T=0.0, gmax_factor=0.0, candidates=(256,
 
 class Batch:
     """Many independent kernel sums (shared kernel, P, window, T) run by one
-    persistent launch per phase and replayed from a HIP graph.
+    launch per phase and replayed from a HIP graph.
 
     problems: list of dicts with keys xi (d x P), n_ft, scale, R, n_max, m_max.
+    With every d <= 64 the projections are computed inside the spreading and
+    gathering kernels (as in a single plan); materialize=True stores them.
     """
 
     TUNING_KEYS = ("blocks_per_cu", "spread_chunk", "gather_group", "use_graph")
 
     def __init__(self, problems, *, kernel, T=0.0, gmax_factor=0.0, window_w=0, oversample=0,
-                 tuning=None, device=None):
+                 tuning=None, device=None, materialize=False):
         lib = L.load()
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.index is None:
@@ -231,7 +233,8 @@ class Batch:
             descs[i] = L.ProblemDesc(x.shape[0], int(p["n_ft"]), float(p.get("scale", 1.0)),
                                      float(p["R"]), x.ctypes.data_as(ctypes.c_void_p),
                                      self.n_max[i], self.m_max[i])
-        common = L.Params(0, self.P, 0, int(window_w), int(oversample), L.KERNELS[kernel], 0, 0,
+        flags = L.FLAG_MATERIALIZE if materialize else 0
+        common = L.Params(0, self.P, 0, int(window_w), int(oversample), L.KERNELS[kernel], 0, flags,
                           1.0, float(T), float(gmax_factor), 1.0)
         self._h = ctypes.c_void_p()
         tun = self._tuning_struct(tuning or {})

@@ -23,10 +23,12 @@ struct ProblemPlan {
     int dpad = 0;
     int64_t n_max = 0, m_max = 0, ldx = 0, ldy = 0, ldm = 0;
     int nchunk_cap = 1, ngroup_cap = 1;
-    // arena offsets (bytes)
+    // arena offsets (bytes); fused batches hold split tiles (at, xt, yt)
+    // in place of A and the projections
     size_t off_A = 0, off_xproj = 0, off_yproj = 0, off_partial = 0, off_grid = 0,
            off_spart = 0, off_exp = 0, off_mult = 0, off_tw = 0;
     float bound = 0.f;
+    float norm2_max = 0.f;     // fused range check: |x / R|^2 bound
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -38,6 +40,9 @@ struct fastsum_batch_s {
     WindowPoly win;
     WindowArgs win_args{};
     int P = 0, W = 4, pstage = 8, nprob = 0, device = 0, num_cu = 256;
+    // projections computed inside spread and gather (every d <= 64, unless
+    // FASTSUM_FLAG_MATERIALIZE asks for stored projections)
+    bool fused = false;
     fastsum_batch_tuning tuning{};
     std::vector<ProblemPlan> plans;
     char* arena = nullptr;
@@ -82,7 +87,16 @@ void free_batch(fastsum_batch_s* b) {
     delete b;
 }
 
+// Fused batches: default chunks of 4 slices; a task covers 16 directions,
+// so a batch of many problems has ample tasks at this length.
+constexpr int64_t kFusedBatchChunk = 4 * kSliceLen;
+
 int chunks_for(const fastsum_batch_s* b, int64_t N) {
+    if (b->fused) {
+        const int64_t len = b->tuning.spread_chunk > 0 ? b->tuning.spread_chunk : kFusedBatchChunk;
+        const int64_t nc = std::max<int64_t>((N + len - 1) / len, (N + kMaxChunk - 1) / kMaxChunk);
+        return (int)std::max<int64_t>(nc, 1);
+    }
     int nc = spread_chunks(N, b->P);
     if (b->tuning.spread_chunk > 0) nc = (int)((N + b->tuning.spread_chunk - 1) / b->tuning.spread_chunk);
     nc = std::min<int>(nc, std::max<int>(spread_chunks(N, b->P), (int)((N + 4095) / 4096)));
@@ -91,6 +105,8 @@ int chunks_for(const fastsum_batch_s* b, int64_t N) {
 }
 
 int group_for(const fastsum_batch_s* b, int64_t M) {
+    if (b->fused)    // one range of all directions unless tuned: targets read once
+        return (int)round_up(b->tuning.gather_group > 0 ? b->tuning.gather_group : b->P, kFuseDirs);
     if (b->tuning.gather_group > 0) return (int)round_up(b->tuning.gather_group, b->pstage);
     return gather_group(M, b->P, b->pstage);
 }
@@ -105,10 +121,54 @@ fastsum_status validate_tuning(const fastsum_batch_tuning* t) {
     return FASTSUM_OK;
 }
 
+// Task lists of one problem of a fused batch, with a cost estimate per
+// spread and gather task (sources or targets times directions) by which
+// those phases are ordered, largest first.
+void fused_tasks(int i, const BatchProblem& d, const fastsum_problem_io& q, int P,
+                 std::vector<BatchTask>* ph, std::vector<int64_t>* cost) {
+    const int64_t xtiles = (q.N + 15) / 16, ytiles = (q.M + 15) / 16;
+    for (int64_t t = 0; t < (xtiles + kSplitTaskTiles - 1) / kSplitTaskTiles; ++t)
+        ph[kBatchProject].push_back({i, 0, (int)t, 0});
+    if (!d.same_xy)
+        for (int64_t t = 0; t < (ytiles + kSplitTaskTiles - 1) / kSplitTaskTiles; ++t)
+            ph[kBatchProject].push_back({i, 1, (int)t, 0});
+    for (int c = 0; c < (int)((q.N + kSliceLen - 1) / kSliceLen); ++c)
+        ph[kBatchScale].push_back({i, c, 0, 0});
+    const int groups = (P + kFuseDirs - 1) / kFuseDirs;
+    for (int c = 0; c < d.nchunk; ++c) {
+        const int64_t len = std::min<int64_t>(d.chunk_len, q.N - (int64_t)c * d.chunk_len);
+        for (int g = 0; g < groups; ++g) {
+            ph[kBatchSpread].push_back({i, g, c, 0});
+            cost[kBatchSpread].push_back(len * std::min(kFuseDirs, P - g * kFuseDirs));
+        }
+    }
+    for (int a = 0; a < (P + 1) / 2; ++a) ph[kBatchFftconv].push_back({i, a, 0, 0});
+    const int64_t tile = fused_gather_tile();
+    const int gtiles = (int)((q.M + tile - 1) / tile);
+    for (int r = 0; r < d.ngroup; ++r)
+        for (int t = 0; t < gtiles; ++t) {
+            ph[kBatchGather].push_back({i, t, r, 0});
+            cost[kBatchGather].push_back(std::min<int64_t>(tile, q.M - t * tile) *
+                                         std::min(d.pg, P - r * d.pg));
+        }
+    const int rt = (int)((q.M + kBlock - 1) / kBlock);
+    for (int t = 0; t < rt; ++t) ph[kBatchReduce].push_back({i, t, 0, 0});
+}
+
+void sort_by_cost(std::vector<BatchTask>& tasks, const std::vector<int64_t>& cost) {
+    std::vector<size_t> idx(tasks.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<BatchTask> out(tasks.size());
+    for (size_t k = 0; k < idx.size(); ++k) out[k] = tasks[idx[k]];
+    tasks.swap(out);
+}
+
 // Fill h_probs / h_tasks for the given io and record per-phase ranges.
 fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
     const int P = b->P;
     std::vector<BatchTask> ph[kBatchPhases];
+    std::vector<int64_t> cost[kBatchPhases];
     for (int i = 0; i < b->nprob; ++i) {
         const ProblemPlan& pp = b->plans[i];
         const fastsum_problem_io& q = io[i];
@@ -121,9 +181,19 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
         d.N = q.N;
         d.M = q.M;
         d.same_xy = (q.x == q.y) ? 1 : 0;
-        d.A = reinterpret_cast<const float*>(b->arena + pp.off_A);
-        d.xproj = reinterpret_cast<float*>(b->arena + pp.off_xproj);
-        d.yproj = reinterpret_cast<float*>(b->arena + pp.off_yproj);
+        if (b->fused) {
+            d.at = reinterpret_cast<const uint16_t*>(b->arena + pp.off_A);
+            d.xt = reinterpret_cast<uint16_t*>(b->arena + pp.off_xproj);
+            d.yt = reinterpret_cast<uint16_t*>(b->arena + pp.off_yproj);
+            d.pscale = (float)(pp.r.tau * pp.r.p.R);
+            d.inv_r = (float)(1.0 / pp.r.p.R);
+            d.norm2_max = pp.norm2_max;
+            d.kb = split_kblocks(pp.r.p.d);
+        } else {
+            d.A = reinterpret_cast<const float*>(b->arena + pp.off_A);
+            d.xproj = reinterpret_cast<float*>(b->arena + pp.off_xproj);
+            d.yproj = reinterpret_cast<float*>(b->arena + pp.off_yproj);
+        }
         d.partial = reinterpret_cast<float*>(b->arena + pp.off_partial);
         d.grid = reinterpret_cast<float*>(b->arena + pp.off_grid);
         d.spart = reinterpret_cast<double*>(b->arena + pp.off_spart);
@@ -144,6 +214,10 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
         d.ngroup = (P + d.pg - 1) / d.pg;
         if (d.ngroup > pp.ngroup_cap) return FASTSUM_EINVAL;
 
+        if (b->fused) {
+            fused_tasks(i, d, q, P, ph, cost);
+            continue;
+        }
         const int ptiles = (P + kProjTileP - 1) / kProjTileP;
         const int nt = (int)((q.N + kProjTileN - 1) / kProjTileN);
         const int mt = (int)((q.M + kProjTileN - 1) / kProjTileN);
@@ -163,6 +237,10 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
         const int rt = (int)((q.M + kBlock - 1) / kBlock);
         for (int t = 0; t < rt; ++t) ph[kBatchReduce].push_back({i, t, 0, 0});
     }
+    if (b->fused) {
+        sort_by_cost(ph[kBatchSpread], cost[kBatchSpread]);
+        sort_by_cost(ph[kBatchGather], cost[kBatchGather]);
+    }
     size_t total = 0;
     for (int k = 0; k < kBatchPhases; ++k) total += ph[k].size();
     if (total > b->task_cap) return FASTSUM_EINVAL;
@@ -181,9 +259,13 @@ fastsum_status launch_all(fastsum_batch_s* b, hipStream_t st) {
     const int grid_blocks = bpc * b->num_cu;
     const size_t lds[kBatchPhases] = {0, 0, b->lds_spread, b->lds_fft, b->lds_gather, 0};
     for (int k = 0; k < kBatchPhases; ++k) {
-        hipError_t e = launch_batch_phase(k, b->W, b->d_probs, b->d_tasks + b->task_off[k],
-                                          b->task_cnt[k], b->P, b->pstage, b->win_args, b->flag,
-                                          grid_blocks, lds[k], st);
+        hipError_t e = b->fused
+            ? launch_batch_phase_fused(k, b->W, b->d_probs, b->d_tasks + b->task_off[k],
+                                       b->task_cnt[k], b->P, b->win_args, b->flag, grid_blocks,
+                                       lds[k], st)
+            : launch_batch_phase(k, b->W, b->d_probs, b->d_tasks + b->task_off[k],
+                                 b->task_cnt[k], b->P, b->pstage, b->win_args, b->flag,
+                                 grid_blocks, lds[k], st);
         if (e != hipSuccess) return status_of(e);
     }
     return FASTSUM_OK;
@@ -233,7 +315,8 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
                                     int32_t n_problems, const fastsum_batch_tuning* tuning,
                                     void* stream, fastsum_batch* out) {
     if (!common || !probs || n_problems < 1 || !out) return FASTSUM_EINVAL;
-    if (common->proj != FASTSUM_PROJ_FP32 || common->flags != 0) return FASTSUM_EUNSUPPORTED;
+    if (common->proj != FASTSUM_PROJ_FP32 || (common->flags & ~FASTSUM_FLAG_MATERIALIZE) != 0)
+        return FASTSUM_EUNSUPPORTED;
     if (validate_tuning(tuning) != FASTSUM_OK) return FASTSUM_EINVAL;
     hipStream_t hs = (hipStream_t)stream;
     fastsum_batch_s* b = new (std::nothrow) fastsum_batch_s();
@@ -248,6 +331,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     int max_nr = 8, max_n = 8;
     std::vector<std::vector<float2>> mults(n_problems), tws(n_problems);
     std::vector<std::vector<float>> As(n_problems);
+    std::vector<std::vector<uint16_t>> Ats(n_problems);
     for (int i = 0; i < n_problems; ++i) {
         const fastsum_problem_desc& pd = probs[i];
         if (!pd.xi || pd.n_max < 1 || pd.m_max < 1) { free_batch(b); return FASTSUM_EINVAL; }
@@ -279,10 +363,29 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
         build_tables(pp.r.p.kernel, pp.r.p.d, pp.r.p.scale, pp.r.tau, pp.r.p.n_ft, n, b->win,
                      mults[i], mult_d, tws[i]);
         As[i].assign((size_t)b->P * pp.dpad, 0.f);
-        for (int p = 0; p < b->P; ++p)
-            for (int k = 0; k < pp.r.p.d; ++k)
-                As[i][(size_t)p * pp.dpad + k] = (float)(pp.r.tau * (double)pd.xi[(size_t)k * b->P + p]);
+        double xi_norm_max = 0.0;
+        for (int p = 0; p < b->P; ++p) {
+            double ss = 0.0;
+            for (int k = 0; k < pp.r.p.d; ++k) {
+                const double v = pd.xi[(size_t)k * b->P + p];
+                As[i][(size_t)p * pp.dpad + k] = (float)(pp.r.tau * v);
+                ss += v * v;
+            }
+            xi_norm_max = std::max(xi_norm_max, std::sqrt(ss));
+        }
+        if (!(xi_norm_max > 0.0)) xi_norm_max = 1.0;
+        // |x~| <= tau R for every direction when |x| max|xi| <= R
+        const double lim = (1.0 + 1e-5) / xi_norm_max;
+        pp.norm2_max = (float)(lim * lim);
     }
+    b->fused = (common->flags & FASTSUM_FLAG_MATERIALIZE) == 0;
+    for (int i = 0; i < n_problems; ++i)
+        b->fused = b->fused && fused_supported(b->plans[i].r.p.d, b->plans[i].geom.nr);
+    if (b->fused)
+        for (int i = 0; i < n_problems; ++i) {
+            split_dirs_host(probs[i].xi, b->plans[i].r.p.d, b->P, Ats[i]);
+            As[i].clear();
+        }
     b->pstage = std::max(1, std::min(8, 12288 / max_nr));
     size_t tasks = 0;
     for (int i = 0; i < n_problems; ++i) {
@@ -291,13 +394,20 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
         // caps: every admissible N and tuning (chunks of >= 4096 sources)
         int nc = std::max(chunks_for(b, pp.n_max), spread_chunks(pp.n_max, P));
         nc = std::max(nc, (int)((pp.n_max + 4095) / 4096));
-        const int ng = (P + b->pstage - 1) / b->pstage;
+        const int ng = (P + (b->fused ? kFuseDirs : b->pstage) - 1) /
+                       (b->fused ? kFuseDirs : b->pstage);
         pp.nchunk_cap = nc;
         pp.ngroup_cap = ng;
         const int nr = pp.geom.nr, n = pp.r.n;
-        pp.off_A = off; off = align256(off + sizeof(float) * (size_t)P * pp.dpad);
-        pp.off_xproj = off; off = align256(off + sizeof(float) * (size_t)P * pp.ldx);
-        pp.off_yproj = off; off = align256(off + sizeof(float) * (size_t)P * pp.ldy);
+        if (b->fused) {
+            pp.off_A = off; off = align256(off + Ats[i].size() * sizeof(uint16_t));
+            pp.off_xproj = off; off = align256(off + (size_t)split_tiles_bytes(pp.n_max, pp.r.p.d));
+            pp.off_yproj = off; off = align256(off + (size_t)split_tiles_bytes(pp.m_max, pp.r.p.d));
+        } else {
+            pp.off_A = off; off = align256(off + sizeof(float) * (size_t)P * pp.dpad);
+            pp.off_xproj = off; off = align256(off + sizeof(float) * (size_t)P * pp.ldx);
+            pp.off_yproj = off; off = align256(off + sizeof(float) * (size_t)P * pp.ldy);
+        }
         pp.off_partial = off; off = align256(off + sizeof(float) * (size_t)nc * P * nr);
         pp.off_grid = off; off = align256(off + sizeof(float) * (size_t)P * nr);
         pp.off_spart = off; off = align256(off + sizeof(double) * (size_t)ng * pp.ldm);
@@ -310,12 +420,15 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
         tasks += (P + 1) / 2;
         tasks += (size_t)ng * ((pp.m_max + kGatherTile - 1) / kGatherTile);
         tasks += (pp.m_max + kBlock - 1) / kBlock;
+        if (b->fused)    // split tasks (the others are bounded by the stored form's)
+            tasks += (size_t)((pp.n_max + 16 * kSplitTaskTiles - 1) / (16 * kSplitTaskTiles) +
+                              (pp.m_max + 16 * kSplitTaskTiles - 1) / (16 * kSplitTaskTiles));
     }
     b->arena_bytes = off;
     b->task_cap = tasks;
-    b->lds_spread = (size_t)max_nr * (sizeof(double) + sizeof(int));
+    b->lds_spread = b->fused ? fused_spread_lds(max_nr) : (size_t)max_nr * (sizeof(double) + sizeof(int));
     b->lds_fft = fftconv_lds_bytes(max_n, false);
-    b->lds_gather = (size_t)b->pstage * max_nr * sizeof(float);
+    b->lds_gather = b->fused ? fused_gather_lds(max_nr) : (size_t)b->pstage * max_nr * sizeof(float);
 
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, b->device);
@@ -329,8 +442,10 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     if (e != hipSuccess) { fastsum_status st = status_of(e); free_batch(b); return st; }
     for (int i = 0; i < n_problems && e == hipSuccess; ++i) {
         const ProblemPlan& pp = b->plans[i];
-        e = hipMemcpyAsync(b->arena + pp.off_A, As[i].data(), As[i].size() * sizeof(float),
-                           hipMemcpyHostToDevice, hs);
+        e = b->fused ? hipMemcpyAsync(b->arena + pp.off_A, Ats[i].data(),
+                                      Ats[i].size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs)
+                     : hipMemcpyAsync(b->arena + pp.off_A, As[i].data(), As[i].size() * sizeof(float),
+                                      hipMemcpyHostToDevice, hs);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->arena + pp.off_mult, mults[i].data(), mults[i].size() * sizeof(float2),
                                hipMemcpyHostToDevice, hs);

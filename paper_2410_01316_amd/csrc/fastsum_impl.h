@@ -154,9 +154,17 @@ struct BatchProblem {
     int64_t chunk_len;
     GridGeom g;
     int d, dpad;
-    int nchunk, pg, ngroup;
+    int nchunk, pg, ngroup;      // fused: pg = directions per gather range
     int same_xy;
     float bound;
+    // fused problems (d <= kSplitMaxD): split tiles instead of projections
+    const uint16_t* at;    // directions, ceil(P/16) tiles
+    uint16_t* xt;          // sources, ceil(n_max/16) tiles
+    uint16_t* yt;          // targets, ceil(m_max/16) tiles
+    float pscale;          // tau R
+    float inv_r;           // 1 / R
+    float norm2_max;       // range check of |x / R|^2
+    int kb;                // ceil(d / 32)
 };
 
 // One tile of one phase of one problem; a, b, c are phase-specific indices.
@@ -169,13 +177,16 @@ struct BatchTask {
 
 enum BatchPhase {
     kBatchProject = 0,   // a = 0 (x) / 1 (y), b = point tile, c = direction tile
+                         // (fused: b = block of kSplitTaskTiles split tiles)
     kBatchScale = 1,     // a = slice of kSliceLen sources
-    kBatchSpread = 2,    // a = direction, b = chunk
+    kBatchSpread = 2,    // a = direction, b = chunk (fused: a = 16-direction group)
     kBatchFftconv = 3,   // a = direction pair
-    kBatchGather = 4,    // a = target tile, b = direction group
+    kBatchGather = 4,    // a = target tile, b = direction group (fused: range)
     kBatchReduce = 5,    // a = block of kBlock targets
     kBatchPhases = 6
 };
+
+constexpr int kSplitTaskTiles = 64;     // split tiles per fused batch task
 
 constexpr int kProjTileP = 64;          // projection tile: directions
 constexpr int kProjTileN = 128;         // projection tile: points
@@ -185,5 +196,15 @@ hipError_t launch_batch_phase(int phase, int W, const BatchProblem* probs,
                               const BatchTask* tasks, int ntasks, int P, int pstage,
                               const WindowArgs& win, int* flag, int grid_blocks,
                               size_t lds_bytes, hipStream_t stream);
+// The split, spread and gather phases of fused batches (every problem with
+// d <= kSplitMaxD); the other phases are shared with launch_batch_phase.
+// Spread and gather run one workgroup per task.
+hipError_t launch_batch_phase_fused(int phase, int W, const BatchProblem* probs,
+                                    const BatchTask* tasks, int ntasks, int P,
+                                    const WindowArgs& win, int* flag, int grid_blocks,
+                                    size_t lds_bytes, hipStream_t stream);
+// LDS bytes of the fused batch spread / gather workgroups for grids of nr cells
+size_t fused_spread_lds(int nr);
+size_t fused_gather_lds(int nr);
 
 }  // namespace fastsum

@@ -1233,13 +1233,10 @@ __device__ __forceinline__ h8 buffer_load_h8(__amdgpu_buffer_rsrc_t rs, int byte
 // and columns >= d are zero.  Also the range check of the fused path: a
 // row with |z * scale|^2 > norm2_max sets *flag (z * scale is x / R, and
 // |<xi, x / R>| <= max|xi| |x| / R bounds every projection of the row).
-__global__ __launch_bounds__(kBlock) void split_points_kernel(
-    const float* __restrict__ Z, int64_t N, int d, float scale, int KB, int64_t ntiles,
-    u32x4* __restrict__ tiles, float norm2_max, int* __restrict__ flag) {
-    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (id >= ntiles * 64) return;                    // whole waves
-    const int lane = (int)(id & 63);
-    const int64_t t = id >> 6;
+__device__ __forceinline__ void split_points_lane(const float* __restrict__ Z, int64_t N, int d,
+                                                  float scale, int KB, int64_t t, int lane,
+                                                  u32x4* __restrict__ tiles, float norm2_max,
+                                                  int* __restrict__ flag) {
     const int64_t row = 16 * t + (lane & 15);
     float ss = 0.f;
     for (int kb = 0; kb < KB; ++kb) {
@@ -1262,6 +1259,14 @@ __global__ __launch_bounds__(kBlock) void split_points_kernel(
     ss += __shfl_xor(ss, 16);
     ss += __shfl_xor(ss, 32);
     if (!(ss <= norm2_max) && lane < 16) atomicOr(flag, 1);   // NaN also flags
+}
+
+__global__ __launch_bounds__(kBlock) void split_points_kernel(
+    const float* __restrict__ Z, int64_t N, int d, float scale, int KB, int64_t ntiles,
+    u32x4* __restrict__ tiles, float norm2_max, int* __restrict__ flag) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id >= ntiles * 64) return;                    // whole waves
+    split_points_lane(Z, N, d, scale, KB, id >> 6, (int)(id & 63), tiles, norm2_max, flag);
 }
 
 // operand of one tile: hi and lo parts of each k-block
@@ -1307,24 +1312,24 @@ __device__ __forceinline__ f32x4 split_mfma(const SplitOp<KB>& a, const SplitOp<
     return acc;
 }
 
-// Spread with projections computed in registers.  Workgroup (x, y) owns the
-// 16 directions 16x .. 16x+15 and the sources of chunk y; grids are
+// Spread with projections computed in registers.  A workgroup owns the 16
+// directions 16 dgroup .. 16 dgroup + 15 and the sources of chunk `chunk`; grids are
 // kFuseDirs x nr int32 cells in LDS (fixed point per slice as in
 // spread_tile) flushed after every slice into per-thread FP32 accumulators.
 // v = <xi_p, x_n / R>; x~ = pscale v with pscale = tau R.  The range check
 // of these points was done when they were split.
 template <int W, int KB>
-__global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
-    const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
-    const float* __restrict__ w, int P, GridGeom g, float pscale, int64_t chunk_len,
-    const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial) {
-    extern __shared__ int cells[];
+__device__ __forceinline__ void spread_fused_body(
+    int* cells, const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
+    const float* __restrict__ w, int P, const GridGeom& g, float pscale, int64_t chunk_len,
+    const float* __restrict__ slice_max, const WindowArgs& win, float* __restrict__ partial,
+    int dgroup, int chunk) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
-    const int p0 = blockIdx.x * kFuseDirs;
+    const int p0 = dgroup * kFuseDirs;
     const int ncell = kFuseDirs * g.nr;
     SplitOp<KB> dop;
-    load_split<KB>(dop, At, blockIdx.x, lane);
+    load_split<KB>(dop, At, dgroup, lane);
     float acc[kFuseAcc];
 #pragma unroll
     for (int q = 0; q < kFuseAcc; ++q) acc[q] = 0.f;
@@ -1332,7 +1337,7 @@ __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
     __syncthreads();
     int* gcol = cells + c * g.nr;                     // grid of direction p0 + c
     const WinEval<W> ev(g, win, pscale);
-    const int64_t i0 = (int64_t)blockIdx.y * chunk_len;   // multiple of kSlice
+    const int64_t i0 = (int64_t)chunk * chunk_len;   // multiple of kSlice
     const int len = (int)min(N - i0, chunk_len);           // <= 2^20 sources
     // the chunk's tiles and a few beyond (prefetch), within the tile array;
     // the weights of the chunk only, so sources past it spread nothing
@@ -1388,12 +1393,23 @@ __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
     }
     // cells j = dir * nr + (cell - lo): the block's rows of partial are contiguous
     const int nvalid = min(kFuseDirs, P - p0) * g.nr;
-    float* __restrict__ dst = partial + ((int64_t)blockIdx.y * P + p0) * g.nr;
+    float* __restrict__ dst = partial + ((int64_t)chunk * P + p0) * g.nr;
 #pragma unroll
     for (int q = 0; q < kFuseAcc; ++q) {
         const int j = tid + q * kSpreadBlock;
         if (j < nvalid) dst[j] = acc[q];
     }
+}
+
+// workgroup (x, y): direction group x, source chunk y
+template <int W, int KB>
+__global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
+    const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
+    const float* __restrict__ w, int P, GridGeom g, float pscale, int64_t chunk_len,
+    const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial) {
+    extern __shared__ int cells[];
+    spread_fused_body<W, KB>(cells, Xt, N, At, w, P, g, pscale, chunk_len, slice_max, win,
+                             partial, blockIdx.x, blockIdx.y);
 }
 
 // Copies the grids of directions p0 .. p0+np-1 (contiguous, np * nr floats)
@@ -1412,24 +1428,24 @@ __device__ __forceinline__ void gather_stage(const float* __restrict__ grid, int
     }
 }
 
-// Gather with projections computed in registers.  Workgroup (x, y) owns the
-// kGatherTargets targets of tile x and the direction range y (prange
-// directions, a multiple of kFuseDirs).  The grids of each group of 16
+// Gather with projections computed in registers.  A workgroup owns the
+// kGatherTargets targets of tile `tile` and the direction range `range`
+// (prange directions, a multiple of kFuseDirs).  The grids of each group of 16
 // directions are staged in one of two LDS buffers while the previous group
 // is interpolated; lane (c, r) holds directions 4r .. 4r+3 of target c of
 // each batch.  Per target the four directions are summed in FP32, the
 // groups in FP64.
 template <int W, int KB>
-__global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
-    const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At, int P,
-    GridGeom g, float pscale, const float* __restrict__ grid, int prange, int stage,
-    WindowArgs win, double* __restrict__ spart, int64_t ldm) {
-    extern __shared__ float gls[];                    // 2 x stage floats
+__device__ __forceinline__ void gather_fused_body(
+    float* gls, const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At,
+    int P, const GridGeom& g, float pscale, const float* __restrict__ grid, int prange,
+    int stage, const WindowArgs& win, double* __restrict__ spart, int64_t ldm, int tile,
+    int range) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
-    const int64_t mb = (int64_t)blockIdx.x * kGatherTargets;
+    const int64_t mb = (int64_t)tile * kGatherTargets;
     const int64_t tw = (mb + wave * (kGatherNB * 16)) / 16;   // wave's first target tile
-    const int p_begin = blockIdx.y * prange;
+    const int p_begin = range * prange;
     const int p_end = min(P, p_begin + prange);
     gather_stage(grid, p_begin, min(kFuseDirs, p_end - p_begin), g.nr, gls, wave, lane);
     // target tiles past the last one read as zero
@@ -1516,8 +1532,19 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
         const int64_t m = mb + wave * (kGatherNB * 16) + 16 * b + c;
-        if (r == 0 && m < M) spart[(int64_t)blockIdx.y * ldm + m] = v;
+        if (r == 0 && m < M) spart[(int64_t)range * ldm + m] = v;
     }
+}
+
+// workgroup (x, y): target tile x, direction range y
+template <int W, int KB>
+__global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
+    const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At, int P,
+    GridGeom g, float pscale, const float* __restrict__ grid, int prange, int stage,
+    WindowArgs win, double* __restrict__ spart, int64_t ldm) {
+    extern __shared__ float gls[];                    // 2 x stage floats
+    gather_fused_body<W, KB>(gls, Yt, M, At, P, g, pscale, grid, prange, stage, win, spart, ldm,
+                             blockIdx.x, blockIdx.y);
 }
 
 template <int W, int KB>
@@ -1713,6 +1740,119 @@ __global__ __launch_bounds__(kBlock) void batch_reduce_kernel(
         reduce_tile(pr.spart, pr.ngroup, pr.ldm, pr.M, 1.0 / P, pr.s,
                     (int64_t)tk.a * kBlock + threadIdx.x);
     }
+}
+
+// Fused batch phases.  Split: one task per kSplitTaskTiles tiles of one
+// point set.  Spread and gather: the single-problem bodies, the operand
+// shape (ceil(d / 32) k-blocks) chosen per task.
+__global__ __launch_bounds__(kBlock) void batch_split_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int* __restrict__ flag) {
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        const bool is_y = tk.a != 0;
+        const int64_t n = is_y ? pr.M : pr.N;
+        const int64_t ntiles = (n + 15) / 16;
+        const int64_t t0 = (int64_t)tk.b * kSplitTaskTiles;
+        const int64_t t1 = min(ntiles, t0 + kSplitTaskTiles);
+        u32x4* dst = reinterpret_cast<u32x4*>(is_y ? pr.yt : pr.xt);
+        for (int64_t id = t0 * 64 + threadIdx.x; id < t1 * 64; id += kBlock)
+            split_points_lane(is_y ? pr.y : pr.x, n, pr.d, pr.inv_r, pr.kb, id >> 6,
+                              (int)(id & 63), dst, pr.norm2_max, flag);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kSpreadBlock) void batch_spread_fused_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P, WindowArgs win) {
+    extern __shared__ int bcells[];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        if (pr.kb == 1)
+            spread_fused_body<W, 1>(bcells, pr.xt, pr.N, pr.at, pr.w, P, pr.g, pr.pscale,
+                                    pr.chunk_len, pr.slice_max, win, pr.partial, tk.a, tk.b);
+        else
+            spread_fused_body<W, 2>(bcells, pr.xt, pr.N, pr.at, pr.w, P, pr.g, pr.pscale,
+                                    pr.chunk_len, pr.slice_max, win, pr.partial, tk.a, tk.b);
+        __syncthreads();
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kGatherBlock) void batch_gather_fused_kernel(
+    const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
+    int P, WindowArgs win) {
+    extern __shared__ float bgls[];
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const BatchTask tk = tasks[t];
+        const BatchProblem& pr = probs[tk.prob];
+        const int stage = (kFuseDirs * pr.g.nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
+        const uint16_t* yt = pr.same_xy ? pr.xt : pr.yt;
+        // no wave may still read the staging buffers of the previous task
+        __syncthreads();
+        if (pr.kb == 1)
+            gather_fused_body<W, 1>(bgls, yt, pr.M, pr.at, P, pr.g, pr.pscale, pr.grid, pr.pg,
+                                    stage, win, pr.spart, pr.ldm, tk.a, tk.b);
+        else
+            gather_fused_body<W, 2>(bgls, yt, pr.M, pr.at, P, pr.g, pr.pscale, pr.grid, pr.pg,
+                                    stage, win, pr.spart, pr.ldm, tk.a, tk.b);
+    }
+}
+
+size_t fused_spread_lds(int nr) { return (size_t)kFuseDirs * nr * sizeof(int); }
+
+size_t fused_gather_lds(int nr) {
+    const int stage = (kFuseDirs * nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
+    return (size_t)2 * stage * sizeof(float);
+}
+
+template <int W>
+void launch_batch_fused_t(int phase, dim3 grid, const BatchProblem* probs, const BatchTask* tasks,
+                          int ntasks, int P, const WindowArgs& win, size_t lds,
+                          hipStream_t stream) {
+    static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_spread_fused_kernel<W>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kFuseMaxCells * (int)sizeof(int));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_gather_fused_kernel<W>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  2 * kFuseMaxCells * (int)sizeof(float));
+        attr_set = true;
+    }
+    if (phase == kBatchSpread)
+        hipLaunchKernelGGL((batch_spread_fused_kernel<W>), grid, dim3(kSpreadBlock), lds, stream,
+                           probs, tasks, ntasks, P, win);
+    else
+        hipLaunchKernelGGL((batch_gather_fused_kernel<W>), grid, dim3(kGatherBlock), lds, stream,
+                           probs, tasks, ntasks, P, win);
+}
+
+hipError_t launch_batch_phase_fused(int phase, int W, const BatchProblem* probs,
+                                    const BatchTask* tasks, int ntasks, int P,
+                                    const WindowArgs& win, int* flag, int grid_blocks,
+                                    size_t lds_bytes, hipStream_t stream) {
+    if (ntasks <= 0) return hipSuccess;
+    if (phase == kBatchProject) {
+        const dim3 grid((unsigned)(grid_blocks < ntasks ? grid_blocks : ntasks));
+        hipLaunchKernelGGL(batch_split_kernel, grid, dim3(kBlock), 0, stream, probs, tasks, ntasks,
+                           flag);
+        return hipGetLastError();
+    }
+    if (phase != kBatchSpread && phase != kBatchGather)
+        return launch_batch_phase(phase, W, probs, tasks, ntasks, P, 8, win, flag, grid_blocks,
+                                  lds_bytes, stream);
+    const dim3 grid((unsigned)ntasks);
+    switch (W) {
+        case 4: launch_batch_fused_t<4>(phase, grid, probs, tasks, ntasks, P, win, lds_bytes, stream); break;
+        case 6: launch_batch_fused_t<6>(phase, grid, probs, tasks, ntasks, P, win, lds_bytes, stream); break;
+        case 8: launch_batch_fused_t<8>(phase, grid, probs, tasks, ntasks, P, win, lds_bytes, stream); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_phase(int phase, int W, const BatchProblem* probs,

@@ -1,5 +1,7 @@
-"""Batched form on the GPU: many uneven problems in one persistent launch per
-phase, replayed from a HIP graph, each checked against the FP64 oracle."""
+"""Batched form on the GPU: many uneven problems in one launch per phase,
+replayed from a HIP graph, each checked against the FP64 oracle.  Batches of
+d <= 64 run the fused kernels (projections inside spread and gather); with
+materialize=True, or a problem of d > 64, the stored-projection kernels."""
 import numpy as np
 import pytest
 
@@ -19,10 +21,17 @@ def _problems(n=10, P=24, frac=0.03, seed=50):
     return probs
 
 
-def _batch(probs, **tuning):
+def _batch(probs, materialize=False, **tuning):
     import paper_2410_01316_amd as F
     return F.Batch([dict(xi=p["xi"], n_ft=p["n_ft"], scale=p["scale"], R=p["R"], n_max=p["N"],
-                         m_max=p["M"]) for p in probs], kernel="gauss", T=0.3, tuning=tuning)
+                         m_max=p["M"]) for p in probs], kernel="gauss", T=0.3, tuning=tuning,
+                   materialize=materialize)
+
+
+def _plan(p, materialize=False):
+    import paper_2410_01316_amd as F
+    return F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"], T=0.3,
+                  n_max=p["N"], m_max=p["M"], materialize=materialize)
 
 
 def _inputs(probs):
@@ -61,16 +70,59 @@ def test_batched_equals_single_plans_and_replays():
     for a, s in zip(first, outs):
         assert np.array_equal(a, s.cpu().numpy())
     for p, a, x, w, y in zip(probs, first, xs, ws, ys):
-        # the batched kernels share the stored-projection path's arithmetic
-        # (FP32 MFMA projections): same results up to accumulation order
-        plan = F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"],
-                      T=0.3, n_max=p["N"], m_max=p["M"], materialize=True)
-        assert rel_l2(a, plan(x, w, y).cpu().numpy()) < 1e-6
-        # the default single plan projects with split-f16 MFMAs (FP32-level,
-        # different rounding)
-        fused = F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"],
-                       T=0.3, n_max=p["N"], m_max=p["M"])
-        assert rel_l2(a, fused(x, w, y).cpu().numpy()) < 1e-5
+        # the fused batch runs the single plan's fused kernel bodies (split-f16
+        # projections): same results up to chunking and accumulation order
+        e1 = rel_l2(a, _plan(p)(x, w, y).cpu().numpy())
+        # stored FP32-MFMA projections round differently (FP32 level)
+        e2 = rel_l2(a, _plan(p, materialize=True)(x, w, y).cpu().numpy())
+        print(p["name"], p["d"], p["N"], p["M"], "%.1e %.1e" % (e1, e2))
+        assert e1 < 1e-6 and e2 < 1e-5
+
+
+def test_materialized_batch_equals_stored_plans():
+    probs = _problems(n=6, seed=75)
+    b = _batch(probs, materialize=True)
+    xs, ws, ys = _inputs(probs)
+    outs = b(xs, ws, ys)
+    b.check()
+    for p, s, x, w, y in zip(probs, outs, xs, ws, ys):
+        a = s.cpu().numpy()
+        assert rel_l2(a, _plan(p, materialize=True)(x, w, y).cpu().numpy()) < 1e-6
+        assert rel_l2(a, _o3(p)) < 1e-4
+
+
+def test_batch_with_a_large_d_problem_and_tiny_problems():
+    """A problem of d = 70 sends the whole batch to the stored-projection
+    kernels; problems of one source or one target and same-x-y problems
+    run in both forms."""
+    from workloads.configs import _finish, bound_R
+    from workloads.points import gaussian_mixture, median_rule_sigma
+    from workloads.directions import directions
+    rng = np.random.default_rng(333)
+    base = _problems(n=3, seed=140)
+    extra = []
+    for d, n, m in [(70, 900, 700), (10, 1, 300), (3, 500, 1)]:
+        x, means = gaussian_mixture(n, d, rng)
+        y, _ = gaussian_mixture(m, d, rng, means=means)
+        sigma = median_rule_sigma(np.vstack([x, y]), np.vstack([y, x]), rng)
+        xi = directions("orth", d, 24, seed=9)
+        cfg = _finish(dict(x=x, y=y, w=rng.standard_normal(n), xi=xi, kernel="gauss",
+                           scale=sigma, n_ft=256, name=f"extra d={d}"))
+        extra.append(cfg)
+    same = dict(base[0], y=base[0]["x"], M=base[0]["N"], name="same x y")
+    same["R"] = bound_R(same["x"], same["y"])
+    small = base + extra[1:] + [same]
+    for probs, label in [(small, "fused"), (small + extra[:1], "stored")]:
+        b = _batch(probs)
+        xs, ws, ys = _inputs(probs)
+        k = len(small) - 1
+        xs[k] = ys[k]                         # same tensor: sources are the targets
+        outs = b(xs, ws, ys)
+        b.check()
+        for p, s in zip(probs, outs):
+            e = rel_l2(s.cpu().numpy(), _o3(p))
+            print(label, p["name"], p["d"], p["N"], p["M"], "%.2e" % e)
+            assert e < 1e-4
 
 
 def test_batched_size_change_recaptures_and_direct_mode():
