@@ -269,7 +269,7 @@ typedef struct {
 /* Launch-shape knobs (chosen by an autotuner); 0 selects the default. */
 typedef struct {
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4;  */
-                            /* fused batches: the split phase only)                */
+                            /* fused batches: scaling, FFT and reduction phases)   */
     int32_t spread_chunk;   /* sources per spread tile, multiple of 4096 (fused    */
                             /* default 16384)                                      */
     int32_t gather_group;   /* directions per gather tile, multiple of 8 (fused:   */

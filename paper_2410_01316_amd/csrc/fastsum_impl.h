@@ -186,7 +186,7 @@ enum BatchPhase {
     kBatchPhases = 6
 };
 
-constexpr int kSplitTaskTiles = 64;     // split tiles per fused batch task
+constexpr int kSplitTaskTiles = 4;      // split tiles per fused batch task (kBlock / 64)
 
 constexpr int kProjTileP = 64;          // projection tile: directions
 constexpr int kProjTileN = 128;         // projection tile: points
@@ -198,7 +198,7 @@ hipError_t launch_batch_phase(int phase, int W, const BatchProblem* probs,
                               size_t lds_bytes, hipStream_t stream);
 // The split, spread and gather phases of fused batches (every problem with
 // d <= kSplitMaxD); the other phases are shared with launch_batch_phase.
-// Spread and gather run one workgroup per task.
+// These three run one workgroup per task.
 hipError_t launch_batch_phase_fused(int phase, int W, const BatchProblem* probs,
                                     const BatchTask* tasks, int ntasks, int P,
                                     const WindowArgs& win, int* flag, int grid_blocks,

@@ -1237,15 +1237,24 @@ __device__ __forceinline__ void split_points_lane(const float* __restrict__ Z, i
                                                   float scale, int KB, int64_t t, int lane,
                                                   u32x4* __restrict__ tiles, float norm2_max,
                                                   int* __restrict__ flag) {
-    const int64_t row = 16 * t + (lane & 15);
+    // The tile's rows as a buffer: a lane reads its eight columns with two
+    // 16-byte loads; rows past N read as zero and columns >= d (the next
+    // row's values) are masked.
+    const int64_t r0 = 16 * t;
+    const int64_t nrows = N - r0 < 16 ? N - r0 : 16;
+    const __amdgpu_buffer_rsrc_t zs =
+        buffer_rsrc(Z + r0 * d, (nrows > 0 ? nrows : 0) * (int64_t)d * 4);
     float ss = 0.f;
     for (int kb = 0; kb < KB; ++kb) {
         const int col0 = 32 * kb + 8 * (lane >> 4);
+        const int off = ((lane & 15) * d + col0) * 4;
+        const u32x4 va = __builtin_amdgcn_raw_buffer_load_b128(zs, off, 0, 0);
+        const u32x4 vb = __builtin_amdgcn_raw_buffer_load_b128(zs, off + 16, 0, 0);
         h8 hi, lo;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int col = col0 + e;
-            const float v = (row < N && col < d) ? Z[row * d + col] * scale : 0.f;
+            const unsigned raw = e < 4 ? va[e] : vb[e - 4];
+            const float v = col0 + e < d ? __uint_as_float(raw) * scale : 0.f;
             ss = fmaf(v, v, ss);
             const _Float16 h = (_Float16)v;
             hi[e] = h;
@@ -1763,8 +1772,10 @@ __global__ __launch_bounds__(kBlock) void batch_split_kernel(
     }
 }
 
+// two workgroups per CU (at most 128 VGPRs), as the single-problem kernel
 template <int W>
-__global__ __launch_bounds__(kSpreadBlock) void batch_spread_fused_kernel(
+__global__ __launch_bounds__(kSpreadBlock) __attribute__((amdgpu_waves_per_eu(4))) void
+batch_spread_fused_kernel(
     const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
     int P, WindowArgs win) {
     extern __shared__ int bcells[];
@@ -1837,9 +1848,8 @@ hipError_t launch_batch_phase_fused(int phase, int W, const BatchProblem* probs,
                                     size_t lds_bytes, hipStream_t stream) {
     if (ntasks <= 0) return hipSuccess;
     if (phase == kBatchProject) {
-        const dim3 grid((unsigned)(grid_blocks < ntasks ? grid_blocks : ntasks));
-        hipLaunchKernelGGL(batch_split_kernel, grid, dim3(kBlock), 0, stream, probs, tasks, ntasks,
-                           flag);
+        hipLaunchKernelGGL(batch_split_kernel, dim3((unsigned)ntasks), dim3(kBlock), 0, stream,
+                           probs, tasks, ntasks, flag);
         return hipGetLastError();
     }
     if (phase != kBatchSpread && phase != kBatchGather)
