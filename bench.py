@@ -210,8 +210,9 @@ TARGET_ERR = 1e-3
 
 
 def batched_form(steps, log_fn):
-    """256 uneven Gauss problems: one batch (persistent launches, graph
-    replay, autotuned launch shape) against a loop of plain plans."""
+    """256 uneven Gauss problems: one batch (fused kernels, one launch per
+    phase, graph replay, autotuned launch shape) against the same batch with
+    stored projections and against a loop of plain plans."""
     import torch
     import paper_2410_01316_amd as F
     from paper_2410_01316_amd.autotune import autotune
@@ -230,6 +231,13 @@ def batched_form(steps, log_fn):
     tuning, _ = autotune(batch, xs, ws, ys, outs, reps=3, log=log_fn)
     ms_b = timed_steps(lambda: batch(xs, ws, ys, outs), steps, 2) * 1e3
     batch.check()
+    descs = [dict(xi=p["xi"], n_ft=p["n_ft"], scale=p["scale"], R=p["R"], n_max=p["N"],
+                  m_max=p["M"]) for p in probs]
+    stored = F.Batch(descs, kernel="gauss", T=0.3, materialize=True)
+    stored_out = [torch.empty_like(o) for o in outs]
+    ms_s = timed_steps(lambda: stored(xs, ws, ys, stored_out), steps, 2) * 1e3
+    stored.check()
+    stored.close()
     plans = [F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"], T=0.3,
                     n_max=p["N"], m_max=p["M"]) for p in probs]
     plain_out = [torch.empty_like(o) for o in outs]
@@ -242,6 +250,7 @@ def batched_form(steps, log_fn):
     dev = max(float((a - b).abs().max() / (b.abs().max() + 1e-30)) for a, b in zip(outs, plain_out))
     res = {
         "batched": dict(ms_per_step=ms_b, pairs_per_s=pairs / (ms_b * 1e-3), tuning=tuning),
+        "stored_projections": dict(ms_per_step=ms_s, pairs_per_s=pairs / (ms_s * 1e-3)),
         "plain_loop": dict(ms_per_step=ms_p, pairs_per_s=pairs / (ms_p * 1e-3)),
         "speedup_batched_vs_plain": ms_p / ms_b,
         "n_problems": len(probs), "sum_NM": pairs, "P": 256,

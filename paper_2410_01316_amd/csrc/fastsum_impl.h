@@ -132,6 +132,20 @@ hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, cons
                                const WindowArgs& win, double* spart, int64_t ldm,
                                hipStream_t stream);
 
+// Adjoint in the targets on the fused path:
+//   grad_y[m*d + i] = coef * v[m] * sum_p t'_{m,p} (tau xi_p)_i
+// with t' the derivative grid interpolated at the in-kernel projections and
+// the sum over p back-projected on the matrix cores.  Ab: per 16-direction
+// group g, MFMA i (0..3) and 16-coordinate chunk q (DC = ceil(d/16)), 64
+// floats: entry k*16 + m = tau xi_{16g + 4k + i}[16q + m] (zero past P, d).
+// gpart: ceil(P / prange) x ldg x 16 DC floats of partial sums (ldg >= M).
+int64_t fused_grad_tile();    // targets per workgroup
+hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const uint16_t* At,
+                             const float* Ab, int P, GridGeom g, float pscale,
+                             const float* grid_d, int prange, const WindowArgs& win,
+                             float* gpart, int64_t ldg, float coef, const float* v,
+                             float* grad_y, hipStream_t stream);
+
 // ---- batched form: one persistent launch per phase over a task list ----
 
 // Everything one problem of a batch needs on the device.

@@ -1556,6 +1556,147 @@ __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
                              blockIdx.x, blockIdx.y);
 }
 
+// Adjoint in the targets, fused: t'_{m,p}, the derivative grid of direction
+// p interpolated at tau <xi_p, y_m>, is formed in registers exactly as the
+// gather forms t_{m,p}, and back-projected at once on the matrix cores:
+//   G[i][m] += sum over the 16 directions p of a group of (tau xi_p)_i t'_{m,p}
+// as four v_mfma_f32_16x16x4f32 per 16 coordinates.  Lane (c, r) holds t'
+// of directions 4r + i of target c, which is the B operand of MFMA i
+// (k = r, column c) when its A operand holds (tau xi)_{4k + i} (Ab: per
+// group, MFMA i and 16-coordinate chunk dc, lane m + 16k holds
+// tau xi_{16 group + 4k + i}[16 dc + m], zero past P and d).  Workgroup
+// (x, y): kGradTargets targets of tile x, direction range y; writes
+// gpart[(y * ldg + m) * 16 DC + i] (FP32, summed over the ranges by
+// grad_reduce_kernel).
+constexpr int kGradNB = 4;                                   // 16-target batches per wave
+constexpr int kGradTargets = kGatherWaves * kGradNB * 16;
+constexpr int kGradMaxDC = kSplitMaxD / 16;
+
+template <int W, int KB>
+__global__ __launch_bounds__(kGatherBlock) void gather_grad_fused_kernel(
+    const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At,
+    const float* __restrict__ Ab, int DC, int P, GridGeom g, float pscale,
+    const float* __restrict__ grid_d, int prange, int stage, WindowArgs win,
+    float* __restrict__ gpart, int64_t ldg) {
+    extern __shared__ float gls[];                    // 2 x stage floats
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, r = lane >> 4;
+    const int64_t mb = (int64_t)blockIdx.x * kGradTargets;
+    const int64_t tw = (mb + wave * (kGradNB * 16)) / 16;     // wave's first target tile
+    const int p_begin = blockIdx.y * prange;
+    const int p_end = min(P, p_begin + prange);
+    gather_stage(grid_d, p_begin, min(kFuseDirs, p_end - p_begin), g.nr, gls, wave, lane);
+    const int64_t ntiles = (M + 15) / 16;
+    const __amdgpu_buffer_rsrc_t ys =
+        buffer_rsrc(Yt + tw * KB * 2 * (kSplitTileBytes / 2),
+                    max((int64_t)0, min((int64_t)kGradNB, ntiles - tw)) * KB * 2 * kSplitTileBytes);
+    SplitOp<KB> yop[kGradNB];
+#pragma unroll
+    for (int b = 0; b < kGradNB; ++b) load_split<KB>(yop[b], ys, b, lane);
+    f32x4 gacc[kGradNB][kGradMaxDC];
+#pragma unroll
+    for (int b = 0; b < kGradNB; ++b)
+#pragma unroll
+        for (int q = 0; q < kGradMaxDC; ++q) gacc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const WinEval<W> ev(g, win, pscale);
+    auto group = [&](int np, const float* gb, const SplitOp<KB>& dop, int grp) {
+        f32x4 pr[kGradNB];
+#pragma unroll
+        for (int b = 0; b < kGradNB; ++b) pr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+            for (int b = 0; b < kGradNB; ++b)
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.hi[kb], yop[b].lo[kb], pr[b], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < kGradNB; ++b)
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.lo[kb], yop[b].hi[kb], pr[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int b = 0; b < kGradNB; ++b)
+                pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.hi[kb], yop[b].hi[kb], pr[b], 0, 0, 0);
+        // this lane's back-projection operands of the group
+        const float* __restrict__ ag = Ab + (int64_t)grp * 4 * DC * 64 + lane;
+        float abv[kGradMaxDC][4];
+#pragma unroll
+        for (int q = 0; q < kGradMaxDC; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) abv[q][i] = q < DC ? ag[(i * DC + q) * 64] : 0.f;
+#pragma unroll
+        for (int b = 0; b < kGradNB; ++b) {
+            float tv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int dir = 4 * r + i;
+                const float v = interp<W>(pr[b][i], gb + dir * g.nr, ev, win);
+                const unsigned keep = 0u - (unsigned)(dir < np);
+                tv[i] = __uint_as_float(__float_as_uint(v) & keep);
+            }
+#pragma unroll
+            for (int q = 0; q < kGradMaxDC; ++q) {
+                if (q >= DC) break;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    gacc[b][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(abv[q][i], tv[i], gacc[b][q],
+                                                                      0, 0, 0);
+            }
+        }
+    };
+    SplitOp<KB> da, db;
+    load_split<KB>(da, At, p_begin / kFuseDirs, lane);
+    float* buf0 = gls;
+    float* buf1 = gls + stage;
+    for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const int p1 = p0 + kFuseDirs;
+        if (p1 < p_end) {
+            gather_stage(grid_d, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
+            load_split<KB>(db, At, p1 / kFuseDirs, lane);
+        }
+        group(min(kFuseDirs, p_end - p0), buf0, da, p0 / kFuseDirs);
+        if (p1 >= p_end) break;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const int p2 = p1 + kFuseDirs;
+        if (p2 < p_end) {
+            gather_stage(grid_d, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
+            load_split<KB>(da, At, p2 / kFuseDirs, lane);
+        }
+        group(min(kFuseDirs, p_end - p1), buf1, db, p1 / kFuseDirs);
+    }
+    // lane (c, r) holds coordinates 16 q + 4 r + j of target c
+    const int dcp = 16 * DC;
+#pragma unroll
+    for (int b = 0; b < kGradNB; ++b) {
+        const int64_t m = mb + wave * (kGradNB * 16) + 16 * b + c;
+        if (m >= M) continue;
+        float* __restrict__ dst = gpart + ((int64_t)blockIdx.y * ldg + m) * dcp + 4 * r;
+#pragma unroll
+        for (int q = 0; q < kGradMaxDC; ++q) {
+            if (q >= DC) break;
+            *reinterpret_cast<float4*>(dst + 16 * q) =
+                make_float4(gacc[b][q][0], gacc[b][q][1], gacc[b][q][2], gacc[b][q][3]);
+        }
+    }
+}
+
+// grad_y[m * d + i] = coef * v[m] * sum over ranges of gpart[(r * ldg + m) * 16 DC + i]
+__global__ __launch_bounds__(kBlock) void grad_reduce_kernel(
+    const float* __restrict__ gpart, int nrange, int64_t ldg, int DC, int64_t M, int d,
+    float coef, const float* __restrict__ v, float* __restrict__ grad_y) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= M * d) return;
+    const int64_t m = e / d;
+    const int i = (int)(e - m * d);
+    const int dcp = 16 * DC;
+    float s = 0.f;
+    for (int q = 0; q < nrange; ++q) s += gpart[((int64_t)q * ldg + m) * dcp + i];
+    grad_y[e] = coef * v[m] * s;
+}
+
 template <int W, int KB>
 void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Xt,
                            int64_t N, const uint16_t* At, const float* w, int P,
@@ -1579,6 +1720,51 @@ void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint
     }
     hipLaunchKernelGGL((gather_fused_kernel<W, KB>), grid, dim3(kGatherBlock), lds, stream, Yt,
                        M, At, P, g, pscale, gridv, prange, stage, win, spart, ldm);
+}
+
+template <int W, int KB>
+void launch_gather_grad_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Yt,
+                          int64_t M, const uint16_t* At, const float* Ab, int DC, int P,
+                          const GridGeom& g, float pscale, const float* grid_d, int prange,
+                          int stage, const WindowArgs& win, float* gpart, int64_t ldg) {
+    static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_grad_fused_kernel<W, KB>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  2 * kFuseMaxCells * (int)sizeof(float));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((gather_grad_fused_kernel<W, KB>), grid, dim3(kGatherBlock), lds, stream,
+                       Yt, M, At, Ab, DC, P, g, pscale, grid_d, prange, stage, win, gpart, ldg);
+}
+
+int64_t fused_grad_tile() { return kGradTargets; }
+
+hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const uint16_t* At,
+                             const float* Ab, int P, GridGeom g, float pscale,
+                             const float* grid_d, int prange, const WindowArgs& win,
+                             float* gpart, int64_t ldg, float coef, const float* v,
+                             float* grad_y, hipStream_t stream) {
+    if (!fused_supported(d, g.nr) || prange % kFuseDirs != 0 || M > ldg) return hipErrorInvalidValue;
+    using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*,
+                       const float*, int, int, const GridGeom&, float, const float*, int, int,
+                       const WindowArgs&, float*, int64_t);
+    static const L t[3][2] = {{launch_gather_grad_t<4, 1>, launch_gather_grad_t<4, 2>},
+                              {launch_gather_grad_t<6, 1>, launch_gather_grad_t<6, 2>},
+                              {launch_gather_grad_t<8, 1>, launch_gather_grad_t<8, 2>}};
+    const int wi = W == 4 ? 0 : W == 6 ? 1 : W == 8 ? 2 : -1;
+    if (wi < 0) return hipErrorInvalidValue;
+    const int DC = (d + 15) / 16;
+    const int stage = (kFuseDirs * g.nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
+    const int nrange = (P + prange - 1) / prange;
+    dim3 gd((unsigned)((M + kGradTargets - 1) / kGradTargets), (unsigned)nrange);
+    t[wi][split_kblocks(d) - 1](gd, (size_t)2 * stage * sizeof(float), stream, Yt, M, At, Ab, DC, P,
+                                g, pscale, grid_d, prange, stage, win, gpart, ldg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((M * d + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, stream, gpart, nrange, ldg, DC, M, d, coef, v, grad_y);
+    return hipGetLastError();
 }
 
 bool fused_supported(int d, int nr) {

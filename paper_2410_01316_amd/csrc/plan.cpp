@@ -389,6 +389,9 @@ struct fastsum_plan_s {
     uint16_t* xt = nullptr;        // split-f16 tiles of the sources / targets (fused plans)
     uint16_t* yt = nullptr;
     double xi_norm_max = 1.0;      // max_p |xi_p| (range check of the fused path)
+    float* ab = nullptr;           // back-projection operands of the fused adjoint
+    float* gpart = nullptr;        // its per-range partial sums, kGradMaxRanges x ldg x 16 DC
+    int64_t ldg = 0;
     uint16_t* A16 = nullptr;       // BF16 copy, P x dpad64 (zero padded)
     uint16_t* Ahs = nullptr;       // Xi^T split into f16 hi + lo (P x dpad64; d > 64, FP32)
     uint16_t* Als = nullptr;
@@ -428,7 +431,7 @@ void free_plan(fastsum_plan_s* p) {
     for (auto e : p->pool) (void)hipEventDestroy(e);
     void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->A16, p->Ahs, p->Als, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
-                    p->slice_max};
+                    p->slice_max, p->ab, p->gpart};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -523,11 +526,43 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
 // (scaled by 1/R), then the projections tau R <xi, x / R> are computed inside
 // the spreading and gathering kernels.
 //   split(x), split(y) -> spread(x, w) -> fftconv -> gather(y) -> reduce
+// Spread (sources xt, weights w), FFT convolution (and the derivative grids
+// when grid_d is given), gather at the targets yt and reduction into out:
+// one sliced Fourier sum on split operand tiles.
+fastsum_status fused_sum(fastsum_plan_s* pl, const uint16_t* xt, const float* w, int64_t N,
+                         const uint16_t* yt, int64_t M, float* out, float* grid, float* grid_d,
+                         hipStream_t st) {
+    const int P = pl->P;
+    const float pscale = (float)(pl->r.tau * pl->r.p.R);
+    int64_t chunk_len = 0;
+    const int nchunk = chunk_plan(pl, N, fused_chunks(N, P, pl->spread_slots), chunk_len);
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
+        FS_TRY(launch_spread_fused(pl->W, xt, N, pl->d, pl->at, w, P, pl->geom, pscale, nchunk,
+                                   chunk_len, pl->slice_max, pl->win_args, pl->partial, st));
+    }
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
+        FS_TRY(launch_fftconv(pl->partial, nchunk, P, pl->geom, pl->tw, pl->mult,
+                              grid_d ? pl->mult_d : nullptr, grid, grid_d, st));
+    }
+    const int prange = pl->tune_dir_range > 0 ? pl->tune_dir_range
+                                              : fused_dir_range(M, P, pl->gather_slots);
+    const int nrange = (P + prange - 1) / prange;
+    pl->last_nchunk = nchunk;
+    pl->last_ngroup = nrange;
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
+        FS_TRY(launch_gather_fused(pl->W, yt, M, pl->d, pl->at, P, pl->geom, pscale, grid,
+                                   prange, pl->win_args, pl->spart, pl->ldm, st));
+    }
+    PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
+    FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, st));
+    return FASTSUM_OK;
+}
+
 fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, int64_t N,
                           const float* y, int64_t M, float* out, hipStream_t st) {
-    const int P = pl->P;
-    const double tauR = pl->r.tau * pl->r.p.R;
-    const float pscale = (float)tauR;
     const float inv_r = (float)(1.0 / pl->r.p.R);
     // |x~| <= tau R for every direction when |x| max|xi| <= R (same slack as
     // the stored path's check of each projection)
@@ -542,31 +577,20 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
             yt = pl->yt;
         }
     }
-    int64_t chunk_len = 0;
-    const int nchunk = chunk_plan(pl, N, fused_chunks(N, P, pl->spread_slots), chunk_len);
-    {
-        PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
-        FS_TRY(launch_spread_fused(pl->W, pl->xt, N, pl->d, pl->at, w, P, pl->geom, pscale, nchunk,
-                                   chunk_len, pl->slice_max, pl->win_args, pl->partial, st));
-    }
-    {
-        PhaseTimer t(pl, FASTSUM_PHASE_FFTCONV, st);
-        FS_TRY(launch_fftconv(pl->partial, nchunk, P, pl->geom, pl->tw, pl->mult, nullptr,
-                              pl->grid, nullptr, st));
-    }
-    const int prange = pl->tune_dir_range > 0 ? pl->tune_dir_range
-                                              : fused_dir_range(M, P, pl->gather_slots);
-    const int nrange = (P + prange - 1) / prange;
-    pl->last_nchunk = nchunk;
-    pl->last_ngroup = nrange;
-    {
-        PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
-        FS_TRY(launch_gather_fused(pl->W, yt, M, pl->d, pl->at, P, pl->geom, pscale, pl->grid,
-                                   prange, pl->win_args, pl->spart, pl->ldm, st));
-    }
-    PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-    FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, st));
-    return FASTSUM_OK;
+    return fused_sum(pl, pl->xt, w, N, yt, M, out, pl->grid,
+                     (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, st);
+}
+
+// direction ranges of the fused adjoint gather: at least three rounds of
+// workgroups when P allows, at most kGradMaxRanges ranges
+constexpr int kGradMaxRanges = 4;
+
+int fused_grad_range(int64_t M, int P, int64_t slots) {
+    const int64_t tiles = (M + fused_grad_tile() - 1) / fused_grad_tile();
+    const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
+    const int64_t want = std::min<int64_t>(kGradMaxRanges, (3 * slots + tiles - 1) / tiles);
+    const int64_t ranges = std::max<int64_t>(1, std::min(groups, want));
+    return (int)round_up((P + ranges - 1) / ranges, kFuseDirs);
 }
 
 fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out, int64_t ld,
@@ -661,8 +685,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     // spreads the targets: size for the larger of the two roles
     pl->nchunk_cap = spread_chunks(cap, P);
     const bool grad = (r.p.flags & FASTSUM_FLAG_GRAD) != 0;
-    pl->fused = !grad && !(r.p.flags & FASTSUM_FLAG_MATERIALIZE) &&
-                r.p.proj == FASTSUM_PROJ_FP32 && fused_supported(pl->d, nr);
+    pl->fused = !(r.p.flags & FASTSUM_FLAG_MATERIALIZE) && r.p.proj == FASTSUM_PROJ_FP32 &&
+                fused_supported(pl->d, nr);
     if (pl->fused) {
         int ncu = 0, sb = 1, gb = 1;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess || ncu < 1)
@@ -694,9 +718,14 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     const bool split_proj = !pl->fused && pl->d > kA64Cols && r.p.proj == FASTSUM_PROJ_FP32;
     if (ok && split_proj)
         ok = dev_alloc(&pl->Ahs, (size_t)P * pl->dpad64) && dev_alloc(&pl->Als, (size_t)P * pl->dpad64);
+    const int DC = (pl->d + 15) / 16;
+    pl->ldg = m_max;
     if (ok && grad)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
-             dev_alloc(&pl->mult_d, (size_t)n) && dev_alloc(&pl->tprime, (size_t)P * pl->ld_y);
+             dev_alloc(&pl->mult_d, (size_t)n) &&
+             (pl->fused ? dev_alloc(&pl->ab, (size_t)gtiles * 4 * DC * 64) &&
+                              dev_alloc(&pl->gpart, (size_t)kGradMaxRanges * pl->ldg * 16 * DC)
+                        : dev_alloc(&pl->tprime, (size_t)P * pl->ld_y));
     if (!ok) { free_plan(pl); return FASTSUM_ENOMEM; }
 
     // tables
@@ -718,6 +747,22 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     }
     std::vector<uint16_t> at, ahs, als;
     if (pl->at) split_dirs_host(xi, pl->d, P, at);
+    // back-projection operands: group g, MFMA i, chunk q, lane k*16 + m
+    std::vector<float> ab;
+    if (pl->ab) {
+        ab.assign((size_t)gtiles * 4 * DC * 64, 0.f);
+        for (int64_t g = 0; g < gtiles; ++g)
+            for (int i = 0; i < 4; ++i)
+                for (int q = 0; q < DC; ++q)
+                    for (int k = 0; k < 4; ++k)
+                        for (int m = 0; m < 16; ++m) {
+                            const int64_t p = 16 * g + 4 * k + i;
+                            const int col = 16 * q + m;
+                            if (p < P && col < pl->d)
+                                ab[(((size_t)g * 4 + i) * DC + q) * 64 + k * 16 + m] =
+                                    A[(size_t)p * pl->dpad + col];
+                        }
+    }
     if (pl->Ahs) {
         ahs.assign((size_t)P * pl->dpad64, 0);
         als.assign((size_t)P * pl->dpad64, 0);
@@ -740,6 +785,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->at)
         e = hipMemcpyAsync(pl->at, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->ab)
+        e = hipMemcpyAsync(pl->ab, ab.data(), ab.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->Ahs)
         e = hipMemcpyAsync(pl->Ahs, ahs.data(), ahs.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->Als)
@@ -816,6 +863,21 @@ fastsum_status fastsum_grad(fastsum_plan pl, const float* grad_s, float* grad_y,
     if (!(pl->r.p.flags & FASTSUM_FLAG_GRAD) || !pl->have_exec) return FASTSUM_ESTATE;
     hipStream_t st = (hipStream_t)stream;
     const int P = pl->P;
+    if (pl->fused) {
+        const uint16_t* yt = pl->last_same ? pl->xt : pl->yt;
+        const int64_t M = pl->last_M, N = pl->last_N;
+        if (grad_y) {
+            PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
+            const int prange = fused_grad_range(M, P, pl->gather_slots);
+            FS_TRY(launch_grad_fused(pl->W, yt, M, pl->d, pl->at, pl->ab, P, pl->geom,
+                                     (float)(pl->r.tau * pl->r.p.R), pl->grid_d, prange,
+                                     pl->win_args, pl->gpart, pl->ldg, (float)(1.0 / P), grad_s,
+                                     grad_y, st));
+        }
+        // K^T v: the sliced Fourier sum with sources y (weights v), targets x
+        if (grad_w) return fused_sum(pl, yt, grad_s, M, pl->xt, N, grad_w, pl->grid_w, nullptr, st);
+        return FASTSUM_OK;
+    }
     const float* yp = pl->last_same ? pl->xproj : pl->yproj;
     const int64_t ldy = pl->last_same ? pl->ld_x : pl->ld_y;
     const int64_t M = pl->last_M, N = pl->last_N;
