@@ -72,10 +72,11 @@ typedef enum {
 /* fastsum_params.flags */
 #define FASTSUM_FLAG_GRAD 1u /* keep what fastsum_grad needs (derivative grids) */
 /* Write the projections tau <xi_p, x_n> to device memory (needed for
- * fastsum_debug_read of which = 0, 1).  Without it, and without
- * FASTSUM_FLAG_GRAD, plans with d <= 64, FP32 projections and
- * 16 * grid_nr <= 16384 compute the projections inside the spreading and
- * gathering kernels and never store them (fastsum_plan_info.fused = 1). */
+ * fastsum_debug_read of which = 0, 1).  Without it, plans with d <= 64,
+ * FP32 projections and 16 * grid_nr <= 16384 compute the projections inside
+ * the spreading and gathering kernels and never store them
+ * (fastsum_plan_info.fused = 1); with FASTSUM_FLAG_GRAD they also form the
+ * adjoint that way. */
 #define FASTSUM_FLAG_MATERIALIZE 2u
 
 /*
@@ -157,9 +158,10 @@ FASTSUM_API void fastsum_destroy(fastsum_plan plan);
  *   x  device, N x d;  w  device, N;  y  device, M x d, may equal x (then the
  *   projections are computed once);  s  device, M (written).
  *   1 <= N <= n_max, 1 <= M <= m_max.
- * Asynchronous on `stream`.  The projections and grids of the call are kept
- * in the plan for a following fastsum_grad.  If a projected point exceeds
- * the bound implied by R a device flag is set (see fastsum_check).
+ * Asynchronous on `stream`.  The projections (fused plans: the split
+ * operand tiles of x and y) and the grids of the call are kept in the plan
+ * for a following fastsum_grad.  If a projected point exceeds the bound
+ * implied by R a device flag is set (see fastsum_check).
  */
 FASTSUM_API fastsum_status fastsum_exec(fastsum_plan plan, const float* x, int64_t N,
                             const float* w, const float* y, int64_t M,
@@ -173,8 +175,11 @@ FASTSUM_API fastsum_status fastsum_exec(fastsum_plan plan, const float* x, int64
  *     of the rescaled 1-D Fourier sum at y~_{m,p} (spectral multiplier 2 pi i k).
  *   grad_w (device, N, or NULL): grad_w[n] = sum_m v_m d s_m / d w_n, the same
  *     sliced Fourier sum with sources and targets exchanged.
- * The inputs of the last exec must still be valid.  Asynchronous.
- * Errors: ESTATE (no exec yet / plan without GRAD), EINVAL.
+ * Fused plans interpolate t' at projections formed in the kernel and
+ * back-project them on the matrix cores, with per-direction-range FP32
+ * partial sums reduced in a second launch; stored plans write t' (P x M)
+ * and back-project it.  The inputs of the last exec must still be valid.
+ * Asynchronous.  Errors: ESTATE (no exec yet / plan without GRAD), EINVAL.
  */
 FASTSUM_API fastsum_status fastsum_grad(fastsum_plan plan, const float* grad_s,
                             float* grad_y, float* grad_w, void* stream);
