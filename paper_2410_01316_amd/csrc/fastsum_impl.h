@@ -37,17 +37,15 @@ struct GridGeom {
 constexpr int kA64Cols = 64;
 hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64, int P,
                               float* out, int64_t ld, float bound, int* flag, hipStream_t stream);
-// Split-f16 MFMA, any d: Ahi, Alo are Xi^T (P x dpad64, unscaled) split into f16
-// hi + lo; x is scaled by inv_r = 1/R while staged and out = pscale * v,
-// pscale = tau R.  FP32-level accuracy.
-hipError_t launch_project_split(const float* X, int64_t N, int d, int dpad64, const uint16_t* Ahi,
-                                const uint16_t* Alo, int P, float inv_r, float pscale, float* out,
+// Tile GEMM, any d: X is first written as operand tiles into xtiles (the
+// tile layout of the fused path below; bf16: one BF16 part per k-block,
+// else f16 hi + lo of x * inv_r), then multiplied with the direction tiles
+// At (bf16: BF16 tau xi; else f16 hi + lo of xi); out = pscale * product.
+// The split form has FP32-level accuracy.
+size_t project_tiles_bytes(int64_t rows, int d, bool bf16);
+hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, const uint16_t* At,
+                                int P, float inv_r, float pscale, uint16_t* xtiles, float* out,
                                 int64_t ld, float bound, int* flag, hipStream_t stream);
-// BF16 MFMA, any d: A is tau * Xi^T in BF16, P x dpad64 (d rounded up to 64,
-// zero padded).
-hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad64,
-                               const uint16_t* A, int P, float* out, int64_t ld,
-                               float bound, int* flag, hipStream_t stream);
 
 // partial[(c*P + p)*nr + j - lo] = sum over sources i of chunk c of
 //   w[i] * window(cell j - u(proj[p*ld + i]))

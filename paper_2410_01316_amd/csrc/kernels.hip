@@ -22,8 +22,6 @@ namespace fastsum {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // window weights
@@ -110,24 +108,19 @@ __device__ __forceinline__ int tap0(float xt, const WinEval<W>& ev, float& sp) {
 constexpr int kProjBM = 64;    // directions per workgroup tile
 constexpr int kProjBN = 128;   // points per workgroup tile (32 per wave)
 constexpr int kProjKC = 32;    // k-chunk staged in LDS (f32)
-constexpr int kProjKCh = 64;   // k-chunk staged in LDS (bf16)
 
 struct ProjSmemF32 {
     float As[kProjBM][kProjKC + 1];
     float Xs[kProjBN][kProjKC + 1];
 };
-struct ProjSmemBF16 {
-    // row stride 72 halves = 144 bytes keeps 16-byte fragment loads aligned
-    __attribute__((aligned(16))) unsigned short As[kProjBM][kProjKCh + 8];
-    __attribute__((aligned(16))) unsigned short Xs[kProjBN][kProjKCh + 8];
-};
 
-__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u)          // inf / nan: keep, quiet nan
-        return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// Two floats to BF16, round to nearest even (one v_cvt_pk_bf16_f32 on
+// gfx950), packed low half first.
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2v){a, b}, bf16x2v));
 }
 
 // The MFMAs compute C^T: acc[bi][bj] holds rows n = wave*32 + bj*16 +
@@ -223,197 +216,6 @@ __device__ __forceinline__ void project_tile_f32(
                     acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
         }
     }
-    project_store(acc, p0, n0, P, N, out, ld, bound, flag);
-}
-
-// Buffer-resource loads shared by the staged projection kernels (the
-// helpers themselves are defined with the fused kernels below).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t proj_rsrc(const void* p, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
-                                             0x00020000);
-}
-
-// Staging of one k-chunk (kProjKCh columns) of a 64-direction x 128-point
-// tile with 16-byte loads from buffer resources: rows past the tile's valid
-// rows read as zero; columns past d read the next row's first elements
-// (zero past the last row), which the zero columns of the direction matrix
-// (row stride dpad64, a multiple of kProjKCh) cancel.  No load is guarded,
-// so none becomes a branch.
-constexpr int kStageX4 = kProjBN * kProjKCh / 4 / kBlock;   // float4 of X per thread
-constexpr int kStageA8 = kProjBM * kProjKCh / 8 / kBlock;   // 8 halves of A per thread
-
-__device__ __forceinline__ void stage_load(f32x4 (&vx)[kStageX4], u16x8 (&va)[kStageA8],
-                                           __amdgpu_buffer_rsrc_t xs, int d,
-                                           __amdgpu_buffer_rsrc_t as, int dpad64, int k0) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int q = 0; q < kStageX4; ++q) {
-        const int e = tid + q * kBlock, r = e >> 4, k = (e & 15) * 4;
-        vx[q] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(xs, (r * d + k0 + k) * 4, 0, 0));
-    }
-#pragma unroll
-    for (int q = 0; q < kStageA8; ++q) {
-        const int e = tid + q * kBlock, r = e >> 3, k = (e & 7) * 8;
-        va[q] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(as, (r * dpad64 + k0 + k) * 2, 0, 0));
-    }
-}
-
-__device__ __forceinline__ void project_tile_bf16(
-    ProjSmemBF16& sm, const float* __restrict__ X, int64_t N, int d, int dpad64,
-    const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
-    float bound, int* __restrict__ flag, int p0, int64_t n0) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    f32x4 acc[4][2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const __amdgpu_buffer_rsrc_t xs = proj_rsrc(X + n0 * d, min((int64_t)kProjBN, N - n0) * d * 4);
-    const __amdgpu_buffer_rsrc_t as =
-        proj_rsrc(A + (int64_t)p0 * dpad64, (int64_t)min(kProjBM, P - p0) * dpad64 * 2);
-    // software pipeline: chunk k0 + KC loads into registers while the MFMAs
-    // of chunk k0 run from LDS
-    f32x4 vx[kStageX4];
-    u16x8 va[kStageA8];
-    stage_load(vx, va, xs, d, as, dpad64, 0);
-    for (int k0 = 0; k0 < d; k0 += kProjKCh) {
-        const int kc = min(kProjKCh, d - k0);
-        __syncthreads();                    // the previous chunk's MFMAs are done with LDS
-#pragma unroll
-        for (int q = 0; q < kStageA8; ++q) {
-            const int e = tid + q * kBlock;
-            *reinterpret_cast<u16x8*>(&sm.As[e >> 3][(e & 7) * 8]) = va[q];
-        }
-#pragma unroll
-        for (int q = 0; q < kStageX4; ++q) {
-            const int e = tid + q * kBlock;
-            u16x4 h;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) h[j] = f32_to_bf16_rne(vx[q][j]);
-            *reinterpret_cast<u16x4*>(&sm.Xs[e >> 4][(e & 15) * 4]) = h;
-        }
-        __syncthreads();
-        if (k0 + kProjKCh < d) stage_load(vx, va, xs, d, as, dpad64, k0 + kProjKCh);
-        for (int ks = 0; ks < kc; ks += 32) {
-            bf16x8 a[4], b[2];
-            const int kk = ks + 8 * (lane >> 4);
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-                a[bi] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sm.As[bi * 16 + (lane & 15)][kk]));
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-                b[bj] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sm.Xs[wave * 32 + bj * 16 + (lane & 15)][kk]));
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[bj], a[bi], acc[bi][bj], 0, 0, 0);
-        }
-    }
-    project_store(acc, p0, n0, P, N, out, ld, bound, flag);
-}
-
-// Split-f16 projection for the stored path: v = <xi_p, x_n / R> with x / R
-// and xi held as f16 hi + lo (hi = f16(v), lo = f16(v - hi)), three
-// v_mfma_f32_16x16x32_f16 per 32 columns (hi hi + hi lo + lo hi, products
-// exact in the FP32 accumulation): FP32-level accuracy at about a fifth of
-// the FP32 MFMA time.  The directions come split from the host (Ahi, Alo:
-// P x dpad64 halves, zero padded); x is split while it is staged.  The stored
-// value is x~ = pscale v, pscale = tau R.
-struct ProjSmemSplit {
-    __attribute__((aligned(16))) unsigned short Ah[kProjBM][kProjKCh + 8];
-    __attribute__((aligned(16))) unsigned short Al[kProjBM][kProjKCh + 8];
-    __attribute__((aligned(16))) unsigned short Xh[kProjBN][kProjKCh + 8];
-    __attribute__((aligned(16))) unsigned short Xl[kProjBN][kProjKCh + 8];
-};
-
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ void project_tile_split(
-    ProjSmemSplit& sm, const float* __restrict__ X, int64_t N, int d, int dpad64,
-    const unsigned short* __restrict__ Ahi, const unsigned short* __restrict__ Alo, int P,
-    float inv_r, float pscale, float* __restrict__ out, int64_t ld, float bound,
-    int* __restrict__ flag, int p0, int64_t n0) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    f32x4 acc[4][2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const __amdgpu_buffer_rsrc_t xs = proj_rsrc(X + n0 * d, min((int64_t)kProjBN, N - n0) * d * 4);
-    const int64_t abytes = (int64_t)min(kProjBM, P - p0) * dpad64 * 2;
-    const __amdgpu_buffer_rsrc_t ahs = proj_rsrc(Ahi + (int64_t)p0 * dpad64, abytes);
-    const __amdgpu_buffer_rsrc_t als = proj_rsrc(Alo + (int64_t)p0 * dpad64, abytes);
-    // software pipeline as in project_tile_bf16; the lo parts of A load
-    // through a second staging pass of the same shape
-    f32x4 vx[kStageX4];
-    u16x8 vah[kStageA8], val[kStageA8];
-    auto load = [&](int k0) {
-        stage_load(vx, vah, xs, d, ahs, dpad64, k0);
-#pragma unroll
-        for (int q = 0; q < kStageA8; ++q) {
-            const int e = tid + q * kBlock, r = e >> 3, k = (e & 7) * 8;
-            val[q] = __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(als, (r * dpad64 + k0 + k) * 2, 0, 0));
-        }
-    };
-    load(0);
-    for (int k0 = 0; k0 < d; k0 += kProjKCh) {
-        const int kc = min(kProjKCh, d - k0);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kStageA8; ++q) {
-            const int e = tid + q * kBlock;
-            *reinterpret_cast<u16x8*>(&sm.Ah[e >> 3][(e & 7) * 8]) = vah[q];
-            *reinterpret_cast<u16x8*>(&sm.Al[e >> 3][(e & 7) * 8]) = val[q];
-        }
-#pragma unroll
-        for (int q = 0; q < kStageX4; ++q) {
-            const int e = tid + q * kBlock;
-            u16x4 hi, lo;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float v = vx[q][j] * inv_r;
-                const _Float16 h = (_Float16)v;
-                hi[j] = __builtin_bit_cast(unsigned short, h);
-                lo[j] = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)h));
-            }
-            *reinterpret_cast<u16x4*>(&sm.Xh[e >> 4][(e & 15) * 4]) = hi;
-            *reinterpret_cast<u16x4*>(&sm.Xl[e >> 4][(e & 15) * 4]) = lo;
-        }
-        __syncthreads();
-        if (k0 + kProjKCh < d) load(k0 + kProjKCh);
-        for (int ks = 0; ks < kc; ks += 32) {
-            f16x8 ah[4], al[4], xh[2], xl[2];
-            const int kk = ks + 8 * (lane >> 4);
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi) {
-                ah[bi] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Ah[bi * 16 + (lane & 15)][kk]));
-                al[bi] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Al[bi * 16 + (lane & 15)][kk]));
-            }
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                xh[bj] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Xh[wave * 32 + bj * 16 + (lane & 15)][kk]));
-                xl[bj] = __builtin_bit_cast(f16x8, *reinterpret_cast<const u16x8*>(&sm.Xl[wave * 32 + bj * 16 + (lane & 15)][kk]));
-            }
-            // C[point][dir]: the small cross terms first
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[bj], al[bi], acc[bi][bj], 0, 0, 0);
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl[bj], ah[bi], acc[bi][bj], 0, 0, 0);
-                }
-#pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh[bj], ah[bi], acc[bi][bj], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] *= pscale;
     project_store(acc, p0, n0, P, N, out, ld, bound, flag);
 }
 
@@ -566,29 +368,6 @@ void launch_xres(dim3 grid, hipStream_t stream, const float* X, int64_t N, int d
                        P, out, ld, bound, flag, prange);
 }
 
-__global__ __launch_bounds__(kBlock) void project_bf16_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad64,
-    const unsigned short* __restrict__ A, int P, float* __restrict__ out, int64_t ld,
-    float bound, int* __restrict__ flag, int ndt, int npt) {
-    __shared__ ProjSmemBF16 sm;
-    int dt, pt;
-    if (!proj_tile_of_block(blockIdx.x, ndt, npt, dt, pt)) return;
-    project_tile_bf16(sm, X, N, d, dpad64, A, P, out, ld, bound, flag, dt * kProjBM,
-                      (int64_t)pt * kProjBN);
-}
-
-__global__ __launch_bounds__(kBlock) void project_split_kernel(
-    const float* __restrict__ X, int64_t N, int d, int dpad64,
-    const unsigned short* __restrict__ Ahi, const unsigned short* __restrict__ Alo, int P,
-    float inv_r, float pscale, float* __restrict__ out, int64_t ld, float bound,
-    int* __restrict__ flag, int ndt, int npt) {
-    __shared__ ProjSmemSplit sm;
-    int dt, pt;
-    if (!proj_tile_of_block(blockIdx.x, ndt, npt, dt, pt)) return;
-    project_tile_split(sm, X, N, d, dpad64, Ahi, Alo, P, inv_r, pscale, out, ld, bound, flag,
-                       dt * kProjBM, (int64_t)pt * kProjBN);
-}
-
 int project_xres_range(int64_t N, int P) {
     const int64_t ntiles = (N + kProjBN - 1) / kProjBN;
     const int64_t ranges = std::max<int64_t>(1, (2048 + ntiles - 1) / ntiles);
@@ -609,27 +388,6 @@ hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64
         launch_xres<9>, launch_xres<10>, launch_xres<11>, launch_xres<12>,
         launch_xres<13>, launch_xres<14>, launch_xres<15>, launch_xres<16>};
     table[(d + 3) / 4 - 1](grid, stream, X, N, d, A64, P, out, ld, bound, flag, prange);
-    return hipGetLastError();
-}
-
-hipError_t launch_project_split(const float* X, int64_t N, int d, int dpad64, const uint16_t* Ahi,
-                                const uint16_t* Alo, int P, float inv_r, float pscale, float* out,
-                                int64_t ld, float bound, int* flag, hipStream_t stream) {
-    const int ndt = (P + kProjBM - 1) / kProjBM, npt = (int)((N + kProjBN - 1) / kProjBN);
-    hipLaunchKernelGGL(project_split_kernel, dim3(proj_grid_blocks(ndt, npt)), dim3(kBlock), 0,
-                       stream, X, N, d, dpad64, Ahi, Alo, P, inv_r, pscale, out, ld, bound, flag,
-                       ndt, npt);
-    return hipGetLastError();
-}
-
-hipError_t launch_project_bf16(const float* X, int64_t N, int d, int dpad64,
-                               const uint16_t* A, int P, float* out, int64_t ld,
-                               float bound, int* flag, hipStream_t stream) {
-    const int ndt = (P + kProjBM - 1) / kProjBM, npt = (int)((N + kProjBN - 1) / kProjBN);
-    dim3 grid(proj_grid_blocks(ndt, npt));
-    hipLaunchKernelGGL(project_bf16_kernel, grid, dim3(kBlock), 0, stream, X, N, d,
-                       dpad64, reinterpret_cast<const unsigned short*>(A), P, out,
-                       ld, bound, flag, ndt, npt);
     return hipGetLastError();
 }
 
@@ -1697,6 +1455,154 @@ __global__ __launch_bounds__(kBlock) void grad_reduce_kernel(
     grad_y[e] = coef * v[m] * s;
 }
 
+// ---------------------------------------------------------------------------
+// stored projections from operand tiles (any d): out[p * ld + n] = pscale *
+// sum_k A[p][k] X[n][k], both operands in the tile layout above with PARTS
+// parts per k-block (2: f16 hi / lo, three v_mfma_f32_16x16x32_f16 per tile
+// pair; 1: BF16, one v_mfma_f32_16x16x32_bf16).  A workgroup of 8 waves owns
+// 8 direction tiles x 16 point tiles (128 x 256); wave w multiplies direction
+// tiles 4 (w & 1) .. +3 with point tiles 4 (w >> 1) .. +3.  The k-blocks
+// stream through three LDS buffers filled by LDS-direct loads (one 1 KB tile
+// part per wave instruction), two k-blocks ahead of the MFMAs, so a wave
+// waits only for the oldest of its two stages in flight.  Per k-block a
+// workgroup moves 24 KB per part and issues 128 (x3) MFMAs.
+// ---------------------------------------------------------------------------
+
+constexpr int kGemmBlock = 512;
+constexpr int kGemmWaves = kGemmBlock / 64;
+constexpr int kGemmDT = 8;                 // direction tiles per workgroup
+constexpr int kGemmPT = 16;                // point tiles per workgroup
+
+template <int PARTS>
+__global__ __launch_bounds__(kGemmBlock) void project_tiles_kernel(
+    const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At, int P, int KB,
+    float pscale, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag,
+    int ndb, int npb) {
+    extern __shared__ __attribute__((aligned(16))) char gsm[];
+    constexpr int kPieces = (kGemmDT + kGemmPT) * PARTS;     // 1 KB pieces per k-block
+    constexpr int kBufBytes = kPieces * kSplitTileBytes;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int db, pb;
+    if (!proj_tile_of_block(blockIdx.x, ndb, npb, db, pb)) return;
+    const int64_t dt0 = (int64_t)db * kGemmDT, pt0 = (int64_t)pb * kGemmPT;
+    const int64_t ndtiles = (P + 15) / 16, nptiles = (N + 15) / 16;
+    // tiles past the ends re-read the last tile (their results are not stored)
+    auto stage = [&](int kb, char* buf) {
+        for (int piece = wave; piece < kPieces; piece += kGemmWaves) {
+            const int t = piece / PARTS, q = piece - t * PARTS;
+            const bool is_dir = t < kGemmDT;
+            const int64_t tile = is_dir ? min(dt0 + t, ndtiles - 1) : min(pt0 + t - kGemmDT, nptiles - 1);
+            const char* src = reinterpret_cast<const char*>(is_dir ? At : Xt) +
+                              ((tile * KB + kb) * PARTS + q) * kSplitTileBytes + lane * 16;
+            __builtin_amdgcn_global_load_lds(src, (lds_void*)(buf + piece * kSplitTileBytes), 16, 0, 0);
+        }
+    };
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int wd = 4 * (wave & 1), wp = kGemmDT + 4 * (wave >> 1);   // first tiles of this wave
+    auto compute = [&](const char* buf) {
+        h8 dop[4][PARTS], xop[4][PARTS];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < PARTS; ++q) {
+                dop[i][q] = *reinterpret_cast<const h8*>(buf + ((wd + i) * PARTS + q) * kSplitTileBytes + lane * 16);
+                xop[i][q] = *reinterpret_cast<const h8*>(buf + ((wp + i) * PARTS + q) * kSplitTileBytes + lane * 16);
+            }
+        // C[point][dir]: lane (c, r) holds points 4r .. 4r+3 of direction c
+        if constexpr (PARTS == 2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xop[j][0], dop[i][1], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xop[j][1], dop[i][0], acc[i][j], 0, 0, 0);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xop[j][0], dop[i][0], acc[i][j], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, xop[j][0]), __builtin_bit_cast(bf16x8, dop[i][0]),
+                        acc[i][j], 0, 0, 0);
+        }
+    };
+    stage(0, gsm);
+    if (KB > 1) stage(1, gsm + kBufBytes);
+    int cur = 0;                               // buffer of k-block kb
+    for (int kb = 0; kb < KB; ++kb) {
+        // this wave's loads of k-block kb have landed (those of kb + 1, the
+        // last 3 * PARTS it issued, may still run); after the barrier every
+        // wave's have, and no wave still reads the buffer of k-block kb - 1,
+        // which k-block kb + 2 goes into
+        if (kb + 1 < KB) {
+            if constexpr (PARTS == 2) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+            else asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        }
+        // a bare s_barrier: __syncthreads() would also wait for the loads
+        // still in flight
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        const int nxt2 = cur == 0 ? 2 : cur - 1;   // (cur + 2) % 3
+        if (kb + 2 < KB) stage(kb + 2, gsm + nxt2 * kBufBytes);
+        compute(gsm + cur * kBufBytes);
+        cur = cur == 2 ? 0 : cur + 1;
+    }
+    const int c = lane & 15, r = lane >> 4;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t p = (dt0 + wd + i) * 16 + c;
+        if (p >= P) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // points past N (zero rows, inside the padded row) are stored too
+            const int64_t n = (pt0 + wp - kGemmDT + j) * 16 + 4 * r;
+            if (n >= nptiles * 16) continue;
+            const f32x4 v = acc[i][j] * pscale;
+            *reinterpret_cast<float4*>(out + p * ld + n) = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bad |= !(fabsf(v[e]) <= bound);
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+// BF16 point tiles (one part per k-block): bf16(Z) in the tile layout
+__global__ __launch_bounds__(kBlock) void bf16_points_kernel(
+    const float* __restrict__ Z, int64_t N, int d, int KB, int64_t ntiles, u32x4* __restrict__ tiles) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id >= ntiles * 64) return;
+    const int lane = (int)(id & 63);
+    const int64_t t = id >> 6, r0 = 16 * t;
+    const int64_t nrows = N - r0 < 16 ? N - r0 : 16;
+    const __amdgpu_buffer_rsrc_t zs = buffer_rsrc(Z + r0 * d, nrows * (int64_t)d * 4);
+    for (int kb = 0; kb < KB; ++kb) {
+        const int col0 = 32 * kb + 8 * (lane >> 4);
+        const int off = ((lane & 15) * d + col0) * 4;
+        const u32x4 va = __builtin_amdgcn_raw_buffer_load_b128(zs, off, 0, 0);
+        const u32x4 vb = __builtin_amdgcn_raw_buffer_load_b128(zs, off + 16, 0, 0);
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            v[e] = col0 + e < d ? __uint_as_float(e < 4 ? va[e] : vb[e - 4]) : 0.f;
+        tiles[(t * KB + kb) * 64 + lane] = u32x4{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]),
+                                                 pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7])};
+    }
+}
+
 template <int W, int KB>
 void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Xt,
                            int64_t N, const uint16_t* At, const float* w, int P,
@@ -1764,6 +1670,47 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((M * d + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, stream, gpart, nrange, ldg, DC, M, d, coef, v, grad_y);
+    return hipGetLastError();
+}
+
+size_t project_tiles_bytes(int64_t rows, int d, bool bf16) {
+    return (size_t)split_tiles_bytes(rows, d) / (bf16 ? 2 : 1);
+}
+
+hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, const uint16_t* At,
+                                int P, float inv_r, float pscale, uint16_t* xtiles, float* out,
+                                int64_t ld, float bound, int* flag, hipStream_t stream) {
+    // three k-block buffers: 144 KB (f16 hi + lo) or 72 KB (BF16) of LDS
+    constexpr int kLds2 = 3 * (kGemmDT + kGemmPT) * 2 * kSplitTileBytes;
+    constexpr int kLds1 = 3 * (kGemmDT + kGemmPT) * kSplitTileBytes;
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&project_tiles_kernel<2>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLds2);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&project_tiles_kernel<1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLds1);
+        attr_set = true;
+    }
+    const int KB = split_kblocks(d);
+    const int64_t ntiles = (N + 15) / 16;
+    const unsigned sb = (unsigned)((ntiles * 64 + kBlock - 1) / kBlock);
+    if (bf16)
+        hipLaunchKernelGGL(bf16_points_kernel, dim3(sb), dim3(kBlock), 0, stream, X, N, d, KB, ntiles,
+                           reinterpret_cast<u32x4*>(xtiles));
+    else   // no range check here: the projections are checked when stored
+        hipLaunchKernelGGL(split_points_kernel, dim3(sb), dim3(kBlock), 0, stream, X, N, d, inv_r,
+                           KB, ntiles, reinterpret_cast<u32x4*>(xtiles), __builtin_inff(), flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int ndb = (P + 16 * kGemmDT - 1) / (16 * kGemmDT);
+    const int npb = (int)((N + 16 * kGemmPT - 1) / (16 * kGemmPT));
+    const dim3 grid(proj_grid_blocks(ndb, npb));
+    if (bf16)
+        hipLaunchKernelGGL(project_tiles_kernel<1>, grid, dim3(kGemmBlock), kLds1, stream, xtiles,
+                           N, At, P, KB, pscale, out, ld, bound, flag, ndb, npb);
+    else
+        hipLaunchKernelGGL(project_tiles_kernel<2>, grid, dim3(kGemmBlock), kLds2, stream, xtiles,
+                           N, At, P, KB, pscale, out, ld, bound, flag, ndb, npb);
     return hipGetLastError();
 }
 

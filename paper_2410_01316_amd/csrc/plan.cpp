@@ -354,6 +354,24 @@ void split_dirs_host(const float* xi, int d, int P, std::vector<uint16_t>& out) 
                 }
 }
 
+// BF16 tiles of tau xi (A: P x dpad, tau xi_p in row p), same layout with
+// one part per k-block; rounded to nearest even.
+void bf16_dirs_host(const std::vector<float>& A, int dpad, int d, int P,
+                    std::vector<uint16_t>& out) {
+    const int KB = split_kblocks(d);
+    const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
+    out.assign((size_t)(groups * KB * kSplitTileBytes / 2), 0);
+    for (int64_t t = 0; t < groups; ++t)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t p = 16 * t + (lane & 15);
+                    const int i = 32 * kb + 8 * (lane >> 4) + e;
+                    const float v = (p < P && i < d) ? A[(size_t)p * dpad + i] : 0.f;
+                    out[(size_t)(t * KB + kb) * (kSplitTileBytes / 2) + 8 * lane + e] = f32_to_bf16_host(v);
+                }
+}
+
 fastsum_status status_of(hipError_t e) {
     if (e == hipSuccess) return FASTSUM_OK;
     if (e == hipErrorOutOfMemory) return FASTSUM_ENOMEM;
@@ -392,9 +410,12 @@ struct fastsum_plan_s {
     float* ab = nullptr;           // back-projection operands of the fused adjoint
     float* gpart = nullptr;        // its per-range partial sums, kGradMaxRanges x ldg x 16 DC
     int64_t ldg = 0;
-    uint16_t* A16 = nullptr;       // BF16 copy, P x dpad64 (zero padded)
-    uint16_t* Ahs = nullptr;       // Xi^T split into f16 hi + lo (P x dpad64; d > 64, FP32)
-    uint16_t* Als = nullptr;
+    // stored projections by the tile GEMM (BF16, or FP32 with d > 64):
+    // direction tiles (BF16 tau xi, or f16 hi / lo of xi) and a point-tile
+    // buffer for one point set at a time
+    bool tile_gemm = false;
+    uint16_t* gdt = nullptr;
+    uint16_t* gpt = nullptr;
     float* xproj = nullptr;
     float* yproj = nullptr;
     float* partial = nullptr;
@@ -429,7 +450,7 @@ void free_plan(fastsum_plan_s* p) {
     if (!p) return;
     for (auto& r : p->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->A16, p->Ahs, p->Als, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
+    void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->gdt, p->gpt, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max, p->ab, p->gpart};
     for (void* b : bufs)
@@ -596,15 +617,17 @@ int fused_grad_range(int64_t M, int P, int64_t slots) {
 fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out, int64_t ld,
                        hipStream_t st) {
     PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
-    if (pl->r.p.proj == FASTSUM_PROJ_BF16)
-        return check(launch_project_bf16(X, N, pl->d, pl->dpad64, pl->A16, pl->P, out, ld,
-                                         pl->bound, pl->flag, st));
-    if (pl->A64)
-        return check(launch_project_f32(X, N, pl->d, pl->A64, pl->P, out, ld, pl->bound,
-                                        pl->flag, st));
-    return check(launch_project_split(X, N, pl->d, pl->dpad64, pl->Ahs, pl->Als, pl->P,
-                                      (float)(1.0 / pl->r.p.R), (float)(pl->r.tau * pl->r.p.R),
-                                      out, ld, pl->bound, pl->flag, st));
+    if (pl->tile_gemm) {
+        // BF16: bf16(x) . bf16(tau xi); FP32: (x / R) . xi split into f16
+        // hi + lo, times tau R
+        const bool bf16 = pl->r.p.proj == FASTSUM_PROJ_BF16;
+        return check(launch_project_tiles(X, N, pl->d, bf16, pl->gdt, pl->P,
+                                          (float)(1.0 / pl->r.p.R),
+                                          bf16 ? 1.f : (float)(pl->r.tau * pl->r.p.R), pl->gpt,
+                                          out, ld, pl->bound, pl->flag, st));
+    }
+    return check(launch_project_f32(X, N, pl->d, pl->A64, pl->P, out, ld, pl->bound, pl->flag,
+                                    st));
 }
 
 }  // namespace
@@ -702,7 +725,6 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     // fused plans store no projections; they keep split operand tiles
     const int64_t gtiles = (P + kFuseDirs - 1) / kFuseDirs;
     bool ok = dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
-              dev_alloc(&pl->A16, (size_t)P * pl->dpad64) &&
               (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
                                dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&
                                dev_alloc(&pl->at, (size_t)split_tiles_bytes(gtiles * kFuseDirs, pl->d) / 2)
@@ -715,9 +737,12 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
               dev_alloc(&pl->flag, 1) && dev_alloc(&pl->slice_max, (size_t)((cap + kSliceLen - 1) / kSliceLen));
     const int64_t p64 = round_up(P, 64);
     if (ok && pl->d <= kA64Cols) ok = dev_alloc(&pl->A64, (size_t)p64 * kA64Cols);
-    const bool split_proj = !pl->fused && pl->d > kA64Cols && r.p.proj == FASTSUM_PROJ_FP32;
-    if (ok && split_proj)
-        ok = dev_alloc(&pl->Ahs, (size_t)P * pl->dpad64) && dev_alloc(&pl->Als, (size_t)P * pl->dpad64);
+    pl->tile_gemm = !pl->fused && (pl->d > kA64Cols || r.p.proj == FASTSUM_PROJ_BF16);
+    if (ok && pl->tile_gemm) {
+        const bool bf16 = r.p.proj == FASTSUM_PROJ_BF16;
+        ok = dev_alloc(&pl->gdt, project_tiles_bytes(gtiles * kFuseDirs, pl->d, bf16) / 2) &&
+             dev_alloc(&pl->gpt, project_tiles_bytes(cap, pl->d, bf16) / 2);
+    }
     const int DC = (pl->d + 15) / 16;
     pl->ldg = m_max;
     if (ok && grad)
@@ -732,21 +757,20 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     std::vector<float2> mult, mult_d, tw;
     build_tables(r.p.kernel, pl->d, r.p.scale, r.tau, r.p.n_ft, n, pl->win, mult, mult_d, tw);
     std::vector<float> A((size_t)P * pl->dpad, 0.f);
-    std::vector<uint16_t> A16((size_t)P * pl->dpad64, 0);
     for (int p = 0; p < P; ++p)
-        for (int i = 0; i < pl->d; ++i) {
-            const float v = (float)(r.tau * (double)xi[(size_t)i * P + p]);
-            A[(size_t)p * pl->dpad + i] = v;
-            A16[(size_t)p * pl->dpad64 + i] = f32_to_bf16_host(v);
-        }
+        for (int i = 0; i < pl->d; ++i) A[(size_t)p * pl->dpad + i] = (float)(r.tau * (double)xi[(size_t)i * P + p]);
     std::vector<float> A64;
     if (pl->A64) {
         A64.assign((size_t)p64 * kA64Cols, 0.f);
         for (int p = 0; p < P; ++p)
             for (int i = 0; i < pl->d; ++i) A64[(size_t)p * kA64Cols + i] = A[(size_t)p * pl->dpad + i];
     }
-    std::vector<uint16_t> at, ahs, als;
+    std::vector<uint16_t> at, gdt;
     if (pl->at) split_dirs_host(xi, pl->d, P, at);
+    if (pl->gdt) {
+        if (r.p.proj == FASTSUM_PROJ_BF16) bf16_dirs_host(A, pl->dpad, pl->d, P, gdt);
+        else split_dirs_host(xi, pl->d, P, gdt);
+    }
     // back-projection operands: group g, MFMA i, chunk q, lane k*16 + m
     std::vector<float> ab;
     if (pl->ab) {
@@ -763,18 +787,6 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
                                     A[(size_t)p * pl->dpad + col];
                         }
     }
-    if (pl->Ahs) {
-        ahs.assign((size_t)P * pl->dpad64, 0);
-        als.assign((size_t)P * pl->dpad64, 0);
-        for (int p = 0; p < P; ++p)
-            for (int i = 0; i < pl->d; ++i) {
-                const float v = xi[(size_t)i * P + p];
-                const _Float16 hi = (_Float16)v;
-                const _Float16 lo = (_Float16)(v - (float)hi);
-                std::memcpy(&ahs[(size_t)p * pl->dpad64 + i], &hi, 2);
-                std::memcpy(&als[(size_t)p * pl->dpad64 + i], &lo, 2);
-            }
-    }
     pl->xi_norm_max = 0.0;
     for (int p = 0; p < P; ++p) {
         double ss = 0.0;
@@ -787,13 +799,10 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         e = hipMemcpyAsync(pl->at, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->ab)
         e = hipMemcpyAsync(pl->ab, ab.data(), ab.size() * sizeof(float), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && pl->Ahs)
-        e = hipMemcpyAsync(pl->Ahs, ahs.data(), ahs.size() * 2, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && pl->Als)
-        e = hipMemcpyAsync(pl->Als, als.data(), als.size() * 2, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->gdt)
+        e = hipMemcpyAsync(pl->gdt, gdt.data(), gdt.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->A64)
         e = hipMemcpyAsync(pl->A64, A64.data(), A64.size() * sizeof(float), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(pl->A16, A16.data(), A16.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->mult, mult.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(pl->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && grad)

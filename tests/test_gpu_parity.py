@@ -50,8 +50,13 @@ def test_tiny_gauss_d3_full_size():
     assert plan.info()["tau"] == pytest.approx(_tau(cfg), rel=1e-15)
 
 
-def test_projections_match_oracle():
-    cfg = make_config("scale", frac=0.01, P=70)
+@pytest.mark.parametrize("name,frac", [("scale", 0.01), ("precision", 0.002)],
+                         ids=["d50-fp32-mfma", "d784-split-f16-tiles"])
+def test_projections_match_oracle(name, frac):
+    """Stored FP32 projections: d <= 64 by the FP32 MFMA kernel, d = 784 by
+    the tile GEMM on f16 hi + lo operands (25 k-blocks, ragged last one,
+    ragged direction and point tiles)."""
+    cfg = make_config(name, frac=frac, P=70)
     s, plan = _run(cfg, materialize=True)
     assert plan.info()["fused"] == 0
     x, y, w, xi = oracle_inputs(cfg)
@@ -63,6 +68,34 @@ def test_projections_match_oracle():
     scale = tau * cfg["R"]
     assert np.abs(px - ref_x).max() < 2e-6 * scale
     assert np.abs(py - ref_y).max() < 2e-6 * scale
+
+
+def _bf16_rne(a):
+    """float32 -> nearest-even BF16, returned as float64 (finite inputs)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_projections_round_to_nearest_even():
+    """The BF16 form rounds x and tau xi to BF16 (nearest even) and
+    accumulates the exact products in FP32: compare with the FP64 product of
+    the same rounded operands, d = 784 (13 k-chunks, ragged 16-column tail)."""
+    cfg = make_config("precision", frac=0.002, P=70)
+    s, plan = _run(cfg, proj="bf16")
+    assert plan.info()["fused"] == 0
+    x, _, _, xi = oracle_inputs(cfg)
+    tau = _tau(cfg)
+    xb = _bf16_rne(x.astype(np.float32))
+    ab = _bf16_rne((tau * xi).astype(np.float32))
+    ref = (xb @ ab).T
+    px = plan.debug_read(0)
+    scale = np.abs(xb) @ np.abs(ab)
+    err = np.abs(px - ref).max() / scale.max()
+    print("bf16 projection max error / max |x||tau xi| %.2e" % err)
+    # FP32 accumulation of 784 exact products: ~1e-7; another rounding of
+    # the operands (toward zero, say) would leave ~1e-3
+    assert err < 1e-5
 
 
 # Width-4 window on the Laplace kernel: its k^-2 spectrum reaches N_ft/2 where
