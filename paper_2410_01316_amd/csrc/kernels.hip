@@ -888,48 +888,77 @@ hipError_t launch_reduce(const double* spart, int nb, int64_t ldm, int64_t M,
     return hipGetLastError();
 }
 
-constexpr int kBpDim = 32;    // dimensions per pass
-constexpr int kBpP = 64;      // directions staged per LDS pass
-
 // grad_y[m][i] = v[m] * coef * sum_p tprime[p][m] * A[p][i]   (A = tau Xi^T)
+// on the matrix cores: a wave owns 64 targets (four 16-target tiles) x 32
+// coordinates (two 16-coordinate chunks) and steps over the directions four
+// at a time with v_mfma_f32_16x16x4f32 (A operand: t' of target 16 t + c,
+// direction p + k at lane c + 16 k, so each direction row is read as 256
+// contiguous bytes; B operand: A[p + k][16 q + c]).  Lane (c, r) ends with
+// targets 16 t + 4r .. +3 of coordinate 16 q + c.
+constexpr int kBpTiles = 4;     // 16-target tiles per wave
+constexpr int kBpChunks = 2;    // 16-coordinate chunks per wave pass
+constexpr int kBpUnroll = 2;    // direction steps of 4 per loop iteration
+
 __global__ __launch_bounds__(kBlock) void backproject_kernel(
     const float* __restrict__ tprime, int64_t ld, int64_t M, int P, int d,
     const float* __restrict__ A, int dpad, float coef,
     const float* __restrict__ v, float* __restrict__ grad_y) {
-    __shared__ float xs[kBpP][kBpDim];
-    const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int i0 = blockIdx.y * kBpDim;
-    float acc[kBpDim];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 15, k = lane >> 4;
+    const int64_t m0 = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * (16 * kBpTiles);
+    if (m0 >= M) return;                       // whole waves; no barriers below
+    const int i0 = blockIdx.y * (16 * kBpChunks);
+    const int nq = min(kBpChunks, (d - i0 + 15) / 16);
+    f32x4 acc[kBpTiles][kBpChunks];
 #pragma unroll
-    for (int i = 0; i < kBpDim; ++i) acc[i] = 0.f;
-    for (int p0 = 0; p0 < P; p0 += kBpP) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kBpP * kBpDim; e += kBlock) {
-            const int pp = e / kBpDim, ii = e % kBpDim;
-            xs[pp][ii] = (p0 + pp < P && i0 + ii < d) ? A[(int64_t)(p0 + pp) * dpad + i0 + ii] : 0.f;
-        }
-        __syncthreads();
-        if (m < M) {
-            const int np = min(kBpP, P - p0);
-            for (int pp = 0; pp < np; ++pp) {
-                const float t = tprime[(int64_t)(p0 + pp) * ld + m];
+    for (int t = 0; t < kBpTiles; ++t)
 #pragma unroll
-                for (int i = 0; i < kBpDim; ++i) acc[i] = fmaf(t, xs[pp][i], acc[i]);
+        for (int q = 0; q < kBpChunks; ++q) acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int p0 = 0; p0 < P; p0 += 4 * kBpUnroll) {
+        float a[kBpUnroll][kBpTiles], b[kBpUnroll][kBpChunks];
+#pragma unroll
+        for (int u = 0; u < kBpUnroll; ++u) {
+            const int p = p0 + 4 * u + k;
+            const float* __restrict__ row = tprime + (int64_t)p * ld + m0 + c;
+#pragma unroll
+            for (int t = 0; t < kBpTiles; ++t)
+                a[u][t] = (p < P && m0 + 16 * t + c < M) ? row[16 * t] : 0.f;
+#pragma unroll
+            for (int q = 0; q < kBpChunks; ++q) {
+                const int col = i0 + 16 * q + c;
+                b[u][q] = (p < P && col < d) ? A[(int64_t)p * dpad + col] : 0.f;
             }
         }
-    }
-    if (m < M) {
-        const float sv = v[m] * coef;
 #pragma unroll
-        for (int i = 0; i < kBpDim; ++i)
-            if (i0 + i < d) grad_y[m * d + i0 + i] = sv * acc[i];
+        for (int u = 0; u < kBpUnroll; ++u)
+#pragma unroll
+            for (int q = 0; q < kBpChunks; ++q)
+                if (q < nq)
+#pragma unroll
+                    for (int t = 0; t < kBpTiles; ++t)
+                        acc[t][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[u][q], acc[t][q], 0, 0, 0);
     }
+#pragma unroll
+    for (int t = 0; t < kBpTiles; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t m = m0 + 16 * t + 4 * k + j;
+            if (m >= M) continue;
+            const float sv = v[m] * coef;
+#pragma unroll
+            for (int q = 0; q < kBpChunks; ++q) {
+                const int col = i0 + 16 * q + c;
+                if (q < nq && col < d) grad_y[m * d + col] = sv * acc[t][q][j];
+            }
+        }
 }
 
 hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
                               int P, int d, const float* A, int dpad, float coef,
                               const float* v, float* grad_y, hipStream_t stream) {
-    dim3 grid((unsigned)((M + kBlock - 1) / kBlock), (unsigned)((d + kBpDim - 1) / kBpDim));
+    const int64_t waves = (M + 16 * kBpTiles - 1) / (16 * kBpTiles);
+    dim3 grid((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)),
+              (unsigned)((d + 16 * kBpChunks - 1) / (16 * kBpChunks)));
     hipLaunchKernelGGL(backproject_kernel, grid, dim3(kBlock), 0, stream, tprime, ld, M,
                        P, d, A, dpad, coef, v, grad_y);
     return hipGetLastError();
