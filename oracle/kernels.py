@@ -6,6 +6,11 @@ Kernels (Table 'tab:kernels', App. A):
   gauss    F(r) = exp(-r^2 / (2 sigma^2))
   laplace  F(r) = exp(-alpha r),  alpha = 1/scale  (Euclidean norm)
   energy   F(r) = -r  (Riesz kernel with r = 1, 'negative distance')
+  matern32, matern52, matern72
+           Matern with nu = 3/2, 5/2, 7/2 and width beta = scale (Sec. 4.1
+           uses nu = p + 1/2, p in {1, 3}):
+           F(r) = 2^{1-nu}/Gamma(nu) z^nu K_nu(z),  z = sqrt(2 nu) r / beta,
+           which for half-integer nu is exp(-z) times a polynomial in z
 """
 import functools
 from math import lgamma, log, pi, sqrt
@@ -13,7 +18,21 @@ from math import lgamma, log, pi, sqrt
 import mpmath as mp
 import numpy as np
 
-KERNELS = ("gauss", "laplace", "energy")
+KERNELS = ("gauss", "laplace", "energy", "matern32", "matern52", "matern72")
+MATERN_NU = {"matern32": 1.5, "matern52": 2.5, "matern72": 3.5}
+
+
+def _matern_poly(nu):
+    """Coefficients a_j (ascending powers of z) with F = exp(-z) sum_j a_j z^j
+    for nu = p + 1/2:  F = exp(-z) p!/(2p)! sum_{i=0}^{p} (p+i)!/(i!(p-i)!)
+    (2z)^{p-i}  (the half-integer closed form of z^nu K_nu(z))."""
+    from math import factorial
+    p = int(round(nu - 0.5))
+    a = np.zeros(p + 1)
+    for i in range(p + 1):
+        a[p - i] += (factorial(p) / factorial(2 * p) * factorial(p + i)
+                     / (factorial(i) * factorial(p - i)) * 2.0 ** (p - i))
+    return a
 
 
 def basis_F(kernel, r, scale):
@@ -25,6 +44,10 @@ def basis_F(kernel, r, scale):
         return np.exp(-r / scale)
     if kernel == "energy":
         return -r
+    if kernel in MATERN_NU:
+        nu = MATERN_NU[kernel]
+        z = sqrt(2.0 * nu) * r / scale
+        return np.exp(-z) * np.polynomial.polynomial.polyval(z, _matern_poly(nu))
     raise ValueError(kernel)
 
 
@@ -37,6 +60,13 @@ def basis_dF(kernel, r, scale):
         return -basis_F(kernel, r, scale) / scale
     if kernel == "energy":
         return -np.ones_like(r)
+    if kernel in MATERN_NU:
+        # d/dz [exp(-z) q(z)] = exp(-z) (q'(z) - q(z)),  dz/dr = sqrt(2 nu)/beta
+        nu = MATERN_NU[kernel]
+        a = _matern_poly(nu)
+        z = sqrt(2.0 * nu) * r / scale
+        P = np.polynomial.polynomial
+        return (sqrt(2.0 * nu) / scale) * np.exp(-z) * (P.polyval(z, P.polyder(a)) - P.polyval(z, a))
     raise ValueError(kernel)
 
 
@@ -59,7 +89,20 @@ def _log_ft_d(kernel, omega, d, scale):
         return (lgamma((d + 1) / 2.0) + d * log(2.0) + 0.5 * (d - 1) * log(pi)
                 - d * log(alpha)
                 - 0.5 * (d + 1) * np.log1p(4.0 * pi * pi * omega ** 2 / alpha ** 2))
+    if kernel in MATERN_NU:
+        return log_ft_matern(omega, d, scale, MATERN_NU[kernel])
     raise ValueError(f"no classical Fourier transform for {kernel!r}")
+
+
+def log_ft_matern(omega, d, beta, nu):
+    """log F_d[F(||.||)](omega) of the Matern kernel of order nu, any nu > 0
+    (Table 'tab:kernels', column 3):
+    Gamma(nu + d/2) 2^{d/2} pi^{d/2} beta^d / (Gamma(nu) nu^{d/2})
+    * (1 + 2 pi^2 beta^2 omega^2 / nu)^{-(nu + d/2)}."""
+    omega = np.abs(np.asarray(omega, dtype=np.float64))
+    return (lgamma(nu + 0.5 * d) + 0.5 * d * log(2.0) + 0.5 * d * log(pi) + d * log(beta)
+            - lgamma(nu) - 0.5 * d * log(nu)
+            - (nu + 0.5 * d) * np.log1p(2.0 * pi * pi * beta * beta * omega ** 2 / nu))
 
 
 def sliced_ft(kernel, omega, d, scale):
@@ -123,17 +166,24 @@ class SlicedBasis:
     d >= 2: the column-4 expressions of Table 'tab:kernels' evaluated with
     mpmath at high precision on Chebyshev nodes, then interpolated (the
     interpolation error is checked against direct evaluation in the tests).
+    Matern: d = 1 and d = 3 only, where f is exact (f = F, and f = (tF)'
+    from eq. integral_transform at d = 3); the table gives the Matern f only
+    by reference and the parity path needs only its transform.
     """
 
     def __init__(self, kernel, d, scale, t_max, nodes=400):
         self.kernel, self.d, self.scale = kernel, d, float(scale)
         self.t_max = float(t_max)
-        self.exact = d == 1 or kernel == "energy"
+        self.exact = d == 1 or kernel == "energy" or kernel in MATERN_NU
+        if kernel in MATERN_NU and d not in (1, 3):
+            raise NotImplementedError("Matern f is provided for d = 1 and d = 3")
         if not self.exact:
             self._coef = _cheb_table(kernel, d, self.scale, self.t_max, nodes)
 
     def mp_value(self, t):
         """Direct extended-precision evaluation (slow)."""
+        if self.kernel in MATERN_NU:
+            return float(self(t))
         dps = 40 + int(2 * float(t) / self.scale) + self.d
         with mp.workdps(dps):
             if self.kernel == "gauss":
@@ -144,6 +194,8 @@ class SlicedBasis:
         t = np.abs(np.asarray(t, dtype=np.float64))
         if self.kernel == "energy":
             return -energy_cd(self.d) * t
+        if self.kernel in MATERN_NU and self.d == 3:
+            return basis_F(self.kernel, t, self.scale) + t * basis_dF(self.kernel, t, self.scale)
         if self.d == 1:
             return basis_F(self.kernel, t, self.scale)
         if np.any(t > self.t_max * (1 + 1e-12)):
@@ -157,9 +209,8 @@ def _cheb_table(kernel, d, scale, t_max, nodes):
     j = np.arange(nodes)
     z = np.cos(pi * (j + 0.5) / nodes)              # Chebyshev points, 1st kind
     t = 0.5 * (z + 1.0) * t_max
-    dps = 40 + int(2 * t_max / scale) + d
     vals = np.empty(nodes)
-    with mp.workdps(dps):
+    with mp.workdps(40 + int(2 * t_max / scale) + d):
         for i, ti in enumerate(t):
             if kernel == "gauss":
                 vals[i] = float(_f_gauss_mp(ti, d, scale))
@@ -179,8 +230,9 @@ def _cheb_table(kernel, d, scale, t_max, nodes):
 def rescale_tau(kernel, R, scale, T, gmax_factor=5.0):
     """tau = min{T/c, 1/(2 g_max)} with c (here the caller's bound R) =
     max ||x_n|| + max ||y_m|| and g_max = gmax_factor * scale (App. I,
-    Step 1).  The energy kernel does not decay, so only T/R applies; its
-    periodic extension (App. J) is built in fourier_coefficients."""
+    Step 1; Matern as Gauss and Laplace).  The energy kernel does not decay,
+    so only T/R applies; its periodic extension (App. J) is built in
+    fourier_coefficients."""
     if kernel == "energy":
         return T / R
     return min(T / R, 1.0 / (2.0 * gmax_factor * scale))
@@ -190,8 +242,8 @@ def fourier_coefficients(kernel, d, scale, tau, n_ft):
     """c_k, k = 0..K (K = n_ft/2), of the 1-periodic rescaled kernel
     g~(x) = f(|x|/tau) (c_{-k} = c_k since g~ is even and real).
 
-    Gauss, Laplace: by Poisson summation c_k ~ F_1[g~](k) = tau F_1[f(|.|)](tau k)
-    (App. I, Step 2).
+    Gauss, Laplace, Matern: by Poisson summation c_k ~ F_1[g~](k) =
+    tau F_1[f(|.|)](tau k) (App. I, Step 2).
     Energy: g~ is taken as the 1-periodic triangle wave equal to
     -(c_d/tau)|x| on [-1/2, 1/2) (a periodic extension in the sense of
     App. J), whose coefficients are c_0 = -c_d/(4 tau),

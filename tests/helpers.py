@@ -2,7 +2,8 @@
 GPU library and the oracle on the same arrays, and compare."""
 import numpy as np
 
-DEFAULT_T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45}
+DEFAULT_T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45,
+             "matern32": 0.2, "matern52": 0.2, "matern72": 0.2}
 
 
 def rel_l2(a, b):

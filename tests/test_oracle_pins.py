@@ -175,10 +175,77 @@ def test_energy_coefficients_triangle_wave():
 
 
 # ---------------------------------------------------------------------------
+# Matern kernels (Table 'tab:kernels', Matern row; App. I)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel,nu", [("matern32", 1.5), ("matern52", 2.5), ("matern72", 3.5)])
+def test_matern_closed_form_is_the_bessel_form(kernel, nu):
+    # column 2: 2^{1-nu}/Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / beta,
+    # evaluated with the modified Bessel function itself
+    from scipy.special import kv
+    beta = 1.3
+    r = np.array([1e-3, 0.05, 0.4, 1.0, 2.5, 6.0, 15.0])
+    z = sqrt(2 * nu) * r / beta
+    ref = 2 ** (1 - nu) / gamma(nu) * z ** nu * kv(nu, z)
+    assert np.abs(O.basis_F(kernel, r, beta) - ref).max() < 1e-14
+    assert O.basis_F(kernel, 0.0, beta) == 1.0
+
+
+@pytest.mark.parametrize("d", [1, 3, 10, 50])
+def test_matern_half_transform_is_laplace(d):
+    # nu = 1/2 is the Laplace kernel with alpha = 1/beta (Sec. 3 remark); the
+    # Matern column-3 transform must then equal the Laplace one
+    from oracle.kernels import log_ft_matern, _log_ft_d
+    w = np.array([0.0, 1e-3, 0.05, 0.3, 2.0, 9.0])
+    assert np.abs(log_ft_matern(w, d, 1.7, 0.5) - _log_ft_d("laplace", w, d, 1.7)).max() < 1e-12
+
+
+@pytest.mark.parametrize("kernel", ["matern32", "matern52", "matern72"])
+def test_matern_d1_transform_is_numeric_transform_of_F(kernel):
+    # d = 1: slicing is the identity, f = F, so the sliced transform must be
+    # the plain 1-D Fourier transform of F(|x|)
+    from scipy.integrate import quad
+    beta = 1.3
+    for w in [0.0, 0.02, 0.1, 0.25, 0.6]:
+        g = lambda x: float(O.basis_F(kernel, x, beta))
+        if w == 0.0:
+            ref = 2 * quad(g, 0, np.inf, epsabs=1e-13)[0]
+        else:
+            ref = 2 * quad(g, 0, np.inf, weight="cos", wvar=2 * pi * w)[0]
+        assert float(O.sliced_ft(kernel, w, 1, beta)) == pytest.approx(ref, rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("kernel", ["matern32", "matern52", "matern72"])
+def test_matern_d3_transform_is_numeric_transform_of_tF_derivative(kernel):
+    # d = 3: eq. integral_transform gives f = (tF)', whose 1-D transform is
+    # the sliced transform the coefficients are built from
+    from scipy.integrate import quad
+    beta = 0.8
+    g = lambda x: float(O.basis_F(kernel, x, beta) + x * O.basis_dF(kernel, x, beta))
+    for w in [0.03, 0.15, 0.4, 1.0]:
+        ref = 2 * quad(g, 0, np.inf, weight="cos", wvar=2 * pi * w)[0]
+        assert float(O.sliced_ft(kernel, w, 3, beta)) == pytest.approx(ref, rel=1e-8, abs=1e-12)
+    t = np.linspace(0.0, 5.0, 11)
+    b = O.SlicedBasis(kernel, 3, beta, 5.0)
+    assert np.abs(b(t) - np.array([g(v) for v in t])).max() < 1e-14
+
+
+@pytest.mark.parametrize("kernel", ["matern32", "matern72"])
+@pytest.mark.parametrize("d", [3, 50])
+def test_matern_coefficients_sum_to_F0(kernel, d):
+    # sum_k c'_k = g~(0) = f(0) = F(0) = 1 up to truncation and periodisation
+    # at the paper's parameters (T = 0.2, g_max = 5 beta, N_ft = 512)
+    scale, R = 1.0, 3.0
+    tau = O.rescale_tau(kernel, R, scale, 0.2)
+    _, cp = O.truncated_coefficients(O.fourier_coefficients(kernel, d, scale, tau, 512))
+    assert cp.sum() == pytest.approx(1.0, abs=2e-3)
+
+
+# ---------------------------------------------------------------------------
 # O1: the direct sum
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy", "matern32", "matern72"])
 def test_direct_single_coincident_point(kernel):
     x = np.array([[0.3, -1.2, 2.0]])
     s = O.kernel_sum_direct(kernel, x, x, np.array([1.7]), 0.9)
@@ -376,7 +443,7 @@ def test_orthonormal_directions_minimise_symmetric_energy():
 # gradients
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy", "matern32", "matern72"])
 def test_direct_gradient_matches_finite_differences(kernel):
     rng = np.random.default_rng(4)
     x = rng.standard_normal((25, 3))
@@ -393,7 +460,7 @@ def test_direct_gradient_matches_finite_differences(kernel):
             assert fd == pytest.approx(g[m, i], rel=1e-6, abs=1e-8)
 
 
-@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy", "matern52"])
 def test_fourier_gradients_match_finite_differences(kernel):
     rng = np.random.default_rng(6)
     x = rng.standard_normal((20, 4))
@@ -401,7 +468,7 @@ def test_fourier_gradients_match_finite_differences(kernel):
     w = rng.standard_normal(20)
     xi = directions("iid", 4, 7, 3)
     R = 8.0
-    T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45}[kernel]
+    T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45, "matern52": 0.2}[kernel]
     tau = O.rescale_tau(kernel, R, 1.0, T)
     n_ft = 256
     g = O.grad_y_fourier(kernel, x, y, w, xi, 1.0, n_ft, tau)

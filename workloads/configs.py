@@ -23,8 +23,10 @@ from .directions import directions
 # Paper defaults for the rescaling threshold T and the number of Fourier
 # modes N_ft (App. I, Steps 1-2); the energy kernel takes T=0.45 with its
 # periodic extension (App. J).
-DEFAULT_T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45}
-DEFAULT_NFT = {"gauss": 128, "laplace": 1024, "energy": 1024}
+DEFAULT_T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45,
+             "matern32": 0.2, "matern52": 0.2, "matern72": 0.2}
+DEFAULT_NFT = {"gauss": 128, "laplace": 1024, "energy": 1024,
+               "matern32": 512, "matern52": 512, "matern72": 512}
 
 CONFIGS = ("tiny", "scale", "precision", "batched", "mmd")
 
