@@ -58,7 +58,7 @@ def f32dev(a):
 
 def make_plan(cfg, **kw):
     import paper_2410_01316_amd as F
-    T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45}[cfg["kernel"]]
+    T = cfg["T"]                  # App. I threshold of the workload's kernel
     return F.Plan(cfg["xi"], kernel=cfg["kernel"], n_ft=cfg["n_ft"], scale=cfg["scale"],
                   R=cfg["R"], T=T, n_max=cfg["N"], m_max=cfg["M"], **kw)
 
@@ -464,6 +464,12 @@ def main():
         log("bench: form laplace")
         forms["laplace_fp32"] = run_form("laplace", make_config("scale", kernel="laplace"),
                                          fsteps, 2, err_targets=64)
+        for kern in ("matern32", "matern72"):
+            log(f"bench: form {kern}")
+            cfgm = make_config("scale", kernel=kern)
+            cfgm["n_ft"] = 512                  # App. I value for the Matern kernel
+            forms[f"{kern}_fp32"] = run_form(kern, cfgm, fsteps, 2, err_targets=64)
+            del cfgm
         log("bench: form precision (d=784)")
         cfg3 = make_config("precision")
         forms["precision_fp32"] = run_form("precision", cfg3, fsteps, 1, proj="fp32",

@@ -59,7 +59,14 @@ typedef enum {
 typedef enum {
     FASTSUM_GAUSS = 0,   /* F(r) = exp(-r^2 / (2 scale^2))                       */
     FASTSUM_LAPLACE = 1, /* F(r) = exp(-r / scale)   (alpha = 1/scale)            */
-    FASTSUM_ENERGY = 2   /* F(r) = -r  (negative distance, Riesz r = 1)           */
+    FASTSUM_ENERGY = 2,  /* F(r) = -r  (negative distance, Riesz r = 1)           */
+    /* Matern of order nu, width beta = scale:                                  */
+    /*   F(r) = 2^{1-nu}/Gamma(nu) z^nu K_nu(z),  z = sqrt(2 nu) r / beta,       */
+    /* coefficients from the column-3 transform of Table 'tab:kernels'; App. I  */
+    /* defaults T = 0.2, g_max = 5 beta (Sec. 4.1 uses nu = 3/2 and 7/2).       */
+    FASTSUM_MATERN32 = 3,   /* nu = 3/2: F = (1 + z) e^{-z}                     */
+    FASTSUM_MATERN52 = 4,   /* nu = 5/2: F = (1 + z + z^2/3) e^{-z}             */
+    FASTSUM_MATERN72 = 5    /* nu = 7/2: F = (1 + z + 2z^2/5 + z^3/15) e^{-z}   */
 } fastsum_kernel;
 
 /* Arithmetic of the projection X . Xi (the only dense contraction). */

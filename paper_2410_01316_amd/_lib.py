@@ -6,7 +6,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libfastsum.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, EUNSUPPORTED, ESTATE = range(7)
-KERNELS = {"gauss": 0, "laplace": 1, "energy": 2}
+KERNELS = {"gauss": 0, "laplace": 1, "energy": 2, "matern32": 3, "matern52": 4, "matern72": 5}
 PROJ = {"fp32": 0, "bf16": 1}
 FLAG_GRAD = 1
 FLAG_MATERIALIZE = 2

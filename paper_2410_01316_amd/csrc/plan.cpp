@@ -27,10 +27,22 @@ namespace host {
 
 // log of the d-dimensional Fourier transform of F(||.||) at radius w
 // (Table 'tab:kernels', column 3, transform convention of eq. Fourier).
+double matern_nu(int kernel) {
+    return kernel == FASTSUM_MATERN32 ? 1.5 : kernel == FASTSUM_MATERN52 ? 2.5 : 3.5;
+}
+
 double log_ft_d(int kernel, double w, int d, double scale) {
     if (kernel == FASTSUM_GAUSS) {
         const double s2 = scale * scale;
         return 0.5 * d * std::log(2.0 * kPi * s2) - 2.0 * kPi * kPi * s2 * w * w;
+    }
+    if (kernel >= FASTSUM_MATERN32) {
+        // Gamma(nu + d/2) 2^{d/2} pi^{d/2} beta^d / (Gamma(nu) nu^{d/2})
+        //   * (1 + 2 pi^2 beta^2 w^2 / nu)^{-(nu + d/2)}
+        const double nu = matern_nu(kernel), hd = 0.5 * d;
+        return std::lgamma(nu + hd) + hd * std::log(2.0 * kPi) + d * std::log(scale) -
+               std::lgamma(nu) - hd * std::log(nu) -
+               (nu + hd) * std::log1p(2.0 * kPi * kPi * scale * scale * w * w / nu);
     }
     const double alpha = 1.0 / scale;   // Laplace
     return std::lgamma(0.5 * (d + 1)) + d * std::log(2.0) + 0.5 * (d - 1) * std::log(kPi) -
@@ -176,7 +188,7 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 fastsum_status resolve_params(const fastsum_params* in, Resolved& r) {
     if (!in) return FASTSUM_EINVAL;
     fastsum_params p = *in;
-    if (p.kernel < FASTSUM_GAUSS || p.kernel > FASTSUM_ENERGY) return FASTSUM_EINVAL;
+    if (p.kernel < FASTSUM_GAUSS || p.kernel > FASTSUM_MATERN72) return FASTSUM_EINVAL;
     if (p.d < 1 || p.d > 4096 || p.P < 1 || p.P > 65536) return FASTSUM_EINVAL;
     if (p.n_ft < 16 || p.n_ft > 4096 || (p.n_ft % 2)) return FASTSUM_EINVAL;
     // Laplace keeps a k^-2 spectrum up to N_ft/2, where the width-4 window's
@@ -187,7 +199,11 @@ fastsum_status resolve_params(const fastsum_params* in, Resolved& r) {
     if (p.oversample != 2 && p.oversample != 4) return FASTSUM_EINVAL;
     if (p.proj != FASTSUM_PROJ_FP32 && p.proj != FASTSUM_PROJ_BF16) return FASTSUM_EINVAL;
     if (p.flags & ~(FASTSUM_FLAG_GRAD | FASTSUM_FLAG_MATERIALIZE)) return FASTSUM_EINVAL;
-    if (p.T == 0.0) p.T = p.kernel == FASTSUM_GAUSS ? 0.3 : (p.kernel == FASTSUM_LAPLACE ? 0.1 : 0.45);
+    // App. I: T = 0.3 (Gauss), 0.1 (Laplace), 0.2 (Matern); 0.45 for the
+    // energy kernel's periodic extension
+    if (p.T == 0.0)
+        p.T = p.kernel == FASTSUM_GAUSS ? 0.3 : p.kernel == FASTSUM_LAPLACE ? 0.1
+              : p.kernel == FASTSUM_ENERGY ? 0.45 : 0.2;
     if (p.gmax_factor == 0.0) p.gmax_factor = 5.0;
     if (!(p.R > 0.0) || !std::isfinite(p.R)) return FASTSUM_EINVAL;
     if (p.kernel != FASTSUM_ENERGY && (!(p.scale > 0.0) || !std::isfinite(p.scale)))

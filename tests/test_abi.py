@@ -43,9 +43,12 @@ def test_status_strings():
 @pytest.mark.parametrize("kernel,d,scale,R,n_ft", [
     ("gauss", 3, 1.03, 2.0, 128), ("gauss", 50, 20.4, 45.0, 1024),
     ("laplace", 50, 20.4, 45.0, 1024), ("laplace", 10, 0.7, 3.0, 256),
-    ("energy", 784, 1.0, 30.0, 1024), ("energy", 20, 1.0, 10.0, 1024)])
+    ("energy", 784, 1.0, 30.0, 1024), ("energy", 20, 1.0, 10.0, 1024),
+    ("matern32", 3, 0.9, 2.5, 512), ("matern32", 50, 20.4, 45.0, 512),
+    ("matern52", 10, 1.3, 4.0, 512), ("matern72", 50, 20.4, 45.0, 512)])
 def test_host_tables_match_oracle(kernel, d, scale, R, n_ft):
-    T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45}[kernel]
+    T = {"gauss": 0.3, "laplace": 0.1, "energy": 0.45,
+         "matern32": 0.2, "matern52": 0.2, "matern72": 0.2}[kernel]
     tau, ck, ph = F.host_tables(kernel, d, n_ft, R=R, scale=scale, T=T)
     assert tau == pytest.approx(O.rescale_tau(kernel, R, scale, T), rel=1e-15)
     ref = O.fourier_coefficients(kernel, d, scale, tau, n_ft)

@@ -113,6 +113,36 @@ def test_scale_config_reduced(kernel, window_w, tol):
     assert rel_l2(s, s3) < tol
 
 
+@pytest.mark.parametrize("kernel,window_w,tol,mat", [
+    ("matern32", 4, 1e-4, False), ("matern32", 6, 1e-5, False), ("matern52", 4, 1e-4, True),
+    ("matern72", 4, 1e-4, False), ("matern72", 6, 1e-5, True)])
+def test_matern_scale_config_reduced(kernel, window_w, tol, mat):
+    """Matern at the paper's N_ft = 512 (App. I) on the d = 50 mixture: GPU
+    against the FP64 Fourier sum, fused and stored-projection paths."""
+    cfg = make_config("scale", kernel=kernel, frac=0.05, P=40)
+    cfg["n_ft"] = 512
+    s, plan = _run(cfg, window_w=window_w, materialize=mat)
+    assert plan.info()["fused"] == (0 if mat else 1)
+    s3 = _o3(cfg)
+    print(kernel, window_w, "gpu-O3 %.2e" % rel_l2(s, s3))
+    assert rel_l2(s, s3) < tol
+
+
+@pytest.mark.parametrize("kernel", ["matern32", "matern72"])
+def test_matern_tiny_against_direct_sum(kernel):
+    """d = 3 unit-ball workload with 256 distance-QMC directions: the GPU
+    against the FP64 direct sum (the method's slicing error) and the FP64
+    Fourier sum (window and rounding)."""
+    cfg = make_config("tiny", kernel=kernel, P=256)
+    cfg["n_ft"] = 512
+    s, _ = _run(cfg)
+    x, y, w, _ = oracle_inputs(cfg)
+    s1 = O.kernel_sum_direct(kernel, x, y, w, cfg["scale"])
+    e1, e3 = rel_l2(s, s1), rel_l2(s, _o3(cfg))
+    print(kernel, "gpu-O1 %.2e gpu-O3 %.2e" % (e1, e3))
+    assert e3 < 1e-4 and e1 < 1e-3
+
+
 def test_ragged_sizes_odd_P_small_d():
     rng = np.random.default_rng(17)
     d, N, M, P = 7, 777, 1333, 37
