@@ -8,6 +8,7 @@ ABI of include/fastsum.h); this package only marshals arguments.
 """
 from ._lib import FastSumError, load as load_library, LIB_PATH
 from .api import Plan, FastSum, Batch, host_tables, choose_nft
+from .flow import MMDFlow
 
-__all__ = ["Plan", "FastSum", "Batch", "FastSumError", "host_tables", "choose_nft",
+__all__ = ["Plan", "FastSum", "Batch", "MMDFlow", "FastSumError", "host_tables", "choose_nft",
            "load_library", "LIB_PATH"]

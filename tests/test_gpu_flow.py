@@ -1,0 +1,68 @@
+"""MMD gradient flow with momentum (App. MMD flows) on the GPU against the
+same flow run with the FP64 oracle's sliced Fourier gradient."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import directions
+from helpers import rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_gradient(kernel, x, y, xi, scale, n_ft, T, R):
+    N, M = x.shape[0], y.shape[0]
+    z = np.vstack([x, y])
+    w = np.concatenate([np.full(N, 1.0 / N**2), np.full(M, -1.0 / (M * N))])
+    tau = O.rescale_tau(kernel, R, scale, T)
+    return O.grad_y_fourier(kernel, z, x, w, xi, scale, n_ft, tau)
+
+
+@pytest.mark.parametrize("kernel,scale", [("energy", 1.0), ("gauss", 2.0)])
+def test_flow_matches_oracle_flow(kernel, scale):
+    import torch
+    import paper_2410_01316_amd as F
+    rng = np.random.default_rng(21)
+    N, M, d, P, n_ft = 300, 250, 5, 64, 256
+    T = {"energy": 0.45, "gauss": 0.3}[kernel]
+    y = rng.standard_normal((M, d)) * 0.5 + 2.0
+    x0 = rng.standard_normal((N, d))
+    xi = directions("distance", d, P, 5)
+    step, steps = float(N), 6          # the gradient is O(1/N): move O(1) per step
+    flow = F.MMDFlow(to_dev(y)[0], xi, N, kernel=kernel, n_ft=n_ft, scale=scale, T=T,
+                     step=step, momentum=0.9)
+    Rs = []
+    xg = flow.run(to_dev(x0)[0], steps, callback=lambda k, x, R: Rs.append(R))
+    xg = xg.cpu().numpy().astype(np.float64)
+    # the same flow in FP64 with the oracle gradient at the R each step used
+    x, v = x0.astype(np.float32).astype(np.float64), np.zeros_like(x0)
+    yy = y.astype(np.float32).astype(np.float64)
+    xio = xi.astype(np.float32).astype(np.float64)
+    for R in Rs:
+        v = _oracle_gradient(kernel, x, yy, xio, scale, n_ft, T, R) + 0.9 * v
+        x = x - step * v
+    e = rel_l2(xg - x0, x - x0)
+    print(kernel, "displacement rel-L2 %.2e, plan rebuilds %d" % (e, flow.rebuilds))
+    assert e < 1e-4
+    flow.close()
+
+
+def test_flow_decreases_mmd():
+    """The energy MMD (direct FP64 sums) falls along the flow."""
+    import paper_2410_01316_amd as F
+    rng = np.random.default_rng(5)
+    N, M, d = 400, 400, 3
+    y = rng.standard_normal((M, d)) * 0.5 + 1.5
+    x0 = rng.standard_normal((N, d))
+
+    def mmd(x):
+        def k(a, b):
+            return -np.linalg.norm(a[:, None, :] - b[None, :, :], axis=2)
+        return k(x, x).mean() / 2 - k(x, y).mean() + k(y, y).mean() / 2
+
+    flow = F.MMDFlow(to_dev(y)[0], directions("distance", d, 128, 6), N, kernel="energy",
+                     n_ft=512, step=float(N), momentum=0.9)
+    xg = flow.run(to_dev(x0)[0], 30).cpu().numpy().astype(np.float64)
+    print("MMD %.4e -> %.4e" % (mmd(x0), mmd(xg)))
+    assert mmd(xg) < 0.5 * mmd(x0)
+    flow.close()
