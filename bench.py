@@ -266,6 +266,37 @@ def batched_form(steps, log_fn):
     return res
 
 
+def mmd_flow_form(steps, log_fn=None):
+    """MMD flow with momentum at the paper's CIFAR10 shape (App. MMD flows:
+    energy kernel, M = N = 50000, d = 3072, P = 1000, m = 0.9, tau = 1) on a
+    synthetic image-like stand-in for the targets; particles start N(0, I).
+    P < d, so an orthonormal direction set (a minimiser of the symmetric
+    distance energy) serves as the QMC design."""
+    import torch
+    import paper_2410_01316_amd as F
+    from workloads import directions
+    from workloads.points import image_like
+    rng = np.random.default_rng(8)
+    N = M = 50000
+    d, P = 3072, 1000
+    y = torch.from_numpy(image_like(M, d, rng).astype(np.float32)).cuda()
+    x0 = torch.from_numpy(rng.standard_normal((N, d)).astype(np.float32)).cuda()
+    flow = F.MMDFlow(y, directions("orth", d, P, 9), N, kernel="energy", n_ft=1024,
+                     step=1.0, momentum=0.9)
+    x, v = x0.clone(), torch.zeros_like(x0)
+    for _ in range(2):
+        flow.step(x, v)
+    ms = timed_steps(lambda: flow.step(x, v), steps, 0) * 1e3
+    res = dict(ms_per_step=ms, N=N, M=M, d=d, P=P, n_ft=1024, kernel="energy",
+               plan_rebuilds=flow.rebuilds, pairs_per_s=(N + M) * N / (ms * 1e-3),
+               note="one step = fused exec (sources [x; y], targets x) + grad_y + momentum "
+                    "update; synthetic image-like targets stand in for CIFAR10")
+    flow.close()
+    del x, v, x0, y
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,6 +513,8 @@ def main():
                                                fsteps, 2, grad=True)
         forms["mmd_energy_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="energy"),
                                                 fsteps, 2, grad=True)
+        log("bench: form MMD flow (d=3072)")
+        forms["mmd_flow_energy_d3072"] = mmd_flow_form(fsteps)
         log("bench: form batched (256 problems)")
         forms["batched_256"] = batched_form(fsteps, None)
         result["forms"] = forms
