@@ -192,6 +192,20 @@ FASTSUM_API fastsum_status fastsum_grad(fastsum_plan plan, const float* grad_s,
                             float* grad_y, float* grad_w, void* stream);
 
 /*
+ * As fastsum_grad, with the gradient in the sources as well:
+ *   grad_x (device, N x d, or NULL): grad_x[n] = sum_m v_m d s_m / d x_n
+ *     = w_n du/dx(x_n), u(x) = sum_m v_m K(x, y_m) the transposed sliced sum
+ *     (sources y with weights v, targets x) whose derivative grids are
+ *     interpolated at the sources and back-projected as for grad_y.
+ * grad_w and grad_x share that transposed spreading and FFT.  The weights w
+ * of the last exec must still be valid.  Asynchronous.
+ * Errors: ESTATE (no exec yet / plan without GRAD), EINVAL.
+ */
+FASTSUM_API fastsum_status fastsum_grad_xyw(fastsum_plan plan, const float* grad_s,
+                                            float* grad_x, float* grad_y, float* grad_w,
+                                            void* stream);
+
+/*
  * Synchronise the plan's last stream and report device-side conditions:
  * returns ERANGE if an exec since the previous check saw a point outside the
  * plan's bound (results are then unreliable), OK otherwise; clears the flag.

@@ -91,3 +91,25 @@ def grad_w_fourier(kernel, x, y, v, xi, scale, n_ft, tau):
         vhat = np.conj(_adjoint_ndft(yt[:, p], v, ks))      # sum_m v_m e^{+2 pi i k y~}
         g += _ndft(xt[:, p], np.conj(cp * vhat), ks).conj().real
     return g / P
+
+
+def grad_x_fourier(kernel, x, y, w, v, xi, scale, n_ft, tau):
+    """Vector-Jacobian product with respect to the sources:
+    sum_m v_m ds_m/dx_n = w_n (tau/P) sum_p xi_p Re sum_k (-2 pi i k) c'_k
+        exp(-2 pi i k x~_{n,p}) sum_m v_m exp(2 pi i k y~_{m,p})
+    (chain rule through x~ = tau <xi, x> in the source factor of eq.
+    Fourier-slicing)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    d, P = xi.shape
+    ks, cp = _modes(kernel, d, scale, tau, n_ft)
+    xt = project(x, xi, tau)
+    yt = project(y, xi, tau)
+    v = np.asarray(v, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    g = np.zeros((xt.shape[0], d))
+    for p in range(P):
+        vhat = np.conj(_adjoint_ndft(yt[:, p], v, ks))      # sum_m v_m e^{+2 pi i k y~}
+        # sum_k (-2 pi i k) c'_k vhat_k e^{-2 pi i k x~}
+        dx = _ndft(xt[:, p], np.conj(-2j * np.pi * ks * cp * vhat), ks).conj().real
+        g += np.outer(dx, xi[:, p])
+    return g * (tau / P) * w[:, None]

@@ -61,6 +61,7 @@ SIGNATURES = {
     "fastsum_destroy": (None, [_vp]),
     "fastsum_exec": (_st, [_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp]),
     "fastsum_grad": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "fastsum_grad_xyw": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fastsum_check": (_st, [_vp]),
     "fastsum_get_info": (_st, [_vp, ctypes.POINTER(PlanInfo)]),
     "fastsum_host_tables": (_st, [ctypes.POINTER(Params), _vp, _vp, _vp]),

@@ -80,22 +80,23 @@ class Plan:
         self._last = (x, w, y)          # keep the inputs alive for grad
         return out
 
-    def grad(self, grad_s, want_y=True, want_w=True):
-        """(grad_y, grad_w) of the last call for the cotangent grad_s."""
+    def grad(self, grad_s, want_y=True, want_w=True, want_x=False):
+        """(grad_y, grad_w) of the last call for the cotangent grad_s, or
+        (grad_x, grad_y, grad_w) when want_x is set."""
         if self._last is None:
             raise L.FastSumError(L.ESTATE, "grad before exec")
         x, w, y = self._last
         M, N = y.shape[0], x.shape[0]
         _need(grad_s, "grad_s", (M,), self.device)
+        gx = torch.empty((N, self.d), dtype=torch.float32, device=self.device) if want_x else None
         gy = torch.empty((M, self.d), dtype=torch.float32, device=self.device) if want_y else None
         gw = torch.empty(N, dtype=torch.float32, device=self.device) if want_w else None
+        opt = lambda t: _ptr(t) if t is not None else None
         with torch.cuda.device(self.device):
-            st = self._lib.fastsum_grad(self._h, _ptr(grad_s),
-                                        _ptr(gy) if gy is not None else None,
-                                        _ptr(gw) if gw is not None else None,
-                                        _stream_ptr(self.device))
-        L.check(st, "fastsum_grad")
-        return gy, gw
+            st = self._lib.fastsum_grad_xyw(self._h, _ptr(grad_s), opt(gx), opt(gy), opt(gw),
+                                            _stream_ptr(self.device))
+        L.check(st, "fastsum_grad_xyw")
+        return (gx, gy, gw) if want_x else (gy, gw)
 
     # -- diagnostics --------------------------------------------------------
     def check(self):
@@ -155,8 +156,8 @@ class Plan:
 
 
 class FastSum(torch.autograd.Function):
-    """s = FastSum.apply(plan, x, y, w): differentiable in y and w (the plan
-    must be created with grad=True).  The gradient in x is not provided."""
+    """s = FastSum.apply(plan, x, y, w): differentiable in x, y and w (the
+    plan must be created with grad=True)."""
 
     @staticmethod
     def forward(ctx, plan, x, y, w):
@@ -166,9 +167,9 @@ class FastSum(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_s):
         plan = ctx.plan
-        gy, gw = plan.grad(grad_s.contiguous(), want_y=ctx.needs_input_grad[2],
-                           want_w=ctx.needs_input_grad[3])
-        return None, None, gy, gw
+        gx, gy, gw = plan.grad(grad_s.contiguous(), want_y=ctx.needs_input_grad[2],
+                               want_w=ctx.needs_input_grad[3], want_x=ctx.needs_input_grad[1])
+        return None, gx, gy, gw
 
 
 def host_tables(kernel, d, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0, window_w=0,

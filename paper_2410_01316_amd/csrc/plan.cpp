@@ -437,7 +437,9 @@ struct fastsum_plan_s {
     float* partial = nullptr;
     float* grid = nullptr;
     float* grid_d = nullptr;
-    float* grid_w = nullptr;       // grids of the weight adjoint
+    float* grid_w = nullptr;       // grids of the transposed sum (weight and source adjoints)
+    float* grid_wd = nullptr;      // its derivative grids (source adjoint)
+    float* tout = nullptr;         // output of the transposed sum when grad_w is not wanted
     double* spart = nullptr;
     float* tprime = nullptr;
     float2* mult = nullptr;
@@ -468,7 +470,7 @@ void free_plan(fastsum_plan_s* p) {
     for (auto e : p->pool) (void)hipEventDestroy(e);
     void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->gdt, p->gpt, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
-                    p->slice_max, p->ab, p->gpart};
+                    p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -760,13 +762,14 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
              dev_alloc(&pl->gpt, project_tiles_bytes(cap, pl->d, bf16) / 2);
     }
     const int DC = (pl->d + 15) / 16;
-    pl->ldg = m_max;
+    pl->ldg = cap;       // the source adjoint back-projects at the sources
     if (ok && grad)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
+             dev_alloc(&pl->grid_wd, (size_t)P * nr) && dev_alloc(&pl->tout, (size_t)cap) &&
              dev_alloc(&pl->mult_d, (size_t)n) &&
              (pl->fused ? dev_alloc(&pl->ab, (size_t)gtiles * 4 * DC * 64) &&
                               dev_alloc(&pl->gpart, (size_t)kGradMaxRanges * pl->ldg * 16 * DC)
-                        : dev_alloc(&pl->tprime, (size_t)P * pl->ld_y));
+                        : dev_alloc(&pl->tprime, (size_t)P * std::max(pl->ld_x, pl->ld_y)));
     if (!ok) { free_plan(pl); return FASTSUM_ENOMEM; }
 
     // tables
@@ -882,30 +885,43 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
     return FASTSUM_OK;
 }
 
-fastsum_status fastsum_grad(fastsum_plan pl, const float* grad_s, float* grad_y, float* grad_w,
-                            void* stream) {
+fastsum_status fastsum_grad_xyw(fastsum_plan pl, const float* grad_s, float* grad_x, float* grad_y,
+                                float* grad_w, void* stream) {
     if (!pl || !grad_s) return FASTSUM_EINVAL;
     if (!(pl->r.p.flags & FASTSUM_FLAG_GRAD) || !pl->have_exec) return FASTSUM_ESTATE;
     hipStream_t st = (hipStream_t)stream;
     const int P = pl->P;
+    const int64_t M = pl->last_M, N = pl->last_N;
+    const float coef = (float)(1.0 / P);
+    // The transposed sum u(x) = sum_m v_m K(x, y_m) (sources y with weights
+    // v = grad_s, targets x) gives grad_w = u(x) and, through its
+    // derivative grids, grad_x[n] = w_n du/dx(x_n).
+    float* uout = grad_w ? grad_w : pl->tout;
     if (pl->fused) {
         const uint16_t* yt = pl->last_same ? pl->xt : pl->yt;
-        const int64_t M = pl->last_M, N = pl->last_N;
+        const float pscale = (float)(pl->r.tau * pl->r.p.R);
         if (grad_y) {
             PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
-            const int prange = fused_grad_range(M, P, pl->gather_slots);
-            FS_TRY(launch_grad_fused(pl->W, yt, M, pl->d, pl->at, pl->ab, P, pl->geom,
-                                     (float)(pl->r.tau * pl->r.p.R), pl->grid_d, prange,
-                                     pl->win_args, pl->gpart, pl->ldg, (float)(1.0 / P), grad_s,
-                                     grad_y, st));
+            FS_TRY(launch_grad_fused(pl->W, yt, M, pl->d, pl->at, pl->ab, P, pl->geom, pscale,
+                                     pl->grid_d, fused_grad_range(M, P, pl->gather_slots),
+                                     pl->win_args, pl->gpart, pl->ldg, coef, grad_s, grad_y, st));
         }
-        // K^T v: the sliced Fourier sum with sources y (weights v), targets x
-        if (grad_w) return fused_sum(pl, yt, grad_s, M, pl->xt, N, grad_w, pl->grid_w, nullptr, st);
+        if (grad_w || grad_x) {
+            fastsum_status r = fused_sum(pl, yt, grad_s, M, pl->xt, N, uout, pl->grid_w,
+                                         grad_x ? pl->grid_wd : nullptr, st);
+            if (r != FASTSUM_OK) return r;
+        }
+        if (grad_x) {
+            PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
+            FS_TRY(launch_grad_fused(pl->W, pl->xt, N, pl->d, pl->at, pl->ab, P, pl->geom, pscale,
+                                     pl->grid_wd, fused_grad_range(N, P, pl->gather_slots),
+                                     pl->win_args, pl->gpart, pl->ldg, coef, pl->last_w, grad_x,
+                                     st));
+        }
         return FASTSUM_OK;
     }
     const float* yp = pl->last_same ? pl->xproj : pl->yproj;
     const int64_t ldy = pl->last_same ? pl->ld_x : pl->ld_y;
-    const int64_t M = pl->last_M, N = pl->last_N;
     if (grad_y) {
         // t'_{m,p}: interpolate the derivative grids of the last exec
         const int pg = gather_group(M, P, pl->pstage);
@@ -915,16 +931,31 @@ fastsum_status fastsum_grad(fastsum_plan pl, const float* grad_s, float* grad_y,
                                  pl->win_args, nullptr, 0, pl->tprime, pl->ld_y, st));
         }
         PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
-        FS_TRY(launch_backproject(pl->tprime, pl->ld_y, M, P, pl->d, pl->A, pl->dpad,
-                                  (float)(1.0 / P), grad_s, grad_y, st));
+        FS_TRY(launch_backproject(pl->tprime, pl->ld_y, M, P, pl->d, pl->A, pl->dpad, coef, grad_s,
+                                  grad_y, st));
     }
-    if (grad_w) {
-        // K^T v: the same sliced Fourier sum, sources y with weights v, targets x
-        fastsum_status r = sum_pass(pl, yp, ldy, grad_s, M, pl->xproj, pl->ld_x, N, grad_w,
-                                    pl->grid_w, nullptr, st);
+    if (grad_w || grad_x) {
+        fastsum_status r = sum_pass(pl, yp, ldy, grad_s, M, pl->xproj, pl->ld_x, N, uout,
+                                    pl->grid_w, grad_x ? pl->grid_wd : nullptr, st);
         if (r != FASTSUM_OK) return r;
     }
+    if (grad_x) {
+        const int pg = gather_group(N, P, pl->pstage);
+        {
+            PhaseTimer t(pl, FASTSUM_PHASE_GATHER, st);
+            FS_TRY(launch_gather(pl->W, pl->xproj, pl->ld_x, N, P, pl->geom, pl->grid_wd, pg,
+                                 pl->pstage, pl->win_args, nullptr, 0, pl->tprime, pl->ld_x, st));
+        }
+        PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
+        FS_TRY(launch_backproject(pl->tprime, pl->ld_x, N, P, pl->d, pl->A, pl->dpad, coef,
+                                  pl->last_w, grad_x, st));
+    }
     return FASTSUM_OK;
+}
+
+fastsum_status fastsum_grad(fastsum_plan pl, const float* grad_s, float* grad_y, float* grad_w,
+                            void* stream) {
+    return fastsum_grad_xyw(pl, grad_s, nullptr, grad_y, grad_w, stream);
 }
 
 fastsum_status fastsum_check(fastsum_plan pl) {

@@ -147,10 +147,9 @@ def test_fused_adjoint_equals_stored(d, N, M, P, same):
         xd, wd = to_dev(x, w)
         yd = xd if same else to_dev(y)[0]
         plan(xd, wd, yd)
-        gy, gw = plan.grad(to_dev(v)[0])
+        gx, gy, gw = plan.grad(to_dev(v)[0], want_x=True)
         plan.check()
-        res[mat] = (gy.cpu().numpy().astype(np.float64), gw.cpu().numpy().astype(np.float64))
-    ey = rel_l2(res[False][0], res[True][0])
-    ew = rel_l2(res[False][1], res[True][1])
-    print(f"d={d} N={N} M={M} P={P} same={same} grad_y {ey:.2e} grad_w {ew:.2e}")
-    assert ey < 2e-5 and ew < 2e-5
+        res[mat] = [g.cpu().numpy().astype(np.float64) for g in (gy, gw, gx)]
+    ey, ew, ex = [rel_l2(a, b) for a, b in zip(res[False], res[True])]
+    print(f"d={d} N={N} M={M} P={P} same={same} grad_y {ey:.2e} grad_w {ew:.2e} grad_x {ex:.2e}")
+    assert ey < 2e-5 and ew < 2e-5 and ex < 2e-5

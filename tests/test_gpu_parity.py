@@ -242,6 +242,7 @@ def test_gradients_match_oracle(kernel, materialize):
     fused = plan.info()["fused"]
     assert fused == (0 if materialize or kernel == "energy" else 1)
     x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    x.requires_grad_(True)
     y.requires_grad_(True)
     w.requires_grad_(True)
     s = F.FastSum.apply(plan, x, y, w)
@@ -252,8 +253,12 @@ def test_gradients_match_oracle(kernel, materialize):
     tau = _tau(cfg)
     gy_ref = O.grad_y_fourier(kernel, xo, yo, wo, xio, cfg["scale"], cfg["n_ft"], tau) * v[:, None]
     gw_ref = O.grad_w_fourier(kernel, xo, yo, v, xio, cfg["scale"], cfg["n_ft"], tau)
+    gx_ref = O.grad_x_fourier(kernel, xo, yo, wo, v, xio, cfg["scale"], cfg["n_ft"], tau)
     gy = y.grad.cpu().numpy()
     gw = w.grad.cpu().numpy()
-    print(kernel, "grad_y %.2e grad_w %.2e" % (rel_l2(gy, gy_ref), rel_l2(gw, gw_ref)))
+    gx = x.grad.cpu().numpy()
+    print(kernel, "grad_y %.2e grad_w %.2e grad_x %.2e"
+          % (rel_l2(gy, gy_ref), rel_l2(gw, gw_ref), rel_l2(gx, gx_ref)))
     assert rel_l2(gy, gy_ref) < 1e-3
     assert rel_l2(gw, gw_ref) < 1e-4
+    assert rel_l2(gx, gx_ref) < 1e-3

@@ -489,6 +489,33 @@ def test_fourier_gradients_match_finite_differences(kernel):
     assert np.abs(gw - jac.T @ v).max() < 1e-10 * np.abs(jac).max() * np.abs(v).sum()
 
 
+@pytest.mark.parametrize("kernel", ["gauss", "energy", "matern32"])
+def test_source_gradient_matches_finite_differences_and_transposed_sum(kernel):
+    # sum_m v_m s_m differentiated in x_n by central differences of the FP64
+    # Fourier sum; and, the sliced Fourier sum being symmetric in sources and
+    # targets, w_n times the target derivative of the transposed sum
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((12, 3))
+    y = rng.standard_normal((7, 3))
+    w = rng.standard_normal(12)
+    v = rng.standard_normal(7)
+    xi = directions("iid", 3, 5, 8)
+    T = {"gauss": 0.3, "energy": 0.45, "matern32": 0.2}[kernel]
+    tau = O.rescale_tau(kernel, 8.0, 1.0, T)
+    n_ft = 256
+    g = O.grad_x_fourier(kernel, x, y, w, v, xi, 1.0, n_ft, tau)
+    f = lambda xx: v @ O.kernel_sum_fourier(kernel, xx, y, w, xi, 1.0, n_ft, tau)
+    h = 1e-6
+    for n in range(12):
+        for i in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[n, i] += h
+            xm[n, i] -= h
+            assert (f(xp) - f(xm)) / (2 * h) == pytest.approx(g[n, i], rel=1e-6, abs=1e-8)
+    gt = O.grad_y_fourier(kernel, y, x, v, xi, 1.0, n_ft, tau) * w[:, None]
+    assert np.abs(g - gt).max() < 1e-12 * np.abs(g).max()
+
+
 def test_golden_parameters_match_workload_defaults():
     from workloads.configs import DEFAULT_T, DEFAULT_NFT
     rows = [l.split() for l in open(os.path.join(GOLDEN, "app_i_parameters.txt")) if l.strip() and not l.startswith("#")]
