@@ -1,0 +1,143 @@
+"""Parity at the benchmark workloads' full sizes, in the launch shapes the
+benchmark times, on outputs the FP64 oracle can afford: sampled targets,
+subsets of the directions (the estimator is a mean over directions, so a
+plan on a subset is the same computation at full N, M and grid), and
+agreement between the two independent projection paths (split-f16 in the
+fused kernels, FP32 MFMA or tile GEMM in the stored ones)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads.configs import make_config, make_batched
+from helpers import rel_l2, err_scale, gpu_plan, to_dev, oracle_inputs, DEFAULT_T
+
+pytestmark = pytest.mark.gpu
+
+
+def _tau(cfg):
+    return O.rescale_tau(cfg["kernel"], cfg["R"], cfg["scale"], DEFAULT_T[cfg["kernel"]])
+
+
+def _run(cfg, **kw):
+    plan = gpu_plan(cfg, **kw)
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    if cfg.get("same_xy"):
+        y = x
+    s = plan(x, w, y).cpu().numpy().astype(np.float64)
+    plan.check()
+    info = plan.info()
+    plan.close()
+    return s, info
+
+
+def test_scale_full_size():
+    """d = 50, N = M = 60000, N_ft = 1024: 8 directions against the exact
+    FP64 Fourier sum on 64 sampled targets; all 1000 directions, fused
+    against stored projections on every target."""
+    cfg = make_config("scale", dirs="orth")
+    sub = dict(cfg, xi=cfg["xi"][:, :8])
+    s8, info = _run(sub)
+    assert info["fused"] == 1
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(cfg["M"], 64, replace=False))
+    x, y, w, xi = oracle_inputs(sub)
+    s3 = O.kernel_sum_fourier("gauss", x, y[idx], w, xi, cfg["scale"], cfg["n_ft"], _tau(cfg))
+    e3 = rel_l2(s8[idx], s3)
+    s_f, _ = _run(cfg)
+    s_m, info_m = _run(cfg, materialize=True)
+    assert info_m["fused"] == 0
+    ef = rel_l2(s_f, s_m)
+    print("scale full size: 8 dirs gpu-O3 %.2e; fused vs stored (1000 dirs) %.2e" % (e3, ef))
+    assert e3 < 1e-4 and ef < 1e-5
+
+
+@pytest.mark.parametrize("proj", ["fp32", "bf16"])
+def test_precision_full_size(proj):
+    """Energy kernel, d = 784, sources = targets = 2e5 image-like points,
+    P = 2000: against the FP64 direct sum on 24 sampled targets (the
+    slicing error of 2000 orthonormal-block directions is included)."""
+    cfg = make_config("precision")
+    s, info = _run(cfg, proj=proj)
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(cfg["M"], 24, replace=False))
+    x, y, w, _ = oracle_inputs(cfg)
+    s1 = O.kernel_sum_direct("energy", x, y[idx], w, 1.0)
+    sa = O.kernel_sum_direct("energy", x, y[idx], np.abs(w), 1.0)
+    e = err_scale(s[idx], s1, sa)
+    print(proj, "precision full size err_scale vs direct %.2e" % e)
+    assert e < 5e-5
+
+
+@pytest.mark.parametrize("kernel", ["gauss", "energy"])
+def test_mmd_full_size_gradients(kernel):
+    """MMD step at N = 4e5 sources, M = 2e5 targets, d = 20, P = 512.  A plan
+    on 2 of the directions at full N, M against the exact FP64 Fourier
+    gradient on 16 sampled particles; Gauss (fused) against the stored path
+    on all directions and every target; the slicing error of all 512
+    directions against the FP64 direct gradient is printed and bounded."""
+    import torch
+    cfg = make_config("mmd", kernel=kernel)
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    ones = torch.ones(cfg["M"], dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(13)
+    idx = np.sort(rng.choice(cfg["M"], 16, replace=False))
+    xo, yo, wo, xio = oracle_inputs(cfg)
+
+    def grads(c, mat=False):
+        plan = gpu_plan(c, grad=True, materialize=mat)
+        s = plan(x, w, y).cpu().numpy().astype(np.float64)
+        gy, _ = plan.grad(ones, want_y=True, want_w=False)
+        plan.check()
+        fused = plan.info()["fused"]
+        plan.close()
+        return s, gy.cpu().numpy().astype(np.float64), fused
+
+    sub = dict(cfg, xi=cfg["xi"][:, :2])
+    _, g2, _ = grads(sub)
+    g3 = O.grad_y_fourier(kernel, xo, yo[idx], wo, xio[:, :2], cfg["scale"], cfg["n_ft"], _tau(cfg))
+    e3 = rel_l2(g2[idx], g3)
+    s_f, g_f, fused = grads(cfg)
+    assert fused == (1 if kernel == "gauss" else 0)     # the energy grids are too wide to fuse
+    g1 = O.grad_y_direct(kernel, xo, yo[idx], wo, cfg["scale"])
+    e1 = rel_l2(g_f[idx], g1)
+    msg = f"{kernel} mmd full size: 2 dirs grad_y vs O3 {e3:.2e}, 512 dirs vs direct {e1:.2e}"
+    if fused:
+        s_m, g_m, _ = grads(cfg, mat=True)
+        msg += f", fused vs stored s {rel_l2(s_f, s_m):.2e} grad_y {rel_l2(g_f, g_m):.2e}"
+        assert rel_l2(s_f, s_m) < 1e-5 and rel_l2(g_f, g_m) < 1e-4
+    print(msg)
+    assert e3 < 1e-3
+    assert e1 < 0.1
+
+
+def test_batched_full_size():
+    """The 256-problem batch (N, M log-uniform in [1e3, 1e5], d in {3, 10,
+    50}, P = 256): every problem against its own plain plan, and the two
+    smallest against the exact FP64 Fourier sum."""
+    import paper_2410_01316_amd as F
+    probs = make_batched(n_problems=256, P=256)
+    for pr in probs:
+        pr["n_ft"] = F.choose_nft("gauss", pr["d"], pr["R"], scale=pr["scale"], T=0.3,
+                                  candidates=(256, 512, 1024))
+    b = F.Batch([dict(xi=p["xi"], n_ft=p["n_ft"], scale=p["scale"], R=p["R"], n_max=p["N"],
+                      m_max=p["M"]) for p in probs], kernel="gauss", T=0.3)
+    dev = [to_dev(p["x"], p["y"], p["w"]) for p in probs]
+    outs = b([d_[0] for d_ in dev], [d_[2] for d_ in dev], [d_[1] for d_ in dev])
+    b.check()
+    worst = 0.0
+    for p, (x, y, w), s in zip(probs, dev, outs):
+        plan = F.Plan(p["xi"], kernel="gauss", n_ft=p["n_ft"], scale=p["scale"], R=p["R"], T=0.3,
+                      n_max=p["N"], m_max=p["M"])
+        worst = max(worst, rel_l2(s.cpu().numpy(), plan(x, w, y).cpu().numpy()))
+        plan.close()
+    small = sorted(range(len(probs)), key=lambda i: probs[i]["N"] + probs[i]["M"])[:2]
+    e3 = []
+    for i in small:
+        p = probs[i]
+        xo, yo, wo, xio = oracle_inputs(p)
+        tau = O.rescale_tau("gauss", p["R"], p["scale"], 0.3)
+        e3.append(rel_l2(outs[i].cpu().numpy(), O.kernel_sum_fourier("gauss", xo, yo, wo, xio,
+                                                                     p["scale"], p["n_ft"], tau)))
+    print("batched full size: worst vs plain %.2e, smallest vs O3 %s" % (worst, ["%.2e" % e for e in e3]))
+    assert worst < 1e-5 and max(e3) < 1e-4
+    b.close()
