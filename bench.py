@@ -187,6 +187,30 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, e
     res = dict(ms_per_step=round(ms, 4), pairs_per_s=cfg["N"] * cfg["M"] / (ms * 1e-3),
                N=cfg["N"], M=cfg["M"], d=cfg["d"], P=cfg["P"], n_ft=cfg["n_ft"],
                kernel=cfg["kernel"], proj=proj, grad=grad)
+    # per-phase kernel time (HIP events on the launch stream) over 3 more steps
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(3):
+        step()
+    ph = plan.profile_read()
+    plan.profile(False)
+    res["fused"] = plan.info()["fused"]
+    res["phases_us_per_step"] = {k: round(t / 3 * 1e3, 1) for k, (t, c) in ph.items() if c}
+    if not res["fused"] and "project" in res["phases_us_per_step"]:
+        # the stored projection GEMM on the matrix cores: 2 d P flops per
+        # projected point (once when sources = targets)
+        pts = cfg["N"] + (0 if cfg.get("same_xy") else cfg["M"])
+        flops = 2.0 * pts * cfg["d"] * cfg["P"]
+        t = res["phases_us_per_step"]["project"] * 1e-6
+        if proj == "bf16":
+            peak, note = PEAK["bf16_mfma_TFs"], "BF16 MFMA, dense peak"
+        elif cfg["d"] > 64:
+            peak, note = PEAK["f16_mfma_TFs"] / 3, "split-f16: three f16 MFMAs per product, f16 peak / 3"
+        else:
+            peak, note = PEAK["fp32_mfma_TFs"], "FP32 MFMA"
+        res["projection_mfma"] = dict(achieved=flops / t / 1e12, peak=peak, unit="TFLOP/s",
+                                      frac=flops / t / 1e12 / peak, note=note,
+                                      includes="operand-tile writing and the GEMM")
     if err_targets:
         rng = np.random.default_rng(7)
         idx = np.sort(rng.choice(cfg["M"], size=err_targets, replace=False))
