@@ -44,6 +44,9 @@ PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TFs": 157.3, "f16_mfma_TFs": 2500.0,
 # gather W interpolation FMAs
 WINDOW_FLOPS = {"spread": 2 + 1 + 2 * (4 + 2 + 4) + 4, "gather": 2 + 1 + 2 * (4 + 2 + 4) + 2 * 4}
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_01316_amd", "csrc", "kernels.hip")
+# int32 LDS atomic adds per clock per CU that a random-address probe sustains
+# on MI355X (4 consecutive cells per lane, as in spreading)
+LDS_ATOMIC_CEILING = 5.8
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -450,6 +453,15 @@ def main():
         roof["mfma_projection"] = dict(flops_per_launch=pf, achieved=pf / avg_s / 1e12,
                                        unit="TFLOP/s", note="split-f16 operands, 3 f16 MFMAs "
                                        "per FP32-equivalent product; f16 dense peak 2500")
+        if dom == "spread":
+            # the resource that binds spreading: W integer LDS atomics per
+            # (source, direction), against the rate a random-address probe
+            # sustains on this chip
+            rate = 4.0 * N * P / avg_s / (256 * 2.4e9)
+            roof["lds_atomics"] = dict(achieved=rate, ceiling=LDS_ATOMIC_CEILING,
+                                       unit="lane-ops/clk/CU", frac=rate / LDS_ATOMIC_CEILING,
+                                       note="4 ds_add_u32 per (source, direction); ceiling "
+                                            "measured with random addresses")
     phase_report = {}
     for p, (t, c) in phases.items():
         if c:
