@@ -217,6 +217,49 @@ def test_range_flag_set_when_bound_violated():
     plan.check()                          # flag cleared
 
 
+@pytest.mark.parametrize("materialize", [False, True], ids=["fused", "stored"])
+def test_error_paths(materialize):
+    """Points outside R and NaN inputs raise ERANGE from check() (then the
+    flag is clear); invalid sizes are rejected with EINVAL before any launch;
+    grad without GRAD or before an exec is ESTATE."""
+    import ctypes
+    import torch
+    import paper_2410_01316_amd as F
+    from paper_2410_01316_amd import _lib as L
+    cfg = make_config("tiny", frac=0.2)
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    plan = gpu_plan(cfg, R=cfg["R"] * 0.25, materialize=materialize)
+    assert plan.info()["fused"] == (0 if materialize else 1)
+    plan(x, w, y)
+    with pytest.raises(F.FastSumError) as e:
+        plan.check()
+    assert e.value.status == L.ERANGE
+    plan.check()
+    good = gpu_plan(cfg, materialize=materialize)
+    xn = x.clone()
+    xn[3, 1] = float("nan")
+    good(xn, w, y)
+    with pytest.raises(F.FastSumError) as e:
+        good.check()
+    assert e.value.status == L.ERANGE
+    out = torch.empty(y.shape[0], dtype=torch.float32, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    N, M = x.shape[0], y.shape[0]
+    # empty, over capacity, and targets equal to the sources with M != N
+    for n, m, yy in [(0, M, y), (N + 1, M, y), (N, 0, y), (N, M + 1, y), (N, N - 1, x)]:
+        r = good._lib.fastsum_exec(good._h, p(x), n, p(w), p(yy), m, p(out), st)
+        assert r == L.EINVAL, (n, m)
+    with pytest.raises(F.FastSumError) as e:
+        good.grad(torch.ones(M, dtype=torch.float32, device="cuda"))
+    assert e.value.status == L.ESTATE                  # plan without GRAD
+    g = gpu_plan(cfg, grad=True, materialize=materialize)
+    r = g._lib.fastsum_grad(g._h, p(out), None, None, st)
+    assert r == L.ESTATE                               # before any exec
+    torch.cuda.synchronize()
+    good.check()
+
+
 def test_repeated_calls_and_reuse_smaller_inputs():
     cfg = make_config("tiny")
     plan = gpu_plan(cfg)
