@@ -77,6 +77,11 @@ typedef enum {
 } fastsum_precision;
 
 /* fastsum_params.flags */
+/* Results are bitwise reproducible without a flag: spreading adds integers
+ * (fixed point per slice of 4096 sources) and every floating-point sum runs
+ * in a fixed order.  Kernel sums are translation invariant, so a caller who
+ * wants a tighter bound R (App. I Step 1) subtracts a common point from x
+ * and y before the call and passes the centred bound. */
 #define FASTSUM_FLAG_GRAD 1u /* keep what fastsum_grad needs (derivative grids) */
 /* Write the projections tau <xi_p, x_n> to device memory (needed for
  * fastsum_debug_read of which = 0, 1).  Without it, plans with d <= 64,
