@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
 the same seeded inputs.
 
-Bars (derived in the design doc): against the exact non-uniform DFT of the same
+Bars: against the exact non-uniform DFT of the same
 truncated Fourier series (O3) the only differences are the NFFT window error
 (<= 3e-5 rel-L2 measured for W = 4, beta = 2.6 W, oversampling 2; ~1e-6 for
 W = 6) and float32 rounding, so rel-L2 <= 1e-4 (W = 4) and <= 1e-5 (W = 6).
