@@ -170,11 +170,12 @@ def cpu_baseline(cfg, s_gpu, n_sample, seed=123):
                        f"(d={cfg['d']}), {dt:.1f} s"), err, idx, s1
 
 
-def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, err_kind=None):
+def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, err_kind=None,
+             sorting=False):
     """Time one more form; returns a dict (ms, pairs/s, optional error)."""
     import torch
     import oracle as O
-    plan = make_plan(cfg, proj=proj, grad=grad)
+    plan = make_plan(cfg, proj=proj, grad=grad, sorting=sorting)
     x, w = f32dev(cfg["x"]), f32dev(cfg["w"])
     y = x if cfg.get("same_xy") else f32dev(cfg["y"])
     out = torch.empty(cfg["M"], dtype=torch.float32, device="cuda")
@@ -190,6 +191,8 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, e
     res = dict(ms_per_step=round(ms, 4), pairs_per_s=cfg["N"] * cfg["M"] / (ms * 1e-3),
                N=cfg["N"], M=cfg["M"], d=cfg["d"], P=cfg["P"], n_ft=cfg["n_ft"],
                kernel=cfg["kernel"], proj=proj, grad=grad)
+    if sorting:
+        res["one_d_sums"] = "exact, by sorting"
     # per-phase kernel time (HIP events on the launch stream) over 3 more steps
     plan.profile(True)
     plan.profile_read()
@@ -543,12 +546,17 @@ def main():
                                            err_targets=16)
         forms["precision_bf16"] = run_form("precision", cfg3, fsteps, 1, proj="bf16",
                                            err_targets=16)
+        log("bench: form precision, exact 1-D sums by sorting")
+        forms["precision_sorted"] = run_form("precision", cfg3, fsteps, 1, err_targets=16,
+                                             sorting=True)
         del cfg3
         log("bench: form mmd (forward + adjoint)")
         forms["mmd_gauss_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="gauss"),
                                                fsteps, 2, grad=True)
         forms["mmd_energy_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="energy"),
                                                 fsteps, 2, grad=True)
+        forms["mmd_energy_sorted"] = run_form("mmd", make_config("mmd", kernel="energy"),
+                                              fsteps, 2, err_targets=32, sorting=True)
         log("bench: form MMD flow (d=3072)")
         forms["mmd_flow_energy_d3072"] = mmd_flow_form(fsteps)
         log("bench: form batched (256 problems)")

@@ -90,6 +90,20 @@ typedef enum {
  * (fastsum_plan_info.fused = 1); with FASTSUM_FLAG_GRAD they also form the
  * adjoint that way. */
 #define FASTSUM_FLAG_MATERIALIZE 2u
+/* Energy kernel only: compute every 1-D sum exactly by sorting instead of by
+ * Fourier summation (the 1-D method the paper takes for the negative
+ * distance kernel, Sec. 4).  Per direction the projected sources and targets
+ * are sorted together (segmented radix sort) and, in sorted order, FP64
+ * prefix sums W_< of w_n and S_< of w_n x~_n over the sources give
+ * sum_n w_n |x~_n - y~| = y~ (2 W_< - W) - (2 S_< - S) at each target.  The
+ * only approximation left is the slicing (eq. (3)); n_ft, window_w and
+ * oversample are validated but unused.  Stores the projections; not
+ * combinable with FASTSUM_FLAG_GRAD.  The plan needs P * L < 2^32 with
+ * L = round_up(n_max, 64) + round_up(m_max, 64), and about
+ * 4 P L (keys) + 4 P L (sorted keys) + 4 P L (positions) + 8 P L (sort
+ * workspace) + 8 P round_up(max(n_max, m_max), 64) (per-direction sums)
+ * bytes of device memory. */
+#define FASTSUM_FLAG_SORTED 4u
 
 /*
  * Plan parameters.  Zero in an optional field selects the default.
@@ -370,7 +384,8 @@ typedef enum {
     FASTSUM_PHASE_GATHER = 3,      /* window interpolation + FP64 sum over P */
     FASTSUM_PHASE_REDUCE = 4,      /* final FP64 reduction of partial sums   */
     FASTSUM_PHASE_BACKPROJECT = 5, /* grad_y = (tau/P) sum_p xi_p t'_p       */
-    FASTSUM_PHASE_COUNT = 6
+    FASTSUM_PHASE_SORT = 6,        /* sorted plans: sort + prefix-sum pass    */
+    FASTSUM_PHASE_COUNT = 7
 } fastsum_phase;
 
 FASTSUM_API fastsum_status fastsum_profile(fastsum_plan plan, int32_t enable);

@@ -10,7 +10,8 @@ KERNELS = {"gauss": 0, "laplace": 1, "energy": 2, "matern32": 3, "matern52": 4, 
 PROJ = {"fp32": 0, "bf16": 1}
 FLAG_GRAD = 1
 FLAG_MATERIALIZE = 2
-PHASES = ("project", "spread", "fftconv", "gather", "reduce", "backproject")
+FLAG_SORTED = 4
+PHASES = ("project", "spread", "fftconv", "gather", "reduce", "backproject", "sort")
 
 
 class Params(ctypes.Structure):

@@ -31,11 +31,13 @@ def _need(t, name, shape, device):
 class Plan:
     """A fast-summation plan: kernel, directions xi (d x P), grid and window
     parameters, the bound R and workspace for up to n_max sources and m_max
-    targets on one GPU.  See include/fastsum.h for every parameter."""
+    targets on one GPU.  See include/fastsum.h for every parameter.
+    sorting=True (energy kernel) takes the exact 1-D sums by sorting instead
+    of Fourier summation."""
 
     def __init__(self, xi, *, kernel, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0,
                  window_w=0, oversample=0, proj="fp32", grad=False, materialize=False,
-                 n_max, m_max, device=None):
+                 sorting=False, n_max, m_max, device=None):
         lib = L.load()
         xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float32))
         if xi.ndim != 2:
@@ -49,7 +51,8 @@ class Plan:
         self.kernel = kernel
         self.prm = L.Params(self.d, self.P, int(n_ft), int(window_w), int(oversample),
                             L.KERNELS[kernel], L.PROJ[proj],
-                            (L.FLAG_GRAD if grad else 0) | (L.FLAG_MATERIALIZE if materialize else 0),
+                            (L.FLAG_GRAD if grad else 0) | (L.FLAG_MATERIALIZE if materialize else 0)
+                            | (L.FLAG_SORTED if sorting else 0),
                             float(scale), float(T), float(gmax_factor), float(R))
         self.n_max, self.m_max = int(n_max), int(m_max)
         self._h = ctypes.c_void_p()

@@ -144,6 +144,20 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
                              float* gpart, int64_t ldg, float coef, const float* v,
                              float* grad_y, hipStream_t stream);
 
+// ---- exact sliced sums for the energy kernel by sorting (sorted.hip) ----
+// Rows of stride L hold, per direction p, the projections of the N sources
+// in keys_in[p L + i], i < N, and (same_xy == 0) of the M targets at
+// i = yoff + m; entries in [N, yoff) are padding of any value.  Each row's
+// first yoff + M (same_xy: N) entries are sorted (keys_out, vals_out =
+// original positions p L + i) and V[p ldm + m] = coef * sum_n w_n |x~_n - y~_m|
+// is written for every target.  P * L < 2^32.  temp holds
+// sorted_energy_temp_bytes(L, P) bytes.
+size_t sorted_energy_temp_bytes(int64_t L, int P);
+hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,
+                                void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
+                                int M, int same_xy, const float* w, double coef, double* V,
+                                int64_t ldm, hipStream_t stream);
+
 // ---- batched form: one persistent launch per phase over a task list ----
 
 // Everything one problem of a batch needs on the device.

@@ -198,7 +198,12 @@ fastsum_status resolve_params(const fastsum_params* in, Resolved& r) {
     if (p.oversample == 0) p.oversample = 2;
     if (p.oversample != 2 && p.oversample != 4) return FASTSUM_EINVAL;
     if (p.proj != FASTSUM_PROJ_FP32 && p.proj != FASTSUM_PROJ_BF16) return FASTSUM_EINVAL;
-    if (p.flags & ~(FASTSUM_FLAG_GRAD | FASTSUM_FLAG_MATERIALIZE)) return FASTSUM_EINVAL;
+    if (p.flags & ~(FASTSUM_FLAG_GRAD | FASTSUM_FLAG_MATERIALIZE | FASTSUM_FLAG_SORTED))
+        return FASTSUM_EINVAL;
+    // exact 1-D sums by sorting exist for the energy kernel only, forward only
+    if ((p.flags & FASTSUM_FLAG_SORTED) &&
+        (p.kernel != FASTSUM_ENERGY || (p.flags & FASTSUM_FLAG_GRAD)))
+        return FASTSUM_EINVAL;
     // App. I: T = 0.3 (Gauss), 0.1 (Laplace), 0.2 (Matern); 0.45 for the
     // energy kernel's periodic extension
     if (p.T == 0.0)
@@ -410,6 +415,7 @@ struct fastsum_plan_s {
     int64_t n_max = 0, m_max = 0, ld_x = 0, ld_y = 0, ldm = 0;
     int nchunk_cap = 1, pstage = 8, ngroup_cap = 1;
     bool fused = false;               // projections inside spread / gather
+    bool sorted = false;              // exact energy sums by sorting, no Fourier buffers
     bool have_proj = false;           // last exec stored its projections
     int64_t tune_chunk_len = 0;       // fastsum_set_launch overrides (0: rule)
     int64_t spread_slots = 1, gather_slots = 1;   // resident fused workgroups on the device
@@ -447,6 +453,14 @@ struct fastsum_plan_s {
     float2* tw = nullptr;
     int* flag = nullptr;
     float* slice_max = nullptr;    // per-slice max |w| (fixed-point scaling)
+    // sorted plans: rows of stride sort_L, sources at 0, targets at sort_yoff
+    float* keys = nullptr;
+    float* keys_out = nullptr;
+    unsigned int* vals = nullptr;
+    void* sort_temp = nullptr;
+    size_t sort_temp_bytes = 0;
+    double* sv = nullptr;          // per-direction exact sums, P x ldm
+    int64_t sort_L = 0, sort_yoff = 0;
     // last exec
     bool have_exec = false, last_same = false;
     const float* last_x = nullptr;
@@ -470,7 +484,8 @@ void free_plan(fastsum_plan_s* p) {
     for (auto e : p->pool) (void)hipEventDestroy(e);
     void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->gdt, p->gpt, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
-                    p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout};
+                    p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout, p->keys,
+                    p->keys_out, p->vals, p->sort_temp, p->sv};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -648,6 +663,33 @@ fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out
                                     st));
 }
 
+// Sorted plans (energy kernel): project x and y into the rows of the sort,
+// then per direction sort + FP64 prefix sums give
+// -(c_d / tau) sum_n w_n |x~_n - y~_m| = sum_n w_n f(<xi_p, x_n - y_m>)
+// exactly, and the FP64 mean over the directions finishes s.
+fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, int64_t N,
+                           const float* y, int64_t M, float* out, bool same, hipStream_t st) {
+    const int64_t L = pl->sort_L, yoff = pl->sort_yoff;
+    fastsum_status r = project(pl, x, N, pl->keys, L, st);
+    if (r != FASTSUM_OK) return r;
+    if (!same) {
+        r = project(pl, y, M, pl->keys + yoff, L, st);
+        if (r != FASTSUM_OK) return r;
+    }
+    const double coef = -energy_cd(pl->d) / pl->r.tau;
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_SORT, st);
+        FS_TRY(launch_sorted_energy(pl->keys, pl->keys_out, pl->vals, pl->sort_temp,
+                                    pl->sort_temp_bytes, L, pl->P, (int)N, (int)yoff, (int)M,
+                                    same ? 1 : 0, w, coef, pl->sv, pl->ldm, st));
+    }
+    pl->last_nchunk = 0;
+    pl->last_ngroup = pl->P;
+    PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
+    FS_TRY(launch_reduce(pl->sv, pl->P, pl->ldm, M, 1.0 / pl->P, out, st));
+    return FASTSUM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -726,7 +768,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     // spreads the targets: size for the larger of the two roles
     pl->nchunk_cap = spread_chunks(cap, P);
     const bool grad = (r.p.flags & FASTSUM_FLAG_GRAD) != 0;
-    pl->fused = !(r.p.flags & FASTSUM_FLAG_MATERIALIZE) && r.p.proj == FASTSUM_PROJ_FP32 &&
+    pl->fused = !(r.p.flags & (FASTSUM_FLAG_MATERIALIZE | FASTSUM_FLAG_SORTED)) &&
+                r.p.proj == FASTSUM_PROJ_FP32 &&
                 fused_supported(pl->d, nr);
     if (pl->fused) {
         int ncu = 0, sb = 1, gb = 1;
@@ -740,9 +783,28 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
                                            kFusedMaxChunks, (cap + kMaxChunk - 1) / kMaxChunk));
     }
 
-    // fused plans store no projections; they keep split operand tiles
+    pl->sorted = (r.p.flags & FASTSUM_FLAG_SORTED) != 0;
+    if (pl->sorted) {
+        pl->sort_yoff = pl->ld_x;
+        pl->sort_L = pl->ld_x + pl->ld_y;
+        if (pl->sort_L > INT32_MAX || (int64_t)P * pl->sort_L >= ((int64_t)1 << 32)) {
+            delete pl;
+            return FASTSUM_EINVAL;
+        }
+        pl->sort_temp_bytes = sorted_energy_temp_bytes(pl->sort_L, P);
+        if (pl->sort_temp_bytes == 0) { delete pl; return FASTSUM_EDEVICE; }
+    }
+
+    // fused plans store no projections; they keep split operand tiles.
+    // Sorted plans keep the projections in their sort rows and have no grids.
     const int64_t gtiles = (P + kFuseDirs - 1) / kFuseDirs;
-    bool ok = dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
+    const size_t PL = (size_t)P * pl->sort_L;
+    bool ok = pl->sorted
+        ? dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->keys, PL) &&
+              dev_alloc(&pl->keys_out, PL) && dev_alloc(&pl->vals, PL) &&
+              dev_alloc((char**)&pl->sort_temp, pl->sort_temp_bytes) &&
+              dev_alloc(&pl->sv, (size_t)P * pl->ldm) && dev_alloc(&pl->flag, 1)
+        : dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
               (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
                                dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&
                                dev_alloc(&pl->at, (size_t)split_tiles_bytes(gtiles * kFuseDirs, pl->d) / 2)
@@ -822,8 +884,10 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         e = hipMemcpyAsync(pl->gdt, gdt.data(), gdt.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->A64)
         e = hipMemcpyAsync(pl->A64, A64.data(), A64.size() * sizeof(float), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(pl->mult, mult.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(pl->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->mult)
+        e = hipMemcpyAsync(pl->mult, mult.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->tw)
+        e = hipMemcpyAsync(pl->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && grad)
         e = hipMemcpyAsync(pl->mult_d, mult_d.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemsetAsync(pl->flag, 0, sizeof(int), hs);
@@ -846,6 +910,20 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
     const bool same = (x == y);
     if (same && N != M) return FASTSUM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    if (pl->sorted) {
+        fastsum_status r = sorted_pass(pl, x, w, N, y, M, s, same, st);
+        if (r != FASTSUM_OK) return r;
+        pl->have_exec = true;
+        pl->have_proj = true;
+        pl->last_same = same;
+        pl->last_x = x;
+        pl->last_w = w;
+        pl->last_y = y;
+        pl->last_N = N;
+        pl->last_M = M;
+        pl->last_stream = st;
+        return FASTSUM_OK;
+    }
     if (pl->fused) {
         fastsum_status r = fused_pass(pl, x, w, N, y, M, s, st);
         if (r != FASTSUM_OK) return r;
@@ -995,7 +1073,12 @@ fastsum_status fastsum_debug_read(fastsum_plan pl, int32_t which, float* host_ou
     const float* src = nullptr;
     int64_t rows = pl->P, cols = 0, ld = 0;
     if ((which == 0 || which == 1) && !pl->have_proj) return FASTSUM_ESTATE;
-    if (which == 0) { src = pl->xproj; cols = pl->last_N; ld = pl->ld_x; }
+    if (pl->sorted && which == 2) return FASTSUM_ESTATE;
+    if (pl->sorted && (which == 0 || which == 1)) {
+        src = (which == 1 && !pl->last_same) ? pl->keys + pl->sort_yoff : pl->keys;
+        cols = which == 0 ? pl->last_N : pl->last_M;
+        ld = pl->sort_L;
+    } else if (which == 0) { src = pl->xproj; cols = pl->last_N; ld = pl->ld_x; }
     else if (which == 1) {
         src = pl->last_same ? pl->xproj : pl->yproj;
         cols = pl->last_M;
