@@ -327,6 +327,50 @@ def mmd_flow_form(steps, log_fn=None):
     return res
 
 
+def copy_calibration():
+    """A plain 256 MiB device copy: what FETCH_SIZE / WRITE_SIZE read for it
+    calibrates the counters against bytes actually moved."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return a.numel() * 4
+
+
+def form_runners(fsteps):
+    """(name, thunk) of every further form: other kernels, the precision
+    workload, the MMD shapes, the flow and the batched form."""
+    from workloads import make_config
+
+    def matern(kern):
+        cfgm = make_config("scale", kernel=kern)
+        cfgm["n_ft"] = 512                      # App. I value for the Matern kernel
+        return run_form(kern, cfgm, fsteps, 2, err_targets=64)
+
+    def precision(**kw):
+        return run_form("precision", make_config("precision"), fsteps, 1, err_targets=16, **kw)
+
+    def mmd(kernel, **kw):
+        return run_form("mmd", make_config("mmd", kernel=kernel), fsteps, 2, **kw)
+
+    return [
+        ("laplace_fp32", lambda: run_form("laplace", make_config("scale", kernel="laplace"),
+                                          fsteps, 2, err_targets=64)),
+        ("matern32_fp32", lambda: matern("matern32")),
+        ("matern72_fp32", lambda: matern("matern72")),
+        ("precision_fp32", lambda: precision(proj="fp32")),
+        ("precision_bf16", lambda: precision(proj="bf16")),
+        ("precision_sorted", lambda: precision(sorting=True)),
+        ("mmd_gauss_fwd_grad", lambda: mmd("gauss", grad=True)),
+        ("mmd_energy_fwd_grad", lambda: mmd("energy", grad=True)),
+        ("mmd_energy_sorted", lambda: mmd("energy", err_targets=32, sorting=True)),
+        ("mmd_flow_energy_d3072", lambda: mmd_flow_form(fsteps)),
+        ("batched_256", lambda: batched_form(fsteps, None)),
+    ]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,6 +384,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--dirs-cache", default="",
                     help="directory for generated direction sets (reused when present)")
+    ap.add_argument("--form", default="",
+                    help="run only this further form (see form_runners) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -354,6 +400,18 @@ def main():
 
     F.load_library()
     torch.cuda.set_device(0)
+    if args.form:
+        runners = dict(form_runners(max(3, args.steps // 4)))
+        if args.form not in runners:
+            print(f"bench.py: unknown form {args.form!r}; one of {sorted(runners)}",
+                  file=sys.stderr)
+            sys.exit(2)
+        log(f"bench: form {args.form}")
+        res = {"form": args.form, **runners[args.form]()}
+        if args.copy_calibration:
+            res["copy_calibration_bytes"] = copy_calibration()
+        print(json.dumps(res), flush=True)
+        return
     t_start = time.perf_counter()
     log("bench: building inputs (d=50, N=M=60000, 10-component mixture)")
     from workloads.directions import directions
@@ -529,48 +587,14 @@ def main():
     if stored is not None:
         result["stored_projection_path"] = stored
     if not args.no_forms:
-        forms = {}
         fsteps = max(3, args.steps // 4)
-        log("bench: form laplace")
-        forms["laplace_fp32"] = run_form("laplace", make_config("scale", kernel="laplace"),
-                                         fsteps, 2, err_targets=64)
-        for kern in ("matern32", "matern72"):
-            log(f"bench: form {kern}")
-            cfgm = make_config("scale", kernel=kern)
-            cfgm["n_ft"] = 512                  # App. I value for the Matern kernel
-            forms[f"{kern}_fp32"] = run_form(kern, cfgm, fsteps, 2, err_targets=64)
-            del cfgm
-        log("bench: form precision (d=784)")
-        cfg3 = make_config("precision")
-        forms["precision_fp32"] = run_form("precision", cfg3, fsteps, 1, proj="fp32",
-                                           err_targets=16)
-        forms["precision_bf16"] = run_form("precision", cfg3, fsteps, 1, proj="bf16",
-                                           err_targets=16)
-        log("bench: form precision, exact 1-D sums by sorting")
-        forms["precision_sorted"] = run_form("precision", cfg3, fsteps, 1, err_targets=16,
-                                             sorting=True)
-        del cfg3
-        log("bench: form mmd (forward + adjoint)")
-        forms["mmd_gauss_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="gauss"),
-                                               fsteps, 2, grad=True)
-        forms["mmd_energy_fwd_grad"] = run_form("mmd", make_config("mmd", kernel="energy"),
-                                                fsteps, 2, grad=True)
-        forms["mmd_energy_sorted"] = run_form("mmd", make_config("mmd", kernel="energy"),
-                                              fsteps, 2, err_targets=32, sorting=True)
-        log("bench: form MMD flow (d=3072)")
-        forms["mmd_flow_energy_d3072"] = mmd_flow_form(fsteps)
-        log("bench: form batched (256 problems)")
-        forms["batched_256"] = batched_form(fsteps, None)
+        forms = {}
+        for name, run in form_runners(fsteps):
+            log(f"bench: form {name}")
+            forms[name] = run()
         result["forms"] = forms
     if args.copy_calibration:
-        # a plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
-        # calibrates the counters against bytes actually moved
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        result["copy_calibration_bytes"] = a.numel() * 4
+        result["copy_calibration_bytes"] = copy_calibration()
     result["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(result), flush=True)
 

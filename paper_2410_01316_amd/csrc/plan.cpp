@@ -787,7 +787,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     if (pl->sorted) {
         pl->sort_yoff = pl->ld_x;
         pl->sort_L = pl->ld_x + pl->ld_y;
-        if (pl->sort_L > INT32_MAX || (int64_t)P * pl->sort_L >= ((int64_t)1 << 32)) {
+        if (pl->sort_L > INT32_MAX / 2 || (int64_t)P * pl->sort_L >= ((int64_t)1 << 32)) {
             delete pl;
             return FASTSUM_EINVAL;
         }

@@ -18,8 +18,10 @@ namespace fastsum {
 
 namespace {
 
-constexpr int kSortBlock = 256;
-constexpr int kSortItems = 4;        // sorted elements per thread and chunk
+constexpr int kSortBlock = 1024;               // 16 waves per direction
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kSortItems = 8;                  // consecutive sorted keys per thread and chunk
+constexpr int kSortChunk = kSortBlock * kSortItems;
 
 // offset of row p: p * L + add
 struct RowOffset {
@@ -33,89 +35,117 @@ struct RowOffset {
 using OffsetIt = rocprim::transform_iterator<rocprim::counting_iterator<unsigned int>, RowOffset,
                                              unsigned int>;
 
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sa, double* sb) {
-    const int tid = threadIdx.x;
-    sa[tid] = a;
-    sb[tid] = b;
-    __syncthreads();
-    for (int h = kSortBlock / 2; h > 0; h >>= 1) {
-        if (tid < h) {
-            sa[tid] += sa[tid + h];
-            sb[tid] += sb[tid + h];
-        }
-        __syncthreads();
+// rows of ~1e5 keys: one 1024-thread block per segment, 8-bit digits
+using SortConfig = rocprim::segmented_radix_sort_config<8, rocprim::kernel_config<1024, 8>>;
+
+__device__ __forceinline__ double wave_incl_scan(double v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
     }
-    a = sa[0];
-    b = sb[0];
-    __syncthreads();
+    return v;
 }
 
-// One workgroup per direction p.  vals holds, for each sorted key, its
-// position g = p L + i in the unsorted row: i < N is source i, i in
-// [yoff, yoff + M) target i - yoff, anything else padding that is skipped
-// (same_xy: every i < N is source and target i).  Writes
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One workgroup per direction p.  keys_in is the unsorted row (sources at
+// i < N); keys / vals the sorted row with, for each key, its position
+// g = p L + i in the unsorted row: i < N is source i, i in [yoff, yoff + M)
+// target i - yoff, anything else padding that is skipped (same_xy: every
+// i < N is source and target i).  Writes
 // V[p ldm + m] = coef * sum_n w_n |x~_n - y~_m|, coef = -c_d / tau.
+// The writes are scattered (targets in sorted order); the workgroups of
+// different directions run spread over the whole device, which measured
+// faster than grouping the chunks of a few directions per XCD.
 __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
-    const float* __restrict__ keys, const unsigned int* __restrict__ vals, int64_t L, int N,
-    int yoff, int M, int same_xy, const float* __restrict__ w, double coef, double* __restrict__ V,
-    int64_t ldm) {
-    __shared__ double sa[kSortBlock], sb[kSortBlock];
-    const int p = blockIdx.x, tid = threadIdx.x;
+    const float* __restrict__ keys_in, const float* __restrict__ keys,
+    const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M, int same_xy,
+    const float* __restrict__ w, double coef, double* __restrict__ V, int64_t ldm) {
+    __shared__ double sa[2][kSortWaves], sb[2][kSortWaves];
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_tot = same_xy ? N : yoff + M;
     const int64_t base = (int64_t)p * L;
     const float* __restrict__ kr = keys + base;
     const unsigned int* __restrict__ vr = vals + base;
     double* __restrict__ vrow = V + (int64_t)p * ldm;
-    // totals over the sources
+    // totals W = sum w_n and S = sum w_n x~_n over the unsorted sources
     double A = 0.0, B = 0.0;
-    for (int i = tid; i < n_tot; i += kSortBlock) {
-        const int idx = (int)((int64_t)vr[i] - base);
-        if (idx >= 0 && idx < N) {
-            const double wi = w[idx];
-            A += wi;
-            B += wi * (double)kr[i];
+    {
+        const float* __restrict__ xr = keys_in + base;
+        for (int n = tid; n < N; n += kSortBlock) {
+            const double wn = w[n];
+            A += wn;
+            B += wn * (double)xr[n];
         }
+        A = wave_sum(A);
+        B = wave_sum(B);
+        if (lane == 0) { sa[1][wave] = A; sb[1][wave] = B; }
+        __syncthreads();
+        A = B = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) { A += sa[1][k]; B += sb[1][k]; }
     }
-    block_sum2(A, B, sa, sb);
-    // chunked exclusive scan in sorted order
+    // exclusive prefix sums W_<, S_< over the sources in sorted order, chunk
+    // by chunk: each thread holds kSortItems consecutive keys, waves scan by
+    // shuffles, the wave totals go through LDS (two buffers: one barrier per
+    // chunk suffices)
     double ca = 0.0, cb = 0.0;                        // sums of the earlier chunks
-    for (int c0 = 0; c0 < n_tot; c0 += kSortBlock * kSortItems) {
+    int par = 0;
+    for (int c0 = 0; c0 < n_tot; c0 += kSortChunk, par ^= 1) {
+        const int i0 = c0 + tid * kSortItems;
         float kk[kSortItems];
         int ii[kSortItems];
+        if (i0 + kSortItems <= n_tot) {
+            const float4 k0 = *reinterpret_cast<const float4*>(kr + i0);
+            const float4 k1 = *reinterpret_cast<const float4*>(kr + i0 + 4);
+            const uint4 v0 = *reinterpret_cast<const uint4*>(vr + i0);
+            const uint4 v1 = *reinterpret_cast<const uint4*>(vr + i0 + 4);
+            kk[0] = k0.x; kk[1] = k0.y; kk[2] = k0.z; kk[3] = k0.w;
+            kk[4] = k1.x; kk[5] = k1.y; kk[6] = k1.z; kk[7] = k1.w;
+            const unsigned int vv[kSortItems] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) ii[j] = (int)((int64_t)vv[j] - base);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) {
+                const int i = i0 + j;
+                kk[j] = i < n_tot ? kr[i] : 0.f;
+                ii[j] = i < n_tot ? (int)((int64_t)vr[i] - base) : -1;
+            }
+        }
         double la[kSortItems], lb[kSortItems];
         double ta = 0.0, tb = 0.0;
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
-            const int i = c0 + tid * kSortItems + j;
-            ii[j] = -1;
-            la[j] = lb[j] = 0.0;
-            kk[j] = 0.f;
-            if (i < n_tot) {
-                kk[j] = kr[i];
-                ii[j] = (int)((int64_t)vr[i] - base);
-                if (ii[j] < 0 || ii[j] >= n_tot) ii[j] = -1;     // not a position of this row
-                if (ii[j] >= 0 && ii[j] < N) {
-                    la[j] = w[ii[j]];
-                    lb[j] = la[j] * (double)kk[j];
-                }
+            if (ii[j] < 0 || ii[j] >= n_tot) ii[j] = -1;        // not a position of this row
+            la[j] = 0.0;
+            lb[j] = 0.0;
+            if (ii[j] >= 0 && ii[j] < N) {
+                la[j] = w[ii[j]];
+                lb[j] = la[j] * (double)kk[j];
             }
             ta += la[j];
             tb += lb[j];
         }
-        // inclusive scan of the thread totals (Hillis-Steele in LDS, FP64)
-        sa[tid] = ta;
-        sb[tid] = tb;
+        const double ia = wave_incl_scan(ta), ib = wave_incl_scan(tb);
+        if (lane == 63) { sa[par][wave] = ia; sb[par][wave] = ib; }
         __syncthreads();
-        for (int h = 1; h < kSortBlock; h <<= 1) {
-            const double xa = tid >= h ? sa[tid - h] : 0.0;
-            const double xb = tid >= h ? sb[tid - h] : 0.0;
-            __syncthreads();
-            sa[tid] += xa;
-            sb[tid] += xb;
-            __syncthreads();
+        double pa = ca, pb = cb;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            const double xa = sa[par][k], xb = sb[par][k];
+            if (k < wave) { pa += xa; pb += xb; }
+            ca += xa;
+            cb += xb;
         }
-        double pa = ca + sa[tid] - ta, pb = cb + sb[tid] - tb;   // exclusive
-        const double chunk_a = sa[kSortBlock - 1], chunk_b = sb[kSortBlock - 1];
+        pa += ia - ta;                                  // exclusive prefix of item 0
+        pb += ib - tb;
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const bool tgt = same_xy ? (ii[j] >= 0 && ii[j] < N) : ii[j] >= yoff;   // < n_tot
@@ -127,9 +157,6 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
             pa += la[j];
             pb += lb[j];
         }
-        ca += chunk_a;
-        cb += chunk_b;
-        __syncthreads();
     }
 }
 
@@ -138,7 +165,7 @@ hipError_t run_sort(void* temp, size_t& temp_bytes, const float* keys_in, float*
     const rocprim::counting_iterator<unsigned int> rows(0u);
     const OffsetIt begin(rows, RowOffset{L, 0});
     const OffsetIt end(rows, RowOffset{L, n_tot});
-    return rocprim::segmented_radix_sort_pairs(temp, temp_bytes, keys_in, keys_out,
+    return rocprim::segmented_radix_sort_pairs<SortConfig>(temp, temp_bytes, keys_in, keys_out,
                                                rocprim::counting_iterator<unsigned int>(0u),
                                                vals_out, (unsigned int)(P * L), (unsigned int)P,
                                                begin, end, 0, 32, stream);
@@ -165,7 +192,7 @@ hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned 
     hipError_t e = run_sort(temp, bytes, keys_in, keys_out, vals_out, L, P, n_tot, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sorted_energy_kernel, dim3((unsigned)P), dim3(kSortBlock), 0, stream,
-                       keys_out, vals_out, L, N, yoff, M, same_xy, w, coef, V, ldm);
+                       keys_in, keys_out, vals_out, L, N, yoff, M, same_xy, w, coef, V, ldm);
     return hipGetLastError();
 }
 
