@@ -175,6 +175,27 @@ class FastSum(torch.autograd.Function):
         return None, gx, gy, gw
 
 
+def kernel_sum(x, y, w, xi, *, kernel, scale=1.0, n_ft=None, R=None, sorting=False, **kw):
+    """One call of s_m ~ sum_n w_n F(||x_n - y_m||) (eq. kernel_sum by the
+    slicing estimator with the directions xi, (d, P) unit columns) on a plan
+    built for exactly these sizes and released afterwards.  R defaults to
+    max ||x|| + max ||y|| (App. J, eq. radius_xy), n_ft to choose_nft's rule
+    (1024 for the energy kernel).  y may be x.  For repeated calls keep a Plan."""
+    if R is None:
+        R = float(torch.linalg.norm(x, dim=1).max() + torch.linalg.norm(y, dim=1).max())
+        R = R * (1.0 + 1e-6) if R > 0 else 1.0
+    if n_ft is None:
+        n_ft = 1024 if kernel == "energy" else choose_nft(kernel, x.shape[1], R, scale=scale)
+    plan = Plan(xi, kernel=kernel, n_ft=n_ft, R=R, scale=scale, sorting=sorting,
+                n_max=x.shape[0], m_max=y.shape[0], device=x.device, **kw)
+    try:
+        s = plan(x, w, y)
+        plan.check()
+    finally:
+        plan.close()
+    return s
+
+
 def host_tables(kernel, d, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0, window_w=0,
                 oversample=0):
     """FP64 host precompute of a plan without touching a device:

@@ -305,3 +305,22 @@ def test_gradients_match_oracle(kernel, materialize):
     assert rel_l2(gy, gy_ref) < 1e-3
     assert rel_l2(gw, gw_ref) < 1e-4
     assert rel_l2(gx, gx_ref) < 1e-3
+
+
+def test_kernel_sum_one_shot():
+    """The one-call helper equals an explicit plan bit for bit; with its
+    default bound R and N_ft it stays within the method's error of it."""
+    import paper_2410_01316_amd as F
+    cfg = make_config("tiny", frac=0.5)
+    x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
+    s_plan, plan = _run(cfg)
+    plan.close()
+    s_one = F.kernel_sum(x, y, w, cfg["xi"], kernel="gauss", scale=cfg["scale"],
+                         n_ft=cfg["n_ft"], R=cfg["R"], T=DEFAULT_T["gauss"])
+    assert np.array_equal(s_one.cpu().numpy(), s_plan)
+    s_def = F.kernel_sum(x, y, w, cfg["xi"], kernel="gauss", scale=cfg["scale"])
+    assert rel_l2(s_def.cpu().numpy(), s_plan) < 1e-4
+    e = F.kernel_sum(x, x, w, cfg["xi"], kernel="energy", sorting=True)
+    xo, _, wo, xio = oracle_inputs(cfg)
+    s2 = O.kernel_sum_sliced("energy", xo, xo, wo, xio, 1.0)
+    assert rel_l2(e.cpu().numpy(), s2) < 1e-5
