@@ -61,11 +61,12 @@ def _points(N, M, d, seed, ties=0):
     return dict(x=x, y=y, w=w, R=R, kernel="energy", scale=1.0, n_ft=1024)
 
 
-@pytest.mark.parametrize("N,M,d,P", [(1500, 1300, 5, 32), (4097, 3, 3, 17), (1, 1, 2, 1),
+@pytest.mark.parametrize("N,M,d,P", [(1500, 1300, 5, 32), (9001, 3, 3, 17), (1, 1, 2, 1),
                                      (5, 700, 64, 40), (900, 1100, 65, 24)])
 def test_sorted_matches_exact_sliced(N, M, d, P):
-    """Ragged sizes (one point, one direction, a tail past a 1024-key chunk),
-    d at both sides of the fused / stored projection boundary."""
+    """Ragged sizes (one point, one direction, a row past one 8192-entry
+    chunk of the prefix-sum pass), d at both sides of the fused / stored
+    projection boundary."""
     cfg = _points(N, M, d, seed=N + 7 * M + d)
     cfg["xi"] = directions("distance" if d > 1 else "orth", d, P, 5)
     plan = _plan(cfg)
@@ -182,3 +183,17 @@ def test_sorted_precision_full_size():
     print("precision full size sorted: 64 dirs vs oracle %.2e; 2000 dirs vs Fourier %.2e"
           % (e, ef))
     assert e < _bar(784) and ef < 1e-4
+
+
+def test_sorted_bf16_projection():
+    """BF16 projections (inputs and directions rounded to 8 mantissa bits)
+    with exact 1-D sums: the error is the projection's, as in the Fourier
+    path's BF16 form (bar 2e-3 of s_abs)."""
+    cfg = make_config("precision", frac=0.004, P=96)
+    plan = _plan(cfg, proj="bf16")
+    s = _gpu(plan, cfg, same=True)
+    plan.close()
+    s2, s_abs = _oracle(cfg)
+    e = err_scale(s, s2, s_abs)
+    print("sorted bf16 d784: err_scale %.2e" % e)
+    assert e < 2e-3
