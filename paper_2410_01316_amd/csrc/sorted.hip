@@ -18,9 +18,9 @@ namespace fastsum {
 
 namespace {
 
-constexpr int kSortBlock = 1024;               // 16 waves per direction
+constexpr int kSortBlock = 512;                // 8 waves per direction
 constexpr int kSortWaves = kSortBlock / 64;
-constexpr int kSortItems = 8;                  // consecutive sorted keys per thread and chunk
+constexpr int kSortItems = 16;                 // consecutive sorted keys per thread and chunk
 constexpr int kSortChunk = kSortBlock * kSortItems;
 
 // offset of row p: p * L + add
@@ -102,15 +102,16 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
         float kk[kSortItems];
         int ii[kSortItems];
         if (i0 + kSortItems <= n_tot) {
-            const float4 k0 = *reinterpret_cast<const float4*>(kr + i0);
-            const float4 k1 = *reinterpret_cast<const float4*>(kr + i0 + 4);
-            const uint4 v0 = *reinterpret_cast<const uint4*>(vr + i0);
-            const uint4 v1 = *reinterpret_cast<const uint4*>(vr + i0 + 4);
-            kk[0] = k0.x; kk[1] = k0.y; kk[2] = k0.z; kk[3] = k0.w;
-            kk[4] = k1.x; kk[5] = k1.y; kk[6] = k1.z; kk[7] = k1.w;
-            const unsigned int vv[kSortItems] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-            for (int j = 0; j < kSortItems; ++j) ii[j] = (int)((int64_t)vv[j] - base);
+            for (int q = 0; q < kSortItems / 4; ++q) {
+                const float4 kq = *reinterpret_cast<const float4*>(kr + i0 + 4 * q);
+                const uint4 vq = *reinterpret_cast<const uint4*>(vr + i0 + 4 * q);
+                kk[4 * q] = kq.x; kk[4 * q + 1] = kq.y; kk[4 * q + 2] = kq.z; kk[4 * q + 3] = kq.w;
+                ii[4 * q] = (int)((int64_t)vq.x - base);
+                ii[4 * q + 1] = (int)((int64_t)vq.y - base);
+                ii[4 * q + 2] = (int)((int64_t)vq.z - base);
+                ii[4 * q + 3] = (int)((int64_t)vq.w - base);
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j) {
