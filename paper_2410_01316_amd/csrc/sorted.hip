@@ -35,8 +35,9 @@ struct RowOffset {
 using OffsetIt = rocprim::transform_iterator<rocprim::counting_iterator<unsigned int>, RowOffset,
                                              unsigned int>;
 
-// rows of ~1e5 keys: one 1024-thread block per segment, 8-bit digits
-using SortConfig = rocprim::segmented_radix_sort_config<8, rocprim::kernel_config<1024, 8>>;
+// rows of ~1e5 keys: one 1024-thread block per segment, 12 keys per thread,
+// 8-bit digits (measured fastest of the shapes tried at 2000 rows of 2e5)
+using SortConfig = rocprim::segmented_radix_sort_config<8, rocprim::kernel_config<1024, 12>>;
 
 __device__ __forceinline__ double wave_incl_scan(double v) {
     const int lane = threadIdx.x & 63;
