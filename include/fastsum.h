@@ -95,13 +95,14 @@ typedef enum {
  * distance kernel, Sec. 4).  Per direction the projected sources and targets
  * are sorted together (segmented radix sort) and, in sorted order, FP64
  * prefix sums W_< of w_n and S_< of w_n x~_n over the sources give
- * sum_n w_n |x~_n - y~| = y~ (2 W_< - W) - (2 S_< - S) at each target.  The
- * only approximation left is the slicing (eq. (3)); n_ft, window_w and
+ * sum_n w_n |x~_n - y~| = y~ (2 W_< - W) - (2 S_< - S) at each target; each
+ * direction's sum is stored in FP32 and their mean taken in FP64.  The only
+ * approximation left is the slicing (eq. (3)); n_ft, window_w and
  * oversample are validated but unused.  Stores the projections; not
  * combinable with FASTSUM_FLAG_GRAD.  The plan needs P * L < 2^32 with
  * L = round_up(n_max, 64) + round_up(m_max, 64), and about
  * 4 P L (keys) + 4 P L (sorted keys) + 4 P L (positions) + 8 P L (sort
- * workspace) + 8 P round_up(max(n_max, m_max), 64) (per-direction sums)
+ * workspace) + 4 P round_up(max(n_max, m_max), 64) (per-direction sums)
  * bytes of device memory. */
 #define FASTSUM_FLAG_SORTED 4u
 

@@ -150,13 +150,16 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
 // i = yoff + m; entries in [N, yoff) are padding of any value.  Each row's
 // first yoff + M (same_xy: N) entries are sorted (keys_out, vals_out =
 // original positions p L + i) and V[p ldm + m] = coef * sum_n w_n |x~_n - y~_m|
-// is written for every target.  P * L < 2^32.  temp holds
+// is written for every target (FP32; launch_sorted_reduce takes the FP64
+// mean s[m] = scale * sum_p V[p ldm + m]).  P * L < 2^32.  temp holds
 // sorted_energy_temp_bytes(L, P) bytes.
 size_t sorted_energy_temp_bytes(int64_t L, int P);
 hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,
                                 void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
-                                int M, int same_xy, const float* w, double coef, double* V,
+                                int M, int same_xy, const float* w, double coef, float* V,
                                 int64_t ldm, hipStream_t stream);
+hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
+                                float* s, hipStream_t stream);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

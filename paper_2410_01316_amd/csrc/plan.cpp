@@ -459,7 +459,7 @@ struct fastsum_plan_s {
     unsigned int* vals = nullptr;
     void* sort_temp = nullptr;
     size_t sort_temp_bytes = 0;
-    double* sv = nullptr;          // per-direction exact sums, P x ldm
+    float* sv = nullptr;           // per-direction exact sums, P x ldm
     int64_t sort_L = 0, sort_yoff = 0;
     // last exec
     bool have_exec = false, last_same = false;
@@ -686,7 +686,7 @@ fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, i
     pl->last_nchunk = 0;
     pl->last_ngroup = pl->P;
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-    FS_TRY(launch_reduce(pl->sv, pl->P, pl->ldm, M, 1.0 / pl->P, out, st));
+    FS_TRY(launch_sorted_reduce(pl->sv, pl->P, pl->ldm, M, 1.0 / pl->P, out, st));
     return FASTSUM_OK;
 }
 

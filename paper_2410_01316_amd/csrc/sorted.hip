@@ -60,21 +60,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 // g = p L + i in the unsorted row: i < N is source i, i in [yoff, yoff + M)
 // target i - yoff, anything else padding that is skipped (same_xy: every
 // i < N is source and target i).  Writes
-// V[p ldm + m] = coef * sum_n w_n |x~_n - y~_m|, coef = -c_d / tau.
+// V[p ldm + m] = coef * sum_n w_n |x~_n - y~_m|, coef = -c_d / tau, computed in
+// FP64 and stored in FP32 (relative rounding 6e-8 of one direction's sum;
+// the mean over the directions is taken in FP64 by sorted_reduce_kernel).
 // The writes are scattered (targets in sorted order); the workgroups of
 // different directions run spread over the whole device, which measured
 // faster than grouping the chunks of a few directions per XCD.
 __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
     const float* __restrict__ keys_in, const float* __restrict__ keys,
     const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M, int same_xy,
-    const float* __restrict__ w, double coef, double* __restrict__ V, int64_t ldm) {
+    const float* __restrict__ w, double coef, float* __restrict__ V, int64_t ldm) {
     __shared__ double sa[2][kSortWaves], sb[2][kSortWaves];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_tot = same_xy ? N : yoff + M;
     const int64_t base = (int64_t)p * L;
     const float* __restrict__ kr = keys + base;
     const unsigned int* __restrict__ vr = vals + base;
-    double* __restrict__ vrow = V + (int64_t)p * ldm;
+    float* __restrict__ vrow = V + (int64_t)p * ldm;
     // totals W = sum w_n and S = sum w_n x~_n over the unsorted sources
     double A = 0.0, B = 0.0;
     {
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
             if (tgt) {
                 const int m = same_xy ? ii[j] : ii[j] - yoff;
                 const double y = kk[j];
-                vrow[m] = coef * (y * (2.0 * pa - A) - (2.0 * pb - B));
+                vrow[m] = (float)(coef * (y * (2.0 * pa - A) - (2.0 * pb - B)));
             }
             pa += la[j];
             pb += lb[j];
@@ -173,7 +175,25 @@ hipError_t run_sort(void* temp, size_t& temp_bytes, const float* keys_in, float*
                                                begin, end, 0, 32, stream);
 }
 
+// s[m] = scale * sum_p V[p ldm + m], FP64 over the directions in order.
+__global__ __launch_bounds__(256) void sorted_reduce_kernel(const float* __restrict__ V, int P,
+                                                            int64_t ldm, int64_t M, double scale,
+                                                            float* __restrict__ s) {
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p) acc += (double)V[(int64_t)p * ldm + m];
+    s[m] = (float)(scale * acc);
+}
+
 }  // namespace
+
+hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
+                                float* s, hipStream_t stream) {
+    hipLaunchKernelGGL(sorted_reduce_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0,
+                       stream, V, P, ldm, M, scale, s);
+    return hipGetLastError();
+}
 
 size_t sorted_energy_temp_bytes(int64_t L, int P) {
     size_t bytes = 0;
@@ -184,7 +204,7 @@ size_t sorted_energy_temp_bytes(int64_t L, int P) {
 
 hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,
                                 void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
-                                int M, int same_xy, const float* w, double coef, double* V,
+                                int M, int same_xy, const float* w, double coef, float* V,
                                 int64_t ldm, hipStream_t stream) {
     const int n_tot = same_xy ? N : yoff + M;
     if (N < 1 || M < 1 || (!same_xy && yoff < N) || n_tot > L || M > ldm ||
