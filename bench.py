@@ -393,6 +393,10 @@ def main():
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of "
               "it (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.form and args.form not in dict(form_runners(1)):
+        print(f"bench.py: unknown form {args.form!r}; one of "
+              f"{sorted(dict(form_runners(1)))}", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     import paper_2410_01316_amd as F
@@ -402,10 +406,6 @@ def main():
     torch.cuda.set_device(0)
     if args.form:
         runners = dict(form_runners(max(3, args.steps // 4)))
-        if args.form not in runners:
-            print(f"bench.py: unknown form {args.form!r}; one of {sorted(runners)}",
-                  file=sys.stderr)
-            sys.exit(2)
         log(f"bench: form {args.form}")
         res = {"form": args.form, **runners[args.form]()}
         if args.copy_calibration:
