@@ -92,7 +92,7 @@ typedef enum {
 #define FASTSUM_FLAG_MATERIALIZE 2u
 /* Energy kernel only: compute every 1-D sum exactly by sorting instead of by
  * Fourier summation (the 1-D method the paper takes for the negative
- * distance kernel, Sec. 4).  Per direction the projected sources and targets
+ * distance kernel, Sec. 4.3).  Per direction the projected sources and targets
  * are sorted together (segmented radix sort) and, in sorted order, FP64
  * prefix sums W_< of w_n and S_< of w_n x~_n over the sources give
  * sum_n w_n |x~_n - y~| = y~ (2 W_< - W) - (2 S_< - S) at each target; each

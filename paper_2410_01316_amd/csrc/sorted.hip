@@ -1,6 +1,7 @@
 // Exact sliced sums for the energy kernel by sorting, the 1-D method the
-// paper uses for the negative distance kernel (Sec. 4; f(t) = -c_d |t| from
-// Table 'tab:kernels', Riesz row with r = 1).  Per direction the sources and
+// paper uses for the negative distance kernel (Sec. 4.3; one of the 1-D
+// algorithms listed in Sec. 2.1; f(t) = -c_d |t| from Table 'tab:kernels',
+// Riesz row with r = 1).  Per direction the sources and
 // targets are sorted together by projection; in sorted order the FP64
 // prefix sums W_< of w and S_< of w x~ over the sources give, at a target
 // with projection y~,
