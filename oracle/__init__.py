@@ -20,13 +20,13 @@ from .kernels import (KERNELS, basis_F, basis_dF, energy_cd, sliced_ft,
                       SlicedBasis, rescale_tau, fourier_coefficients,
                       truncated_coefficients)
 from .direct import kernel_sum_direct, grad_y_direct
-from .sliced import kernel_sum_sliced
+from .sliced import kernel_sum_sliced, grad_sliced_energy
 from .fourier import (kernel_sum_fourier, grad_y_fourier, grad_w_fourier, grad_x_fourier,
                       project)
 
 __all__ = [
     "KERNELS", "basis_F", "basis_dF", "energy_cd", "sliced_ft", "SlicedBasis",
     "rescale_tau", "fourier_coefficients", "truncated_coefficients",
-    "kernel_sum_direct", "grad_y_direct", "kernel_sum_sliced",
+    "kernel_sum_direct", "grad_y_direct", "kernel_sum_sliced", "grad_sliced_energy",
     "kernel_sum_fourier", "grad_y_fourier", "grad_w_fourier", "grad_x_fourier", "project",
 ]

@@ -522,3 +522,47 @@ def test_golden_parameters_match_workload_defaults():
     for kernel, T, gf, nft in rows:
         assert DEFAULT_T[kernel] == float(T)
         assert DEFAULT_NFT[kernel] == int(nft)
+
+
+def test_sliced_energy_gradients_match_finite_differences():
+    """The exact sliced energy sum is piecewise linear in x, y and w, so a
+    central difference with a small step reproduces its derivative away from
+    kinks, and at an exact tie (a target on a source, as in an MMD flow)
+    gives the symmetric value sign(0) = 0 that the gradient takes there."""
+    rng = np.random.default_rng(21)
+    N, M, d, P = 14, 11, 4, 6
+    x = rng.standard_normal((N, d))
+    y = rng.standard_normal((M, d))
+    y[3] = x[5]                                   # a coincident pair
+    w = rng.standard_normal(N)
+    v = rng.standard_normal(M)
+    xi = rng.standard_normal((d, P))
+    xi /= np.linalg.norm(xi, axis=0)
+    gx, gy, gw = O.grad_sliced_energy(x, y, w, v, xi)
+
+    def J(x_, y_, w_):
+        return float(v @ O.kernel_sum_sliced("energy", x_, y_, w_, xi, 1.0))
+
+    h = 1e-6
+    for (m, i) in [(0, 0), (3, 1), (3, 3), (7, 2)]:
+        e = np.zeros_like(y)
+        e[m, i] = h
+        fd = (J(x, y + e, w) - J(x, y - e, w)) / (2 * h)
+        assert abs(fd - gy[m, i]) < 1e-6 * (1 + abs(gy[m, i])), (m, i, fd, gy[m, i])
+    for (n, i) in [(0, 0), (5, 2), (9, 3)]:
+        e = np.zeros_like(x)
+        e[n, i] = h
+        fd = (J(x + e, y, w) - J(x - e, y, w)) / (2 * h)
+        assert abs(fd - gx[n, i]) < 1e-6 * (1 + abs(gx[n, i])), (n, i, fd, gx[n, i])
+    for n in (0, 5, 13):
+        e = np.zeros_like(w)
+        e[n] = 1.0
+        assert J(x, y, w + e) - J(x, y, w) == pytest.approx(gw[n], rel=1e-12, abs=1e-12)
+    # the coincident pair contributes nothing to either gradient
+    wz = w.copy()
+    wz[5] = 0.0
+    _, gy0, _ = O.grad_sliced_energy(x, y, wz, v, xi)
+    _, gy1, _ = O.grad_sliced_energy(x, y, w, v, xi)
+    tie_only = gy1[3] - gy0[3]
+    t = (x[5] - y[3]) @ xi
+    assert np.all(t == 0.0) and np.allclose(tie_only, 0.0, atol=1e-15)
