@@ -366,6 +366,7 @@ def form_runners(fsteps):
         ("mmd_gauss_fwd_grad", lambda: mmd("gauss", grad=True)),
         ("mmd_energy_fwd_grad", lambda: mmd("energy", grad=True)),
         ("mmd_energy_sorted", lambda: mmd("energy", err_targets=32, sorting=True)),
+        ("mmd_energy_sorted_fwd_grad", lambda: mmd("energy", grad=True, sorting=True)),
         ("mmd_flow_energy_d3072", lambda: mmd_flow_form(fsteps)),
         ("batched_256", lambda: batched_form(fsteps, None)),
     ]

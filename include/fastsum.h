@@ -98,12 +98,17 @@ typedef enum {
  * sum_n w_n |x~_n - y~| = y~ (2 W_< - W) - (2 S_< - S) at each target; each
  * direction's sum is stored in FP32 and their mean taken in FP64.  The only
  * approximation left is the slicing (eq. (3)); n_ft, window_w and
- * oversample are validated but unused.  Stores the projections; not
- * combinable with FASTSUM_FLAG_GRAD.  The plan needs P * L < 2^32 with
+ * oversample are validated but unused.  Stores the projections.  With
+ * FASTSUM_FLAG_GRAD, fastsum_grad_xyw is exact too: an ascending and a
+ * descending sort of sources and targets give per direction the weight sums
+ * over strictly smaller and strictly larger keys, i.e. the derivative
+ * sum_n w_n sign(y~ - x~_n) with sign(0) = 0 where projections coincide, and
+ * the transposed sums for grad_w.  The plan needs P * L < 2^32 with
  * L = round_up(n_max, 64) + round_up(m_max, 64), and about
  * 4 P L (keys) + 4 P L (sorted keys) + 4 P L (positions) + 8 P L (sort
- * workspace) + 4 P round_up(max(n_max, m_max), 64) (per-direction sums)
- * bytes of device memory. */
+ * workspace) + 4 P ldm (per-direction sums) bytes of device memory,
+ * ldm = round_up(max(n_max, m_max), 64), plus 8 P ldm with
+ * FASTSUM_FLAG_GRAD. */
 #define FASTSUM_FLAG_SORTED 4u
 
 /*

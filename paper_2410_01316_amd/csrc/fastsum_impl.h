@@ -160,6 +160,16 @@ hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned 
                                 int64_t ldm, hipStream_t stream);
 hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
                                 float* s, hipStream_t stream);
+// Adjoint pieces per direction from an ascending and a descending sort of
+// the rows (sources at i < N with weights w, targets at yoff + m with
+// cotangent v; sign(0) = 0 at equal keys), all P x ldm FP32:
+//   Ty[p][m] = coef sum_n w_n sign(y~_m - x~_n) (want bit 0),
+//   Tx[p][n] = coef sum_m v_m sign(x~_n - y~_m) (bit 1),
+//   U[p][n] = coef sum_m v_m |x~_n - y~_m| (bit 2).
+hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned int* vals_out,
+                              void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
+                              int M, const float* w, const float* v, double coef, float* Ty,
+                              float* Tx, float* U, int64_t ldm, int want, hipStream_t stream);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

@@ -200,10 +200,8 @@ fastsum_status resolve_params(const fastsum_params* in, Resolved& r) {
     if (p.proj != FASTSUM_PROJ_FP32 && p.proj != FASTSUM_PROJ_BF16) return FASTSUM_EINVAL;
     if (p.flags & ~(FASTSUM_FLAG_GRAD | FASTSUM_FLAG_MATERIALIZE | FASTSUM_FLAG_SORTED))
         return FASTSUM_EINVAL;
-    // exact 1-D sums by sorting exist for the energy kernel only, forward only
-    if ((p.flags & FASTSUM_FLAG_SORTED) &&
-        (p.kernel != FASTSUM_ENERGY || (p.flags & FASTSUM_FLAG_GRAD)))
-        return FASTSUM_EINVAL;
+    // exact 1-D sums by sorting exist for the energy kernel only
+    if ((p.flags & FASTSUM_FLAG_SORTED) && p.kernel != FASTSUM_ENERGY) return FASTSUM_EINVAL;
     // App. I: T = 0.3 (Gauss), 0.1 (Laplace), 0.2 (Matern); 0.45 for the
     // energy kernel's periodic extension
     if (p.T == 0.0)
@@ -460,6 +458,8 @@ struct fastsum_plan_s {
     void* sort_temp = nullptr;
     size_t sort_temp_bytes = 0;
     float* sv = nullptr;           // per-direction exact sums, P x ldm
+    float* sty = nullptr;          // sorted adjoint: d/dy~ and d/dx~ per direction, P x ldm
+    float* stx = nullptr;
     int64_t sort_L = 0, sort_yoff = 0;
     // last exec
     bool have_exec = false, last_same = false;
@@ -485,7 +485,7 @@ void free_plan(fastsum_plan_s* p) {
     void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->gdt, p->gpt, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout, p->keys,
-                    p->keys_out, p->vals, p->sort_temp, p->sv};
+                    p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -690,6 +690,45 @@ fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, i
     return FASTSUM_OK;
 }
 
+// Adjoint of a sorted exec: an ascending and a descending sort of the rows
+// (sources x, targets y) give per direction the one-sided sums of w and v
+// at every point; back-projection with tau Xi and the weights v or w gives
+// grad_y and grad_x, the FP64 mean of the transposed sums grad_w.
+fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, float* grad_y,
+                           float* grad_w, hipStream_t st) {
+    const int64_t L = pl->sort_L, yoff = pl->sort_yoff, N = pl->last_N, M = pl->last_M;
+    const int P = pl->P;
+    if (!grad_x && !grad_y && !grad_w) return FASTSUM_OK;
+    if (pl->last_same) {          // the exec projected one copy; the adjoint needs both roles
+        fastsum_status r = project(pl, pl->last_x, N, pl->keys + yoff, L, st);
+        if (r != FASTSUM_OK) return r;
+    }
+    const double coef = -energy_cd(pl->d) / pl->r.tau;
+    {
+        PhaseTimer t(pl, FASTSUM_PHASE_SORT, st);
+        FS_TRY(launch_sorted_grad(pl->keys, pl->keys_out, pl->vals, pl->sort_temp,
+                                  pl->sort_temp_bytes, L, P, (int)N, (int)yoff, (int)M,
+                                  pl->last_w, v, coef, pl->sty, pl->stx, pl->sv, pl->ldm,
+                                  (grad_y ? 1 : 0) | (grad_x ? 2 : 0) | (grad_w ? 4 : 0), st));
+    }
+    const float inv_p = (float)(1.0 / P);
+    if (grad_y) {
+        PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
+        FS_TRY(launch_backproject(pl->sty, pl->ldm, M, P, pl->d, pl->A, pl->dpad, inv_p, v,
+                                  grad_y, st));
+    }
+    if (grad_x) {
+        PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
+        FS_TRY(launch_backproject(pl->stx, pl->ldm, N, P, pl->d, pl->A, pl->dpad, inv_p,
+                                  pl->last_w, grad_x, st));
+    }
+    if (grad_w) {
+        PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
+        FS_TRY(launch_sorted_reduce(pl->sv, P, pl->ldm, N, 1.0 / P, grad_w, st));
+    }
+    return FASTSUM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -825,7 +864,9 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     }
     const int DC = (pl->d + 15) / 16;
     pl->ldg = cap;       // the source adjoint back-projects at the sources
-    if (ok && grad)
+    if (ok && grad && pl->sorted)
+        ok = dev_alloc(&pl->sty, (size_t)P * pl->ldm) && dev_alloc(&pl->stx, (size_t)P * pl->ldm);
+    if (ok && grad && !pl->sorted)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
              dev_alloc(&pl->grid_wd, (size_t)P * nr) && dev_alloc(&pl->tout, (size_t)cap) &&
              dev_alloc(&pl->mult_d, (size_t)n) &&
@@ -888,7 +929,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         e = hipMemcpyAsync(pl->mult, mult.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->tw)
         e = hipMemcpyAsync(pl->tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && grad)
+    if (e == hipSuccess && pl->mult_d)
         e = hipMemcpyAsync(pl->mult_d, mult_d.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemsetAsync(pl->flag, 0, sizeof(int), hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
@@ -975,6 +1016,7 @@ fastsum_status fastsum_grad_xyw(fastsum_plan pl, const float* grad_s, float* gra
     // v = grad_s, targets x) gives grad_w = u(x) and, through its
     // derivative grids, grad_x[n] = w_n du/dx(x_n).
     float* uout = grad_w ? grad_w : pl->tout;
+    if (pl->sorted) return sorted_grad(pl, grad_s, grad_x, grad_y, grad_w, st);
     if (pl->fused) {
         const uint16_t* yt = pl->last_same ? pl->xt : pl->yt;
         const float pscale = (float)(pl->r.tau * pl->r.p.R);

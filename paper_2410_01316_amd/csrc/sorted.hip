@@ -56,6 +56,37 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Keys and row positions of the kSortItems sorted entries from i0 (16-byte
+// loads where the whole group lies in the row; ii = -1 past its end or for
+// a position outside the row).
+__device__ __forceinline__ void load_sorted(const float* __restrict__ kr,
+                                            const unsigned int* __restrict__ vr, int64_t base,
+                                            int i0, int n_tot, float (&kk)[kSortItems],
+                                            int (&ii)[kSortItems]) {
+    if (i0 + kSortItems <= n_tot) {
+#pragma unroll
+        for (int q = 0; q < kSortItems / 4; ++q) {
+            const float4 kq = *reinterpret_cast<const float4*>(kr + i0 + 4 * q);
+            const uint4 vq = *reinterpret_cast<const uint4*>(vr + i0 + 4 * q);
+            kk[4 * q] = kq.x; kk[4 * q + 1] = kq.y; kk[4 * q + 2] = kq.z; kk[4 * q + 3] = kq.w;
+            ii[4 * q] = (int)((int64_t)vq.x - base);
+            ii[4 * q + 1] = (int)((int64_t)vq.y - base);
+            ii[4 * q + 2] = (int)((int64_t)vq.z - base);
+            ii[4 * q + 3] = (int)((int64_t)vq.w - base);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int i = i0 + j;
+            kk[j] = i < n_tot ? kr[i] : 0.f;
+            ii[j] = i < n_tot ? (int)((int64_t)vr[i] - base) : -1;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j)
+        if (ii[j] < 0 || ii[j] >= n_tot) ii[j] = -1;
+}
+
 // One workgroup per direction p.  keys_in is the unsorted row (sources at
 // i < N); keys / vals the sorted row with, for each key, its position
 // g = p L + i in the unsorted row: i < N is source i, i in [yoff, yoff + M)
@@ -105,25 +136,7 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
         const int i0 = c0 + tid * kSortItems;
         float kk[kSortItems];
         int ii[kSortItems];
-        if (i0 + kSortItems <= n_tot) {
-#pragma unroll
-            for (int q = 0; q < kSortItems / 4; ++q) {
-                const float4 kq = *reinterpret_cast<const float4*>(kr + i0 + 4 * q);
-                const uint4 vq = *reinterpret_cast<const uint4*>(vr + i0 + 4 * q);
-                kk[4 * q] = kq.x; kk[4 * q + 1] = kq.y; kk[4 * q + 2] = kq.z; kk[4 * q + 3] = kq.w;
-                ii[4 * q] = (int)((int64_t)vq.x - base);
-                ii[4 * q + 1] = (int)((int64_t)vq.y - base);
-                ii[4 * q + 2] = (int)((int64_t)vq.z - base);
-                ii[4 * q + 3] = (int)((int64_t)vq.w - base);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kSortItems; ++j) {
-                const int i = i0 + j;
-                kk[j] = i < n_tot ? kr[i] : 0.f;
-                ii[j] = i < n_tot ? (int)((int64_t)vr[i] - base) : -1;
-            }
-        }
+        load_sorted(kr, vr, base, i0, n_tot, kk, ii);
         double la[kSortItems], lb[kSortItems];
         double ta = 0.0, tb = 0.0;
 #pragma unroll
@@ -165,15 +178,133 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
     }
 }
 
+// Both directions are stable: equal keys keep the order of their positions.
 hipError_t run_sort(void* temp, size_t& temp_bytes, const float* keys_in, float* keys_out,
-                    unsigned int* vals_out, int64_t L, int P, int n_tot, hipStream_t stream) {
+                    unsigned int* vals_out, int64_t L, int P, int n_tot, hipStream_t stream,
+                    bool descending = false) {
     const rocprim::counting_iterator<unsigned int> rows(0u);
     const OffsetIt begin(rows, RowOffset{L, 0});
     const OffsetIt end(rows, RowOffset{L, n_tot});
+    if (descending)
+        return rocprim::segmented_radix_sort_pairs_desc<SortConfig>(
+            temp, temp_bytes, keys_in, keys_out, rocprim::counting_iterator<unsigned int>(0u),
+            vals_out, (unsigned int)(P * L), (unsigned int)P, begin, end, 0, 32, stream);
     return rocprim::segmented_radix_sort_pairs<SortConfig>(temp, temp_bytes, keys_in, keys_out,
                                                rocprim::counting_iterator<unsigned int>(0u),
                                                vals_out, (unsigned int)(P * L), (unsigned int)P,
                                                begin, end, 0, 32, stream);
+}
+
+// Adjoint of the sorted energy sums.  The row holds the sources x (weights
+// w, positions i < N) and the targets y (cotangent v, positions yoff + m).
+// Per direction, with coef = -c_d / tau and sign(0) = 0 at equal keys,
+//   Ty[p][m] = coef sum_n w_n sign(y~_m - x~_n) = coef (W_< - W_>)   (d/dy~ of the sum)
+//   Tx[p][n] = coef sum_m v_m sign(x~_n - y~_m) = coef (V_< - V_>)   (d/dx~ of the transposed sum)
+//   U[p][n]  = coef sum_m v_m |x~_n - y~_m|                         (the transposed sum)
+// The sums over strictly smaller or larger keys come from two stable sorts
+// of the same row, in which every x precedes every y of equal key:
+//   ascending (DESC = 0): x before y_m  = W_<=, y before x_n = V_<;
+//   descending (DESC = 1): x before y_m = W_>=, y before x_n = V_>.
+// Pass 0 writes Ty = coef (W_<= - W), Tx = coef V_<, U; pass 1 adds
+// coef (W - W_>=) to Ty and -coef V_> to Tx (each entry once per row).
+// want: bit 0 Ty, bit 1 Tx, bit 2 U (the others are neither read nor written).
+template <bool DESC>
+__global__ __launch_bounds__(kSortBlock) void sorted_grad_kernel(
+    const float* __restrict__ keys_in, const float* __restrict__ keys,
+    const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M,
+    const float* __restrict__ w, const float* __restrict__ v, double coef,
+    float* __restrict__ Ty, float* __restrict__ Tx, float* __restrict__ U, int64_t ldm,
+    int want) {
+    __shared__ double sa[2][kSortWaves], sb[2][kSortWaves], sc[2][kSortWaves];
+    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n_tot = yoff + M;
+    const int64_t base = (int64_t)p * L;
+    const float* __restrict__ kr = keys + base;
+    const unsigned int* __restrict__ vr = vals + base;
+    float* __restrict__ ty = Ty + (int64_t)p * ldm;
+    float* __restrict__ tx = Tx + (int64_t)p * ldm;
+    float* __restrict__ u = U + (int64_t)p * ldm;
+    // totals W = sum w, V = sum v, SV = sum v y~ over the unsorted row
+    double W = 0.0, V = 0.0, SV = 0.0;
+    {
+        const float* __restrict__ xr = keys_in + base;
+        for (int n = tid; n < N; n += kSortBlock) W += (double)w[n];
+        for (int m = tid; m < M; m += kSortBlock) {
+            const double vm = v[m];
+            V += vm;
+            SV += vm * (double)xr[yoff + m];
+        }
+        W = wave_sum(W);
+        V = wave_sum(V);
+        SV = wave_sum(SV);
+        if (lane == 0) { sa[1][wave] = W; sb[1][wave] = V; sc[1][wave] = SV; }
+        __syncthreads();
+        W = V = SV = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) { W += sa[1][k]; V += sb[1][k]; SV += sc[1][k]; }
+    }
+    double cw = 0.0, cv = 0.0, csv = 0.0;             // sums of the earlier chunks
+    int par = 0;
+    for (int c0 = 0; c0 < n_tot; c0 += kSortChunk, par ^= 1) {
+        const int i0 = c0 + tid * kSortItems;
+        float kk[kSortItems];
+        int ii[kSortItems];
+        load_sorted(kr, vr, base, i0, n_tot, kk, ii);
+        // x entries ii < N, y entries ii >= yoff, padding otherwise
+        double lw[kSortItems], lv[kSortItems], lsv[kSortItems];
+        double tw = 0.0, tv = 0.0, tsv = 0.0;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            lw[j] = lv[j] = lsv[j] = 0.0;
+            if (ii[j] >= 0 && ii[j] < N) lw[j] = w[ii[j]];
+            if (ii[j] >= yoff) {
+                lv[j] = v[ii[j] - yoff];
+                lsv[j] = lv[j] * (double)kk[j];
+            }
+            tw += lw[j];
+            tv += lv[j];
+            tsv += lsv[j];
+        }
+        const double iw = wave_incl_scan(tw), iv = wave_incl_scan(tv), isv = wave_incl_scan(tsv);
+        if (lane == 63) { sa[par][wave] = iw; sb[par][wave] = iv; sc[par][wave] = isv; }
+        __syncthreads();
+        double ew = cw, ev = cv, esv = csv;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            const double xa = sa[par][k], xb = sb[par][k], xc = sc[par][k];
+            if (k < wave) { ew += xa; ev += xb; esv += xc; }
+            cw += xa;
+            cv += xb;
+            csv += xc;
+        }
+        ew += iw - tw;                                  // exclusive prefixes of item 0
+        ev += iv - tv;
+        esv += isv - tsv;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (ii[j] >= yoff) {
+                const int m = ii[j] - yoff;
+                if (want & 1) {
+                    if (!DESC) ty[m] = (float)(coef * (ew - W));
+                    else ty[m] = (float)((double)ty[m] + coef * (W - ew));
+                }
+            } else if (ii[j] >= 0 && ii[j] < N) {
+                const int n = ii[j];
+                if (!DESC) {
+                    if (want & 2) tx[n] = (float)(coef * ev);
+                    if (want & 4) {
+                        const double x = kk[j];
+                        u[n] = (float)(coef * (x * (2.0 * ev - V) - (2.0 * esv - SV)));
+                    }
+                } else if (want & 2) {
+                    tx[n] = (float)((double)tx[n] - coef * ev);
+                }
+            }
+            ew += lw[j];
+            ev += lv[j];
+            esv += lsv[j];
+        }
+    }
 }
 
 // s[m] = scale * sum_p V[p ldm + m], FP64 over the directions in order.
@@ -197,10 +328,41 @@ hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, d
 }
 
 size_t sorted_energy_temp_bytes(int64_t L, int P) {
-    size_t bytes = 0;
-    if (run_sort(nullptr, bytes, nullptr, nullptr, nullptr, L, P, (int)L, nullptr) != hipSuccess)
+    size_t up = 0, down = 0;
+    if (run_sort(nullptr, up, nullptr, nullptr, nullptr, L, P, (int)L, nullptr) != hipSuccess ||
+        run_sort(nullptr, down, nullptr, nullptr, nullptr, L, P, (int)L, nullptr, true) !=
+            hipSuccess)
         return 0;
-    return bytes;
+    return up > down ? up : down;
+}
+
+hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned int* vals_out,
+                              void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
+                              int M, const float* w, const float* v, double coef, float* Ty,
+                              float* Tx, float* U, int64_t ldm, int want, hipStream_t stream) {
+    const int n_tot = yoff + M;
+    if (N < 1 || M < 1 || yoff < N || n_tot > L || N > ldm || M > ldm ||
+        (int64_t)P * L >= ((int64_t)1 << 32))
+        return hipErrorInvalidValue;
+    // the descending pass only completes the derivatives
+    const int passes = (want & 3) ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+        size_t bytes = temp_bytes;
+        hipError_t e = run_sort(temp, bytes, keys_in, keys_out, vals_out, L, P, n_tot, stream,
+                                pass == 1);
+        if (e != hipSuccess) return e;
+        if (pass == 0)
+            hipLaunchKernelGGL(sorted_grad_kernel<false>, dim3((unsigned)P), dim3(kSortBlock), 0,
+                               stream, keys_in, keys_out, vals_out, L, N, yoff, M, w, v, coef, Ty,
+                               Tx, U, ldm, want);
+        else
+            hipLaunchKernelGGL(sorted_grad_kernel<true>, dim3((unsigned)P), dim3(kSortBlock), 0,
+                               stream, keys_in, keys_out, vals_out, L, N, yoff, M, w, v, coef, Ty,
+                               Tx, U, ldm, want);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,

@@ -23,12 +23,13 @@ class MMDFlow:
     """Particles flowing towards the targets y (M x d, float32 on the GPU).
 
     xi: (d, P) directions; kernel, n_ft, scale, T, window_w as in Plan;
+    sorting: exact 1-D sums and derivatives by sorting (energy kernel);
     step: tau of the Euler step; momentum: m; margin: factor applied to the
     particles' current bound when the plan is (re)built.
     """
 
     def __init__(self, y, xi, n_particles, *, kernel="energy", n_ft=1024, scale=1.0, T=0.0,
-                 window_w=0, step=1.0, momentum=0.9, margin=1.5):
+                 window_w=0, sorting=False, step=1.0, momentum=0.9, margin=1.5):
         if not (isinstance(y, torch.Tensor) and y.dtype == torch.float32 and y.is_cuda):
             raise ValueError("y must be a float32 tensor on the GPU")
         self.y = y.contiguous()
@@ -38,6 +39,7 @@ class MMDFlow:
         if self.xi.shape[0] != self.d:
             raise ValueError("xi must be (d, P)")
         self.kernel, self.n_ft, self.scale, self.T, self.window_w = kernel, n_ft, scale, T, window_w
+        self.sorting = bool(sorting)
         self.step_size, self.momentum, self.margin = float(step), float(momentum), float(margin)
         dev = self.y.device
         N, M = self.N, self.M
@@ -63,7 +65,8 @@ class MMDFlow:
             self.plan.close()
         self.R = self.margin * need
         self.plan = Plan(self.xi, kernel=self.kernel, n_ft=self.n_ft, R=self.R, scale=self.scale,
-                         T=self.T, window_w=self.window_w, grad=True, n_max=self.N + self.M,
+                         T=self.T, window_w=self.window_w, grad=True, sorting=self.sorting,
+                         n_max=self.N + self.M,
                          m_max=self.N, device=self.y.device)
         self.rebuilds += 1
 

@@ -142,8 +142,8 @@ def test_sorted_plan_errors():
     with pytest.raises(F.FastSumError):
         F.Plan(xi, kernel="gauss", n_ft=128, scale=1.0, R=4.0, sorting=True, n_max=10, m_max=10)
     with pytest.raises(F.FastSumError):
-        F.Plan(xi, kernel="energy", n_ft=1024, R=4.0, sorting=True, grad=True, n_max=10,
-               m_max=10)
+        F.Plan(xi, kernel="laplace", n_ft=1024, scale=1.0, R=4.0, sorting=True, grad=True,
+               n_max=10, m_max=10)
     plan = F.Plan(xi, kernel="energy", n_ft=1024, R=4.0, sorting=True, n_max=10, m_max=10)
     import torch
     x = torch.zeros((10, 3), device="cuda")
@@ -197,3 +197,111 @@ def test_sorted_bf16_projection():
     e = err_scale(s, s2, s_abs)
     print("sorted bf16 d784: err_scale %.2e" % e)
     assert e < 2e-3
+
+
+def _grid_points(N, M, d, seed):
+    """Points on a 1/8 grid in [-2, 2]^d: along the coordinate axes every
+    projection is exact in FP32 and many of them coincide (ties)."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(-16, 17, size=(N, d)) / 8.0
+    y = rng.integers(-16, 17, size=(M, d)) / 8.0
+    y[: M // 4] = x[: M // 4]                    # targets on sources
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    return x, y, f32(rng.standard_normal(N)), f32(rng.standard_normal(M))
+
+
+def _sorted_grads(x, y, w, v, xi, same=False):
+    import paper_2410_01316_amd as F
+    import torch
+    R = float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max()) + 0.5
+    plan = F.Plan(xi, kernel="energy", n_ft=1024, R=R, T=DEFAULT_T["energy"], sorting=True,
+                  grad=True, n_max=x.shape[0], m_max=y.shape[0])
+    xd, yd, wd, vd = to_dev(x, y, w, v)
+    if same:
+        yd = xd
+    s = plan(xd, wd, yd)
+    gx, gy, gw = plan.grad(vd, want_x=True)
+    torch.cuda.synchronize()
+    plan.check()
+    plan.close()
+    f = lambda t: t.cpu().numpy().astype(np.float64)
+    return f(s), f(gx), f(gy), f(gw)
+
+
+@pytest.mark.parametrize("same", [False, True])
+def test_sorted_gradients_exact_ties(same):
+    """Axis directions and grid points: exact keys with many ties, so the
+    adjoint must take sign(0) = 0 for every coincident pair (the symmetric
+    difference quotient the oracle pins).  Bar 1e-5 rel-L2: the per-direction
+    one-sided sums are combined in FP32."""
+    N, M, d = 700, 500, 3
+    x, y, w, v = _grid_points(N, M, d, seed=31)
+    if same:
+        y = x
+        v = np.random.default_rng(32).standard_normal(N).astype(np.float32).astype(np.float64)
+    xi = np.concatenate([np.eye(d), -np.eye(d)], axis=1)
+    s, gx, gy, gw = _sorted_grads(x, y, w, v, xi, same)
+    ox, oy, ow = O.grad_sliced_energy(x, y, w, v, xi)
+    s2 = O.kernel_sum_sliced("energy", x, y, w, xi, 1.0)
+    e = [rel_l2(s, s2), rel_l2(gx, ox), rel_l2(gy, oy), rel_l2(gw, ow)]
+    print("sorted grads, ties (same=%s): s %.1e gx %.1e gy %.1e gw %.1e" % (same, *e))
+    assert max(e) < 1e-5
+
+
+def test_sorted_gradients_qmc_directions():
+    """Distance-QMC directions at d = 5: the FP32 projections can order a
+    source and a target differently from the FP64 oracle when they lie
+    within ~1e-7 of each other (a few of 6e7 pairs), each flipping one sign
+    in one direction's derivative, so the derivative bar is 2e-3 rel-L2;
+    the transposed sum (grad_w) has no such jump and meets 1e-5."""
+    N, M, d, P = 1500, 1300, 5, 32
+    cfg = _points(N, M, d, seed=41)
+    x, y, w = cfg["x"], cfg["y"], cfg["w"]
+    v = np.random.default_rng(42).standard_normal(M).astype(np.float32).astype(np.float64)
+    xi = directions("distance", d, P, 7)
+    s, gx, gy, gw = _sorted_grads(x, y, w, v, xi)
+    xo, yo, wo, xio = oracle_inputs(dict(x=x, y=y, w=w, xi=xi))
+    ox, oy, ow = O.grad_sliced_energy(xo, yo, wo, v, xio)
+    e = [rel_l2(gx, ox), rel_l2(gy, oy), rel_l2(gw, ow)]
+    print("sorted grads, QMC: gx %.1e gy %.1e gw %.1e" % tuple(e))
+    assert e[0] < 2e-3 and e[1] < 2e-3 and e[2] < 1e-5
+
+
+def test_sorted_autograd_matches_plan_grad():
+    import paper_2410_01316_amd as F
+    import torch
+    x, y, w, v = _grid_points(300, 200, 3, seed=51)
+    xi = directions("distance", 3, 16, 8)
+    R = float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max()) + 0.5
+    plan = F.Plan(xi, kernel="energy", n_ft=1024, R=R, sorting=True, grad=True,
+                  n_max=300, m_max=200)
+    xd, yd, wd, vd = to_dev(x, y, w, v)
+    xa, ya, wa = (t.clone().requires_grad_(True) for t in (xd, yd, wd))
+    s = F.FastSum.apply(plan, xa, ya, wa)
+    (s * vd).sum().backward()
+    plan(xd, wd, yd)
+    gx, gy, gw = plan.grad(vd, want_x=True)
+    for a, b in ((xa.grad, gx), (ya.grad, gy), (wa.grad, gw)):
+        assert torch.equal(a, b)
+    plan.close()
+
+
+def test_sorted_gradient_subsets():
+    """Requesting one adjoint alone computes only its pieces and gives the
+    same values as requesting all three."""
+    import paper_2410_01316_amd as F
+    x, y, w, v = _grid_points(400, 300, 3, seed=61)
+    xi = directions("distance", 3, 24, 9)
+    R = float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max()) + 0.5
+    plan = F.Plan(xi, kernel="energy", n_ft=1024, R=R, sorting=True, grad=True,
+                  n_max=400, m_max=300)
+    xd, yd, wd, vd = to_dev(x, y, w, v)
+    plan(xd, wd, yd)
+    gx, gy, gw = (t.cpu().numpy() for t in plan.grad(vd, want_x=True))
+    gy1, _ = plan.grad(vd, want_y=True, want_w=False)
+    _, gw1 = plan.grad(vd, want_y=False, want_w=True)
+    gx1, _, _ = plan.grad(vd, want_x=True, want_y=False, want_w=False)
+    plan.close()
+    assert np.array_equal(gy1.cpu().numpy(), gy)
+    assert np.array_equal(gw1.cpu().numpy(), gw)
+    assert np.array_equal(gx1.cpu().numpy(), gx)
