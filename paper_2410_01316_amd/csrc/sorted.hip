@@ -179,6 +179,9 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
 }
 
 // Both directions are stable: equal keys keep the order of their positions.
+// The radix order puts -0.0 below +0.0; the projections never produce -0.0
+// (their accumulations start from +0.0, and +0.0 + -0.0 = +0.0), so equal
+// keys are equal bit patterns.
 hipError_t run_sort(void* temp, size_t& temp_bytes, const float* keys_in, float* keys_out,
                     unsigned int* vals_out, int64_t L, int P, int n_tot, hipStream_t stream,
                     bool descending = false) {
