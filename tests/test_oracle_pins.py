@@ -566,3 +566,25 @@ def test_sliced_energy_gradients_match_finite_differences():
     tie_only = gy1[3] - gy0[3]
     t = (x[5] - y[3]) @ xi
     assert np.all(t == 0.0) and np.allclose(tie_only, 0.0, atol=1e-15)
+
+
+def test_distance_energy_gradient_and_adam():
+    """The distance-energy gradient against central differences; the
+    projected Adam iteration keeps unit rows, raises the energy, and for
+    P <= d ends at an orthonormal system, the minimiser of App. H."""
+    rng = np.random.default_rng(33)
+    xi = rng.standard_normal((7, 4))
+    xi /= np.linalg.norm(xi, axis=1, keepdims=True)
+    g = O.distance_energy_grad(xi)
+    h = 1e-6
+    for (p, i) in [(0, 0), (3, 2), (6, 3)]:
+        e = np.zeros_like(xi)
+        e[p, i] = h
+        fd = (O.distance_energy(xi + e) - O.distance_energy(xi - e)) / (2 * h) / 2
+        assert abs(fd - g[p, i]) < 1e-6 * (1 + abs(g[p, i]))
+    out = O.projected_adam(xi, 300, 0.02)
+    assert np.allclose(np.linalg.norm(out, axis=1), 1.0, atol=1e-12)
+    assert O.distance_energy(out) > O.distance_energy(xi)
+    x0 = rng.standard_normal((5, 5))
+    orth = O.projected_adam(x0, 2000, 0.05)
+    assert np.abs(orth @ orth.T - np.eye(5)).max() < 1e-3
