@@ -365,6 +365,24 @@ FASTSUM_API fastsum_status fastsum_batch_check(fastsum_batch batch);
 FASTSUM_API void fastsum_batch_destroy(fastsum_batch batch);
 
 /*
+ * Distance QMC directions (App. H): iters projected Adam steps that raise
+ * sum_{p,q} |xi_p - xi_q| + |xi_p + xi_q| (the symmetrised distance energy
+ * of eq. distance-sym, lowered), each step on the tangent part of the
+ * gradient followed by renormalising the rows; the step size falls
+ * linearly from lr to lr/10 (Adam moments 0.9, 0.999).
+ *   xi      device, P x d row-major (row p is direction p; the transpose of
+ *           the d x P layout fastsum_plan_create takes): unit rows in, the
+ *           design out (in place)
+ *   d       1..64;  P >= 1;  iters >= 0;  lr > 0
+ *   stream  the steps run on it; the call returns after they finish
+ * Allocates 12 P d bytes of workspace for the call.  FP32 arithmetic; the
+ * randomisation of App. E (a random rotation) is the caller's.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t iters, double lr,
+                                                float* xi, void* stream);
+
+/*
  * Host-only N_ft selection rule: the smallest candidate N_ft whose discarded
  * Fourier mass sum_{|k| > N_ft/2} |c_k| is at most tol * sum_k |c_k| (FP64,
  * c_k of prm's kernel, d, scale, T, R; tails summed to |k| = 4096).  Falls

@@ -79,6 +79,8 @@ SIGNATURES = {
     "fastsum_choose_nft": (_st, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]),
     "fastsum_profile_read": (_st, [_vp, _vp, _vp]),
+    "fastsum_distance_qmc": (_st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   _vp, _vp]),
 }
 
 _lib = None

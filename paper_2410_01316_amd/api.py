@@ -196,6 +196,34 @@ def kernel_sum(x, y, w, xi, *, kernel, scale=1.0, n_ft=None, R=None, sorting=Fal
     return s
 
 
+def distance_qmc(d, P, *, iters=400, lr=None, seed=0, rotate=True, device=None):
+    """Distance QMC directions (App. H) built on the GPU by
+    fastsum_distance_qmc: `iters` projected Adam steps from P seeded i.i.d.
+    unit vectors (d <= 64), then, with `rotate`, a seeded random rotation
+    (App. E) so the sliced estimator stays unbiased.  Returns the (d, P)
+    float32 array of unit columns that Plan takes."""
+    lib = L.load()
+    rng = np.random.default_rng(seed)
+    x0 = rng.standard_normal((P, d))
+    x0 /= np.linalg.norm(x0, axis=1, keepdims=True)
+    if lr is None:
+        lr = 0.05 * P ** (-1.0 / max(d - 1, 1))
+    dev = torch.device(device if device is not None else "cuda")
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    t = torch.from_numpy(x0.astype(np.float32)).to(dev)
+    with torch.cuda.device(dev):
+        st = lib.fastsum_distance_qmc(int(d), int(P), int(iters), float(lr), _ptr(t),
+                                      _stream_ptr(dev))
+    L.check(st, "fastsum_distance_qmc")
+    xi = t.cpu().numpy().astype(np.float64).T
+    if rotate:
+        q, r = np.linalg.qr(rng.standard_normal((d, d)))
+        xi = (q * np.sign(np.diag(r))) @ xi
+    xi /= np.linalg.norm(xi, axis=0, keepdims=True)
+    return xi.astype(np.float32)
+
+
 def host_tables(kernel, d, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0, window_w=0,
                 oversample=0):
     """FP64 host precompute of a plan without touching a device:

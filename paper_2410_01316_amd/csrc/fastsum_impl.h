@@ -171,6 +171,12 @@ hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned in
                               int M, const float* w, const float* v, double coef, float* Ty,
                               float* Tx, float* U, int64_t ldm, int want, hipStream_t stream);
 
+// ---- distance QMC directions (qmc.hip) ----
+// iters projected Adam steps on the rows of xi (P x d, d <= 64, unit rows)
+// in place; grad, m, v: P x d workspaces.
+hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* grad, float* m,
+                        float* v, hipStream_t st);
+
 // ---- batched form: one persistent launch per phase over a task list ----
 
 // Everything one problem of a batch needs on the device.

@@ -1135,6 +1135,28 @@ fastsum_status fastsum_debug_read(fastsum_plan pl, int32_t which, float* host_ou
     return FASTSUM_OK;
 }
 
+fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t iters, double lr, float* xi,
+                                    void* stream) {
+    if (!xi || d < 1 || d > 64 || P < 1 || iters < 0 || !(lr > 0.0) || !std::isfinite(lr))
+        return FASTSUM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    float *grad = nullptr, *m = nullptr, *v = nullptr;
+    const size_t n = (size_t)P * d;
+    if (!dev_alloc(&grad, n) || !dev_alloc(&m, n) || !dev_alloc(&v, n)) {
+        if (grad) (void)hipFree(grad);
+        if (m) (void)hipFree(m);
+        if (v) (void)hipFree(v);
+        return FASTSUM_ENOMEM;
+    }
+    hipError_t e = distance_qmc(xi, P, d, iters, lr, grad, m, v, st);
+    const hipError_t es = hipStreamSynchronize(st);
+    (void)hipFree(grad);
+    (void)hipFree(m);
+    (void)hipFree(v);
+    if (e == hipErrorInvalidValue) return FASTSUM_EINVAL;
+    return (e == hipSuccess && es == hipSuccess) ? FASTSUM_OK : FASTSUM_EDEVICE;
+}
+
 fastsum_status fastsum_set_launch(fastsum_plan pl, int64_t chunk_len, int32_t dir_range) {
     if (!pl || chunk_len < 0 || chunk_len % kChunkAlign != 0 || chunk_len > kMaxChunk ||
         dir_range < 0 || dir_range % kFuseDirs != 0)

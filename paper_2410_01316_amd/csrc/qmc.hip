@@ -1,0 +1,124 @@
+// Distance QMC designs on the GPU (App. H): P unit directions that locally
+// maximise sum_{p,q} (|xi_p - xi_q| + |xi_p + xi_q|) (the symmetrised
+// distance energy of eq. distance-sym with its sign reversed), by projected
+// Adam steps from a given start.  Rows of xi are directions (P x d, FP32).
+//
+// Gradient of row p:  xi_p sum_q (a_pq + b_pq) + sum_q (b_pq - a_pq) xi_q,
+// a_pq = 1/|xi_p - xi_q| (0 for q = p), b_pq = 1/|xi_p + xi_q|, with
+// |xi_p -+ xi_q|^2 = 2 -+ 2 <xi_p, xi_q> for unit rows; then its tangent
+// part.  One thread per row p holds xi_p and its accumulator in registers
+// (d <= 64, zero-padded to DMAX); the rows q stream through LDS in tiles of
+// 64 and are read as broadcasts.
+#include "fastsum_impl.h"
+
+#include <cmath>
+
+namespace fastsum {
+
+namespace {
+
+constexpr int kQmcBlock = 256;
+constexpr int kQmcTile = 64;
+
+template <int DMAX>
+__global__ __launch_bounds__(kQmcBlock) void qmc_grad_kernel(const float* __restrict__ xi, int P,
+                                                             int d, float* __restrict__ grad) {
+    __shared__ float tile[kQmcTile][DMAX];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x * kQmcBlock + tid;
+    float xp[DMAX], acc[DMAX];
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+        xp[i] = (p < P && i < d) ? xi[(int64_t)p * d + i] : 0.f;
+        acc[i] = 0.f;
+    }
+    float s = 0.f;
+    for (int q0 = 0; q0 < P; q0 += kQmcTile) {
+        __syncthreads();
+        for (int j = tid; j < kQmcTile * DMAX; j += kQmcBlock) {
+            const int r = j / DMAX, i = j % DMAX;
+            tile[r][i] = (q0 + r < P && i < d) ? xi[(int64_t)(q0 + r) * d + i] : 0.f;
+        }
+        __syncthreads();
+        const int nq = min(kQmcTile, P - q0);
+        for (int r = 0; r < nq; ++r) {
+            float g = 0.f;
+#pragma unroll
+            for (int i = 0; i < DMAX; ++i) g = fmaf(xp[i], tile[r][i], g);
+            g = fminf(1.f, fmaxf(-1.f, g));
+            const float a = (q0 + r == p) ? 0.f : rsqrtf(fmaxf(2.f - 2.f * g, 1e-24f));
+            const float b = rsqrtf(fmaxf(2.f + 2.f * g, 1e-24f));
+            s += a + b;
+            const float c = b - a;
+#pragma unroll
+            for (int i = 0; i < DMAX; ++i) acc[i] = fmaf(c, tile[r][i], acc[i]);
+        }
+    }
+    if (p >= P) return;
+    float radial = 0.f;
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+        acc[i] = fmaf(s, xp[i], acc[i]);
+        radial = fmaf(acc[i], xp[i], radial);
+    }
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i)
+        if (i < d) grad[(int64_t)p * d + i] = acc[i] - radial * xp[i];
+}
+
+// Adam step on every row, then renormalisation: m, v moments (taken as
+// zero before the first step); bc1, bc2 the bias corrections 1 - beta^it;
+// step the iteration's step size.
+__global__ __launch_bounds__(kQmcBlock) void qmc_adam_kernel(
+    float* __restrict__ xi, const float* __restrict__ grad, float* __restrict__ m,
+    float* __restrict__ v, int P, int d, float step, float bc1, float bc2, int first) {
+    const int p = blockIdx.x * kQmcBlock + threadIdx.x;
+    if (p >= P) return;
+    constexpr float b1 = 0.9f, b2 = 0.999f, eps = 1e-12f;
+    float* __restrict__ x = xi + (int64_t)p * d;
+    float ss = 0.f;
+    for (int i = 0; i < d; ++i) {
+        const int64_t k = (int64_t)p * d + i;
+        const float g = grad[k];
+        const float mi = (first ? 0.f : b1 * m[k]) + (1.f - b1) * g;
+        const float vi = (first ? 0.f : b2 * v[k]) + (1.f - b2) * g * g;
+        m[k] = mi;
+        v[k] = vi;
+        const float xn = x[i] + step * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        x[i] = xn;
+        ss = fmaf(xn, xn, ss);
+    }
+    const float inv = rsqrtf(ss);
+    for (int i = 0; i < d; ++i) x[i] *= inv;
+}
+
+template <int DMAX>
+void launch_qmc_grad(const float* xi, int P, int d, float* grad, hipStream_t st) {
+    hipLaunchKernelGGL(qmc_grad_kernel<DMAX>, dim3((unsigned)((P + kQmcBlock - 1) / kQmcBlock)),
+                       dim3(kQmcBlock), 0, st, xi, P, d, grad);
+}
+
+}  // namespace
+
+hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* grad, float* m,
+                        float* v, hipStream_t st) {
+    if (P < 1 || d < 1 || d > 64 || iters < 0) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    const dim3 grid((unsigned)((P + kQmcBlock - 1) / kQmcBlock));
+    double p1 = 1.0, p2 = 1.0;
+    for (int it = 1; it <= iters; ++it) {
+        if (d <= 16) launch_qmc_grad<16>(xi, P, d, grad, st);
+        else if (d <= 32) launch_qmc_grad<32>(xi, P, d, grad, st);
+        else launch_qmc_grad<64>(xi, P, d, grad, st);
+        p1 *= 0.9;
+        p2 *= 0.999;
+        const double step = lr * (1.0 - 0.9 * it / iters);
+        hipLaunchKernelGGL(qmc_adam_kernel, grid, dim3(kQmcBlock), 0, st, xi, grad, m, v, P, d,
+                           (float)step, (float)(1.0 - p1), (float)(1.0 - p2), it == 1 ? 1 : 0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace fastsum
