@@ -339,6 +339,41 @@ def copy_calibration():
     return a.numel() * 4
 
 
+def qmc_form(d=50, P=3500, iters=200):
+    """Distance-QMC construction (App. H) on the GPU: ms per projected Adam
+    step of fastsum_distance_qmc (FP32 kernels) beside the same iteration in
+    FP64 torch (the generator the workloads use); the gradient costs about
+    4 d + 12 flops per (p, q) pair."""
+    import ctypes
+    import torch
+    import paper_2410_01316_amd as F
+    from paper_2410_01316_amd import _lib as L
+    from workloads.directions import _distance_qmc_torch
+    rng = np.random.default_rng(0)
+    x0 = rng.standard_normal((P, d))
+    x0 /= np.linalg.norm(x0, axis=1, keepdims=True)
+    lr = 0.05 * P ** (-1.0 / (d - 1))
+    t = torch.from_numpy(x0.astype(np.float32)).cuda()
+    lib = F.load_library()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L.check(lib.fastsum_distance_qmc(d, P, 5, lr, ctypes.c_void_p(t.data_ptr()), stream), "qmc")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.check(lib.fastsum_distance_qmc(d, P, iters, lr, ctypes.c_void_p(t.data_ptr()), stream), "qmc")
+    ms = (time.perf_counter() - t0) * 1e3 / iters
+    ref_iters = 20
+    _distance_qmc_torch(x0, 2, lr, "cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _distance_qmc_torch(x0, ref_iters, lr, "cuda")
+    torch.cuda.synchronize()
+    ms_ref = (time.perf_counter() - t0) * 1e3 / ref_iters
+    flops = P * P * (4.0 * d + 12.0)
+    return dict(d=d, P=P, ms_per_step=round(ms, 4), torch_fp64_ms_per_step=round(ms_ref, 4),
+                achieved_TFs=flops / (ms * 1e-3) / 1e12, peak_TFs=PEAK["fp32_valu_TFs"],
+                note="energy gradient on the vector ALUs (FP32), P^2 (4d + 12) flops per step")
+
+
 def form_runners(fsteps):
     """(name, thunk) of every further form: other kernels, the precision
     workload, the MMD shapes, the flow and the batched form."""
@@ -369,6 +404,7 @@ def form_runners(fsteps):
         ("mmd_energy_sorted_fwd_grad", lambda: mmd("energy", grad=True, sorting=True)),
         ("mmd_flow_energy_d3072", lambda: mmd_flow_form(fsteps)),
         ("batched_256", lambda: batched_form(fsteps, None)),
+        ("qmc_distance_d50_P3500", lambda: qmc_form()),
     ]
 
 

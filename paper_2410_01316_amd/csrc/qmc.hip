@@ -11,6 +11,7 @@
 // 64 and are read as broadcasts.
 #include "fastsum_impl.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace fastsum {
@@ -18,14 +19,20 @@ namespace fastsum {
 namespace {
 
 constexpr int kQmcBlock = 256;
-constexpr int kQmcTile = 64;
+constexpr int kQmcRows = 64;         // rows p per gradient workgroup (one wave)
+constexpr int kQmcTile = 64;         // rows q per LDS tile
 
+// Partial gradient sums of rows p0 .. p0+63 over the rows q of chunk
+// blockIdx.y (qlen rows each, a multiple of the tile): part[(chunk P + p)
+// (DMAX + 1) + i] = sum_q (b - a) xi_q[i] for i < DMAX, and at i = DMAX
+// sum_q (a + b).
 template <int DMAX>
-__global__ __launch_bounds__(kQmcBlock) void qmc_grad_kernel(const float* __restrict__ xi, int P,
-                                                             int d, float* __restrict__ grad) {
+__global__ __launch_bounds__(kQmcRows) void qmc_grad_partial_kernel(
+    const float* __restrict__ xi, int P, int d, int qlen, float* __restrict__ part) {
     __shared__ float tile[kQmcTile][DMAX];
     const int tid = threadIdx.x;
-    const int p = blockIdx.x * kQmcBlock + tid;
+    const int p = blockIdx.x * kQmcRows + tid;
+    const int q_begin = blockIdx.y * qlen, q_end = min(P, q_begin + qlen);
     float xp[DMAX], acc[DMAX];
 #pragma unroll
     for (int i = 0; i < DMAX; ++i) {
@@ -33,14 +40,14 @@ __global__ __launch_bounds__(kQmcBlock) void qmc_grad_kernel(const float* __rest
         acc[i] = 0.f;
     }
     float s = 0.f;
-    for (int q0 = 0; q0 < P; q0 += kQmcTile) {
+    for (int q0 = q_begin; q0 < q_end; q0 += kQmcTile) {
         __syncthreads();
-        for (int j = tid; j < kQmcTile * DMAX; j += kQmcBlock) {
+        for (int j = tid; j < kQmcTile * DMAX; j += kQmcRows) {
             const int r = j / DMAX, i = j % DMAX;
-            tile[r][i] = (q0 + r < P && i < d) ? xi[(int64_t)(q0 + r) * d + i] : 0.f;
+            tile[r][i] = (q0 + r < q_end && i < d) ? xi[(int64_t)(q0 + r) * d + i] : 0.f;
         }
         __syncthreads();
-        const int nq = min(kQmcTile, P - q0);
+        const int nq = min(kQmcTile, q_end - q0);
         for (int r = 0; r < nq; ++r) {
             float g = 0.f;
 #pragma unroll
@@ -55,6 +62,33 @@ __global__ __launch_bounds__(kQmcBlock) void qmc_grad_kernel(const float* __rest
         }
     }
     if (p >= P) return;
+    float* __restrict__ dst = part + ((int64_t)blockIdx.y * P + p) * (DMAX + 1);
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) dst[i] = acc[i];
+    dst[DMAX] = s;
+}
+
+// grad_p = tangent part of (s xi_p + acc), the chunk partials summed in
+// chunk order.
+template <int DMAX>
+__global__ __launch_bounds__(kQmcBlock) void qmc_grad_finish_kernel(
+    const float* __restrict__ xi, int P, int d, int nchunk, const float* __restrict__ part,
+    float* __restrict__ grad) {
+    const int p = blockIdx.x * kQmcBlock + threadIdx.x;
+    if (p >= P) return;
+    float acc[DMAX], xp[DMAX];
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+        acc[i] = 0.f;
+        xp[i] = i < d ? xi[(int64_t)p * d + i] : 0.f;
+    }
+    for (int c = 0; c < nchunk; ++c) {
+        const float* __restrict__ src = part + ((int64_t)c * P + p) * (DMAX + 1);
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i) acc[i] += src[i];
+        s += src[DMAX];
+    }
     float radial = 0.f;
 #pragma unroll
     for (int i = 0; i < DMAX; ++i) {
@@ -92,24 +126,44 @@ __global__ __launch_bounds__(kQmcBlock) void qmc_adam_kernel(
     for (int i = 0; i < d; ++i) x[i] *= inv;
 }
 
+// q-chunks so that the gradient has about 2048 workgroups (at least 8 per
+// CU), each chunk a whole number of tiles
+int qmc_chunk_len(int P) {
+    const int pblocks = (P + kQmcRows - 1) / kQmcRows;
+    const int tiles = (P + kQmcTile - 1) / kQmcTile;
+    const int want = std::max(1, std::min(tiles, (2048 + pblocks - 1) / pblocks));
+    return ((tiles + want - 1) / want) * kQmcTile;
+}
+
 template <int DMAX>
-void launch_qmc_grad(const float* xi, int P, int d, float* grad, hipStream_t st) {
-    hipLaunchKernelGGL(qmc_grad_kernel<DMAX>, dim3((unsigned)((P + kQmcBlock - 1) / kQmcBlock)),
-                       dim3(kQmcBlock), 0, st, xi, P, d, grad);
+void launch_qmc_grad(const float* xi, int P, int d, float* part, float* grad, hipStream_t st) {
+    const int qlen = qmc_chunk_len(P);
+    const int nchunk = (P + qlen - 1) / qlen;
+    hipLaunchKernelGGL(qmc_grad_partial_kernel<DMAX>,
+                       dim3((unsigned)((P + kQmcRows - 1) / kQmcRows), (unsigned)nchunk),
+                       dim3(kQmcRows), 0, st, xi, P, d, qlen, part);
+    hipLaunchKernelGGL(qmc_grad_finish_kernel<DMAX>,
+                       dim3((unsigned)((P + kQmcBlock - 1) / kQmcBlock)), dim3(kQmcBlock), 0, st,
+                       xi, P, d, nchunk, part, grad);
 }
 
 }  // namespace
 
+size_t distance_qmc_part_floats(int P) {
+    const int qlen = qmc_chunk_len(P);
+    return (size_t)((P + qlen - 1) / qlen) * P * (64 + 1);
+}
+
 hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* grad, float* m,
-                        float* v, hipStream_t st) {
+                        float* v, float* part, hipStream_t st) {
     if (P < 1 || d < 1 || d > 64 || iters < 0) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     const dim3 grid((unsigned)((P + kQmcBlock - 1) / kQmcBlock));
     double p1 = 1.0, p2 = 1.0;
     for (int it = 1; it <= iters; ++it) {
-        if (d <= 16) launch_qmc_grad<16>(xi, P, d, grad, st);
-        else if (d <= 32) launch_qmc_grad<32>(xi, P, d, grad, st);
-        else launch_qmc_grad<64>(xi, P, d, grad, st);
+        if (d <= 16) launch_qmc_grad<16>(xi, P, d, part, grad, st);
+        else if (d <= 32) launch_qmc_grad<32>(xi, P, d, part, grad, st);
+        else launch_qmc_grad<64>(xi, P, d, part, grad, st);
         p1 *= 0.9;
         p2 *= 0.999;
         const double step = lr * (1.0 - 0.9 * it / iters);
