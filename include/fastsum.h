@@ -375,7 +375,7 @@ FASTSUM_API void fastsum_batch_destroy(fastsum_batch batch);
  *           design out (in place)
  *   d       1..64;  P >= 1;  iters >= 0;  lr > 0
  *   stream  the steps run on it; the call returns after they finish
- * Allocates its workspace for the call (12 P d bytes plus partial sums of
+ * Allocates its workspace for the call (8 P d bytes plus partial sums of
  * at most 260 P ceil(2048 / ceil(P/64)) bytes).  FP32 arithmetic; the
  * randomisation of App. E (a random rotation) is the caller's.
  * Errors: EINVAL, ENOMEM, EDEVICE.

@@ -173,10 +173,10 @@ hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned in
 
 // ---- distance QMC directions (qmc.hip) ----
 // iters projected Adam steps on the rows of xi (P x d, d <= 64, unit rows)
-// in place; grad, m, v: P x d workspaces; part: distance_qmc_part_floats(P).
+// in place; m, v: P x d workspaces; part: distance_qmc_part_floats(P).
 size_t distance_qmc_part_floats(int P);
-hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* grad, float* m,
-                        float* v, float* part, hipStream_t st);
+hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* m, float* v,
+                        float* part, hipStream_t st);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

@@ -1140,17 +1140,16 @@ fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t iters, double 
     if (!xi || d < 1 || d > 64 || P < 1 || iters < 0 || !(lr > 0.0) || !std::isfinite(lr))
         return FASTSUM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    float *grad = nullptr, *m = nullptr, *v = nullptr, *part = nullptr;
+    float *m = nullptr, *v = nullptr, *part = nullptr;
     const size_t n = (size_t)P * d;
-    if (!dev_alloc(&grad, n) || !dev_alloc(&m, n) || !dev_alloc(&v, n) ||
-        !dev_alloc(&part, distance_qmc_part_floats(P))) {
-        for (float* b : {grad, m, v, part})
+    if (!dev_alloc(&m, n) || !dev_alloc(&v, n) || !dev_alloc(&part, distance_qmc_part_floats(P))) {
+        for (float* b : {m, v, part})
             if (b) (void)hipFree(b);
         return FASTSUM_ENOMEM;
     }
-    hipError_t e = distance_qmc(xi, P, d, iters, lr, grad, m, v, part, st);
+    hipError_t e = distance_qmc(xi, P, d, iters, lr, m, v, part, st);
     const hipError_t es = hipStreamSynchronize(st);
-    for (float* b : {grad, m, v, part}) (void)hipFree(b);
+    for (float* b : {m, v, part}) (void)hipFree(b);
     if (e == hipErrorInvalidValue) return FASTSUM_EINVAL;
     return (e == hipSuccess && es == hipSuccess) ? FASTSUM_OK : FASTSUM_EDEVICE;
 }

@@ -68,62 +68,45 @@ __global__ __launch_bounds__(kQmcRows) void qmc_grad_partial_kernel(
     dst[DMAX] = s;
 }
 
-// grad_p = tangent part of (s xi_p + acc), the chunk partials summed in
-// chunk order.
-template <int DMAX>
-__global__ __launch_bounds__(kQmcBlock) void qmc_grad_finish_kernel(
-    const float* __restrict__ xi, int P, int d, int nchunk, const float* __restrict__ part,
-    float* __restrict__ grad) {
-    const int p = blockIdx.x * kQmcBlock + threadIdx.x;
-    if (p >= P) return;
-    float acc[DMAX], xp[DMAX];
-    float s = 0.f;
+__device__ __forceinline__ float qmc_wave_sum(float v) {
 #pragma unroll
-    for (int i = 0; i < DMAX; ++i) {
-        acc[i] = 0.f;
-        xp[i] = i < d ? xi[(int64_t)p * d + i] : 0.f;
-    }
-    for (int c = 0; c < nchunk; ++c) {
-        const float* __restrict__ src = part + ((int64_t)c * P + p) * (DMAX + 1);
-#pragma unroll
-        for (int i = 0; i < DMAX; ++i) acc[i] += src[i];
-        s += src[DMAX];
-    }
-    float radial = 0.f;
-#pragma unroll
-    for (int i = 0; i < DMAX; ++i) {
-        acc[i] = fmaf(s, xp[i], acc[i]);
-        radial = fmaf(acc[i], xp[i], radial);
-    }
-#pragma unroll
-    for (int i = 0; i < DMAX; ++i)
-        if (i < d) grad[(int64_t)p * d + i] = acc[i] - radial * xp[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
-// Adam step on every row, then renormalisation: m, v moments (taken as
-// zero before the first step); bc1, bc2 the bias corrections 1 - beta^it;
-// step the iteration's step size.
-__global__ __launch_bounds__(kQmcBlock) void qmc_adam_kernel(
-    float* __restrict__ xi, const float* __restrict__ grad, float* __restrict__ m,
-    float* __restrict__ v, int P, int d, float step, float bc1, float bc2, int first) {
-    const int p = blockIdx.x * kQmcBlock + threadIdx.x;
-    if (p >= P) return;
+// One wave per row p, lane i for coordinate i (d <= 64): the chunk partials
+// summed in chunk order give g = tangent part of (s xi_p + acc); then the
+// Adam step (moments m, v taken as zero before the first step; bc1, bc2 the
+// bias corrections 1 - beta^it) and the renormalisation of the row.
+__global__ __launch_bounds__(kQmcBlock) void qmc_step_kernel(
+    float* __restrict__ xi, int P, int d, int nchunk, int stride,
+    const float* __restrict__ part, float* __restrict__ m, float* __restrict__ v, float step,
+    float bc1, float bc2, int first) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * (kQmcBlock / 64) + (threadIdx.x >> 6);
+    if (p >= P) return;                        // whole waves; no barriers below
     constexpr float b1 = 0.9f, b2 = 0.999f, eps = 1e-12f;
-    float* __restrict__ x = xi + (int64_t)p * d;
-    float ss = 0.f;
-    for (int i = 0; i < d; ++i) {
-        const int64_t k = (int64_t)p * d + i;
-        const float g = grad[k];
+    const bool on = lane < d;
+    const int64_t k = (int64_t)p * d + lane;
+    const float x = on ? xi[k] : 0.f;
+    float acc = 0.f, s = 0.f;
+    for (int c = 0; c < nchunk; ++c) {
+        const float* __restrict__ src = part + ((int64_t)c * P + p) * stride;
+        if (on) acc += src[lane];
+        s += src[stride - 1];
+    }
+    float g = fmaf(s, x, acc);
+    g -= qmc_wave_sum(g * x) * x;
+    float xn = 0.f;
+    if (on) {
         const float mi = (first ? 0.f : b1 * m[k]) + (1.f - b1) * g;
         const float vi = (first ? 0.f : b2 * v[k]) + (1.f - b2) * g * g;
         m[k] = mi;
         v[k] = vi;
-        const float xn = x[i] + step * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-        x[i] = xn;
-        ss = fmaf(xn, xn, ss);
+        xn = x + step * (mi / bc1) / (sqrtf(vi / bc2) + eps);
     }
-    const float inv = rsqrtf(ss);
-    for (int i = 0; i < d; ++i) x[i] *= inv;
+    const float inv = rsqrtf(qmc_wave_sum(xn * xn));
+    if (on) xi[k] = xn * inv;
 }
 
 // q-chunks so that the gradient has about 2048 workgroups (at least 8 per
@@ -136,15 +119,13 @@ int qmc_chunk_len(int P) {
 }
 
 template <int DMAX>
-void launch_qmc_grad(const float* xi, int P, int d, float* part, float* grad, hipStream_t st) {
+int launch_qmc_partial(const float* xi, int P, int d, float* part, hipStream_t st) {
     const int qlen = qmc_chunk_len(P);
     const int nchunk = (P + qlen - 1) / qlen;
     hipLaunchKernelGGL(qmc_grad_partial_kernel<DMAX>,
                        dim3((unsigned)((P + kQmcRows - 1) / kQmcRows), (unsigned)nchunk),
                        dim3(kQmcRows), 0, st, xi, P, d, qlen, part);
-    hipLaunchKernelGGL(qmc_grad_finish_kernel<DMAX>,
-                       dim3((unsigned)((P + kQmcBlock - 1) / kQmcBlock)), dim3(kQmcBlock), 0, st,
-                       xi, P, d, nchunk, part, grad);
+    return nchunk;
 }
 
 }  // namespace
@@ -154,21 +135,24 @@ size_t distance_qmc_part_floats(int P) {
     return (size_t)((P + qlen - 1) / qlen) * P * (64 + 1);
 }
 
-hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* grad, float* m,
-                        float* v, float* part, hipStream_t st) {
+hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* m, float* v,
+                        float* part, hipStream_t st) {
     if (P < 1 || d < 1 || d > 64 || iters < 0) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
-    const dim3 grid((unsigned)((P + kQmcBlock - 1) / kQmcBlock));
+    const dim3 grid((unsigned)((P + kQmcBlock / 64 - 1) / (kQmcBlock / 64)));
+    const int dmax = d <= 16 ? 16 : d <= 32 ? 32 : 64;
     double p1 = 1.0, p2 = 1.0;
     for (int it = 1; it <= iters; ++it) {
-        if (d <= 16) launch_qmc_grad<16>(xi, P, d, part, grad, st);
-        else if (d <= 32) launch_qmc_grad<32>(xi, P, d, part, grad, st);
-        else launch_qmc_grad<64>(xi, P, d, part, grad, st);
+        int nchunk;
+        if (dmax == 16) nchunk = launch_qmc_partial<16>(xi, P, d, part, st);
+        else if (dmax == 32) nchunk = launch_qmc_partial<32>(xi, P, d, part, st);
+        else nchunk = launch_qmc_partial<64>(xi, P, d, part, st);
         p1 *= 0.9;
         p2 *= 0.999;
         const double step = lr * (1.0 - 0.9 * it / iters);
-        hipLaunchKernelGGL(qmc_adam_kernel, grid, dim3(kQmcBlock), 0, st, xi, grad, m, v, P, d,
-                           (float)step, (float)(1.0 - p1), (float)(1.0 - p2), it == 1 ? 1 : 0);
+        hipLaunchKernelGGL(qmc_step_kernel, grid, dim3(kQmcBlock), 0, st, xi, P, d, nchunk,
+                           dmax + 1, part, m, v, (float)step, (float)(1.0 - p1),
+                           (float)(1.0 - p2), it == 1 ? 1 : 0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
