@@ -6,9 +6,11 @@
 // Gradient of row p:  xi_p sum_q (a_pq + b_pq) + sum_q (b_pq - a_pq) xi_q,
 // a_pq = 1/|xi_p - xi_q| (0 for q = p), b_pq = 1/|xi_p + xi_q|, with
 // |xi_p -+ xi_q|^2 = 2 -+ 2 <xi_p, xi_q> for unit rows; then its tangent
-// part.  One thread per row p holds xi_p and its accumulator in registers
-// (d <= 64, zero-padded to DMAX); the rows q stream through LDS in tiles of
-// 64 and are read as broadcasts.
+// part.  In the partial-gradient kernel one thread per row p holds xi_p and
+// its accumulator in registers (d <= 64, zero-padded to DMAX) while the rows
+// q of one q-chunk stream through LDS in tiles of 64, read as broadcasts;
+// a second kernel, one wave per row, sums the chunks in order and takes the
+// Adam step.
 #include "fastsum_impl.h"
 
 #include <algorithm>
