@@ -60,3 +60,8 @@ def test_api_and_errors():
     assert np.allclose(np.linalg.norm(xi, axis=0), 1.0, atol=1e-6)
     with pytest.raises(F.FastSumError):
         F.distance_qmc(65, 10, iters=1)
+
+
+def test_reproducible():
+    x0 = _start(700, 20, 5)
+    assert np.array_equal(_run(x0, 30, 0.02), _run(x0, 30, 0.02))

@@ -305,3 +305,24 @@ def test_sorted_gradient_subsets():
     assert np.array_equal(gy1.cpu().numpy(), gy)
     assert np.array_equal(gw1.cpu().numpy(), gw)
     assert np.array_equal(gx1.cpu().numpy(), gx)
+
+
+def test_sorted_bitwise_reproducible():
+    """The stable sorts and the fixed-order scans make repeated calls
+    bitwise identical, gradients included."""
+    import paper_2410_01316_amd as F
+    x, y, w, v = _grid_points(2000, 1500, 3, seed=71)
+    x = x + np.random.default_rng(72).standard_normal(x.shape) * 0.01
+    xi = directions("distance", 3, 40, 10)
+    R = float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max()) + 0.5
+    plan = F.Plan(xi, kernel="energy", n_ft=1024, R=R, sorting=True, grad=True,
+                  n_max=2000, m_max=1500)
+    xd, yd, wd, vd = to_dev(x, y, w, v)
+    runs = []
+    for _ in range(2):
+        s = plan(xd, wd, yd).cpu().numpy()
+        g = [t.cpu().numpy() for t in plan.grad(vd, want_x=True)]
+        runs.append([s] + g)
+    plan.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
