@@ -142,12 +142,13 @@ hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* m,
     if (P < 1 || d < 1 || d > 64 || iters < 0) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     const dim3 grid((unsigned)((P + kQmcBlock / 64 - 1) / (kQmcBlock / 64)));
-    const int dmax = d <= 16 ? 16 : d <= 32 ? 32 : 64;
+    const int dmax = d <= 16 ? 16 : d <= 32 ? 32 : d <= 48 ? 48 : 64;
     double p1 = 1.0, p2 = 1.0;
     for (int it = 1; it <= iters; ++it) {
         int nchunk;
         if (dmax == 16) nchunk = launch_qmc_partial<16>(xi, P, d, part, st);
         else if (dmax == 32) nchunk = launch_qmc_partial<32>(xi, P, d, part, st);
+        else if (dmax == 48) nchunk = launch_qmc_partial<48>(xi, P, d, part, st);
         else nchunk = launch_qmc_partial<64>(xi, P, d, part, st);
         p1 *= 0.9;
         p2 *= 0.999;

@@ -65,3 +65,19 @@ def test_api_and_errors():
 def test_reproducible():
     x0 = _start(700, 20, 5)
     assert np.array_equal(_run(x0, 30, 0.02), _run(x0, 30, 0.02))
+
+
+def test_register_widths():
+    """d at the edges of the register-row widths (16, 32, 48, 64): the energy
+    after 20 steps matches the FP64 iteration (Adam's normalised first steps
+    turn FP32-level differences in a near-zero gradient component into a
+    full step of either sign, so single coordinates are not compared), and
+    for P = d the iteration ends orthonormal."""
+    for d in (16, 17, 32, 33, 48, 49, 64):
+        x0 = _start(130, d, d)
+        lr = 0.05 * 130 ** (-1.0 / (d - 1))
+        e_gpu = O.distance_energy(_run(x0, 20, lr))
+        e_ref = O.distance_energy(O.projected_adam(x0, 20, lr))
+        assert abs(e_gpu - e_ref) < 1e-6 * e_ref, d
+        g = _run(_start(d, d, d + 1), 1500, 0.05)
+        assert np.abs(g @ g.T - np.eye(d)).max() < 2e-3, d
