@@ -123,3 +123,30 @@ def test_batch_create_rejects_bad_arguments_without_device():
     assert lib.fastsum_batch_exec(None, None, 0, None) == L.EINVAL
     assert lib.fastsum_batch_check(None) == L.EINVAL
     lib.fastsum_batch_destroy(None)
+
+
+def test_sorted_flag_validation_without_device():
+    """The sorted 1-D sums exist for the energy kernel only (with or without
+    the adjoint); unknown flag bits are rejected; the QMC construction
+    checks its arguments before touching a device."""
+    lib = L.load()
+    tau = ctypes.c_double()
+    ck = np.empty(65)
+    ph = np.empty(129)
+
+    def tables(kernel, flags):
+        prm = L.Params(3, 8, 128, 0, 0, L.KERNELS[kernel], 0, flags, 1.0, 0.0, 0.0, 2.0)
+        return lib.fastsum_host_tables(ctypes.byref(prm), ctypes.byref(tau),
+                                       ck.ctypes.data_as(ctypes.c_void_p),
+                                       ph.ctypes.data_as(ctypes.c_void_p))
+
+    assert tables("energy", L.FLAG_SORTED) == L.OK
+    assert tables("energy", L.FLAG_SORTED | L.FLAG_GRAD) == L.OK
+    for kernel in ("gauss", "laplace", "matern32"):
+        assert tables(kernel, L.FLAG_SORTED) == L.EINVAL
+    assert tables("energy", 8) == L.EINVAL
+    buf = ctypes.c_void_p(1)            # never dereferenced: the arguments fail first
+    assert lib.fastsum_distance_qmc(65, 10, 1, 0.01, buf, None) == L.EINVAL
+    assert lib.fastsum_distance_qmc(3, 0, 1, 0.01, buf, None) == L.EINVAL
+    assert lib.fastsum_distance_qmc(3, 10, 1, 0.0, buf, None) == L.EINVAL
+    assert lib.fastsum_distance_qmc(3, 10, 1, 0.01, None, None) == L.EINVAL
