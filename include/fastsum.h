@@ -222,8 +222,12 @@ FASTSUM_API fastsum_status fastsum_grad(fastsum_plan plan, const float* grad_s,
  *     = w_n du/dx(x_n), u(x) = sum_m v_m K(x, y_m) the transposed sliced sum
  *     (sources y with weights v, targets x) whose derivative grids are
  *     interpolated at the sources and back-projected as for grad_y.
- * grad_w and grad_x share that transposed spreading and FFT.  The weights w
- * of the last exec must still be valid.  Asynchronous.
+ * grad_w and grad_x share that transposed spreading and FFT.  Sorted plans
+ * (FASTSUM_FLAG_SORTED) take the exact derivatives instead: t' is
+ * -(c_d/tau) sum_n w_n sign(y~ - x~_n) from an ascending and a descending sort
+ * (sign(0) = 0), the source side likewise with v, and grad_w the transposed
+ * sorted sums; only the requested outputs are computed.  The weights w of
+ * the last exec must still be valid.  Asynchronous.
  * Errors: ESTATE (no exec yet / plan without GRAD), EINVAL.
  */
 FASTSUM_API fastsum_status fastsum_grad_xyw(fastsum_plan plan, const float* grad_s,
