@@ -128,7 +128,9 @@ typedef enum {
  *                0.1 Laplace, 0.45 energy; must satisfy 0 < T < 0.5
  *   gmax_factor  g_max = gmax_factor * scale (App. I Step 1); default 5
  *   R            bound R >= max_n ||x_n|| + max_m ||y_m|| (App. J,
- *                eq. radius_xy), > 0.  Points violating it set the range flag.
+ *                eq. radius_xy), > 0.  Every exec checks it on the device
+ *                (fastsum_check reports a violation); fastsum_bound computes
+ *                the right-hand side.
  */
 typedef struct {
     int32_t d;
@@ -236,13 +238,34 @@ FASTSUM_API fastsum_status fastsum_grad_xyw(fastsum_plan plan, const float* grad
 
 /*
  * Synchronise the plan's last stream and report device-side conditions:
- * returns ERANGE if an exec since the previous check saw a point outside the
- * plan's bound (results are then unreliable), OK otherwise; clears the flag.
- * Plans that store projections test every projection against tau*R; fused
- * plans test every point, |x| max_p|xi_p| <= R, which bounds all of its
- * projections by tau*R (the slack is 1e-5 relative in both cases).
+ * returns ERANGE if an exec since the previous check violated the plan's
+ * bound (results are then unreliable), OK otherwise; clears the flag.  Two
+ * tests run in every exec, each with a slack of 1e-5 relative:
+ *  - the bound of App. J, eq. radius_xy:
+ *    (max_n |x_n| + max_m |y_m|) max_p |xi_p| <= R, from the row norms
+ *    taken while the points are read; it keeps every difference
+ *    tau <xi_p, x_n - y_m> inside the half period where the periodic
+ *    rescaled kernel equals the true one;
+ *  - per point: plans that store projections test every projection against
+ *    tau*R, fused plans test |x| max_p|xi_p| <= R for every point; this keeps
+ *    every window inside the stored grid cells.
+ * Non-finite coordinates fail both.
  */
 FASTSUM_API fastsum_status fastsum_check(fastsum_plan plan);
+
+/*
+ * The right-hand side of App. J, eq. radius_xy, on the device:
+ *   *bound_out = max_n ||x_n|| + max_m ||y_m||
+ * (Euclidean norms about the origin, FP32 sums of squares, returned as a
+ * double), for x (device, N x d) and y (device, M x d; may equal x).  A
+ * plan created with R >= *bound_out * (1 + 1e-5) passes the bound test of
+ * fastsum_check for these points.  Allocates 8 bytes of device memory for
+ * the call and synchronises `stream`.
+ * Errors: EINVAL, ENOMEM, EDEVICE; ERANGE (with *bound_out = inf or NaN)
+ * when a coordinate is not finite.
+ */
+FASTSUM_API fastsum_status fastsum_bound(const float* x, int64_t N, const float* y, int64_t M,
+                                         int32_t d, void* stream, double* bound_out);
 
 /* Copy plan facts into *info.  EINVAL on NULL. */
 FASTSUM_API fastsum_status fastsum_get_info(fastsum_plan plan, fastsum_plan_info* info);

@@ -81,6 +81,7 @@ SIGNATURES = {
     "fastsum_profile_read": (_st, [_vp, _vp, _vp]),
     "fastsum_distance_qmc": (_st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    _vp, _vp]),
+    "fastsum_bound": (_st, [_vp, _i64, _vp, _i64, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None

@@ -63,6 +63,7 @@ class Plan:
         L.check(st, "fastsum_plan_create")
         self._lib = lib
         self._last = None
+        self.execs = 0                  # calls so far (FastSum checks it in backward)
 
     # -- forward / adjoint ------------------------------------------------
     def __call__(self, x, w, y=None, out=None):
@@ -81,6 +82,7 @@ class Plan:
                                         _stream_ptr(self.device))
         L.check(st, "fastsum_exec")
         self._last = (x, w, y)          # keep the inputs alive for grad
+        self.execs += 1
         return out
 
     def grad(self, grad_s, want_y=True, want_w=True, want_x=False):
@@ -160,30 +162,68 @@ class Plan:
 
 class FastSum(torch.autograd.Function):
     """s = FastSum.apply(plan, x, y, w): differentiable in x, y and w (the
-    plan must be created with grad=True)."""
+    plan must be created with grad=True).
+
+    The library's adjoint reads what the plan kept from its last call.  When
+    the plan ran again between this forward and its backward (one plan in
+    several sums of one graph), backward first repeats this forward on the
+    saved inputs; inputs modified in place since the forward make autograd
+    raise instead of returning a wrong gradient."""
 
     @staticmethod
     def forward(ctx, plan, x, y, w):
         ctx.plan = plan
-        return plan(x.detach(), w.detach(), y.detach())
+        ctx.same = y is x
+        xd, yd, wd = x.detach(), y.detach(), w.detach()
+        s = plan(xd, wd, xd if ctx.same else yd)
+        ctx.exec_id = plan.execs
+        ctx.save_for_backward(x, y, w)
+        return s
 
     @staticmethod
     def backward(ctx, grad_s):
         plan = ctx.plan
-        gx, gy, gw = plan.grad(grad_s.contiguous(), want_y=ctx.needs_input_grad[2],
-                               want_w=ctx.needs_input_grad[3], want_x=ctx.needs_input_grad[1])
+        x, y, w = ctx.saved_tensors
+        if plan.execs != ctx.exec_id:
+            xd = x.detach()
+            plan(xd, w.detach(), xd if ctx.same else y.detach())
+            ctx.exec_id = plan.execs
+        want_x, want_y, want_w = ctx.needs_input_grad[1:4]
+        if not (want_x or want_y or want_w):
+            return None, None, None, None
+        r = plan.grad(grad_s.contiguous(), want_y=want_y, want_w=want_w, want_x=want_x)
+        gx, gy, gw = r if want_x else (None, *r)
         return None, gx, gy, gw
+
+
+def bound(x, y=None):
+    """max ||x_n|| + max ||y_m|| (App. J, eq. radius_xy) computed on the
+    device by fastsum_bound; y defaults to x.  Raises FastSumError(ERANGE)
+    when a coordinate is not finite."""
+    lib = L.load()
+    if y is None:
+        y = x
+    d = x.shape[1]
+    _need(x, "x", (x.shape[0], d), x.device)
+    _need(y, "y", (y.shape[0], d), x.device)
+    out = ctypes.c_double()
+    with torch.cuda.device(x.device):
+        st = lib.fastsum_bound(_ptr(x), x.shape[0], _ptr(y), y.shape[0], d,
+                               _stream_ptr(x.device), ctypes.byref(out))
+    L.check(st, "fastsum_bound")
+    return out.value
 
 
 def kernel_sum(x, y, w, xi, *, kernel, scale=1.0, n_ft=None, R=None, sorting=False, **kw):
     """One call of s_m ~ sum_n w_n F(||x_n - y_m||) (eq. kernel_sum by the
     slicing estimator with the directions xi, (d, P) unit columns) on a plan
     built for exactly these sizes and released afterwards.  R defaults to
-    max ||x|| + max ||y|| (App. J, eq. radius_xy), n_ft to choose_nft's rule
-    (1024 for the energy kernel).  y may be x.  For repeated calls keep a Plan."""
+    max ||x|| + max ||y|| (App. J, eq. radius_xy, from fastsum_bound), n_ft to
+    choose_nft's rule (1024 for the energy kernel).  y may be x.  For
+    repeated calls keep a Plan."""
     if R is None:
-        R = float(torch.linalg.norm(x, dim=1).max() + torch.linalg.norm(y, dim=1).max())
-        R = R * (1.0 + 1e-6) if R > 0 else 1.0
+        R = bound(x, y)
+        R = R * (1.0 + 1e-4) if R > 0 else 1.0
     if n_ft is None:
         n_ft = 1024 if kernel == "energy" else choose_nft(kernel, x.shape[1], R, scale=scale)
     plan = Plan(xi, kernel=kernel, n_ft=n_ft, R=R, scale=scale, sorting=sorting,

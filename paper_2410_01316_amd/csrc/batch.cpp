@@ -29,6 +29,7 @@ struct ProblemPlan {
            off_spart = 0, off_exp = 0, off_mult = 0, off_tw = 0;
     float bound = 0.f;
     float norm2_max = 0.f;     // fused range check: |x / R|^2 bound
+    float norm_lim = 1.f;      // bound check: (1 + 1e-5) / max_p |xi_p|
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -57,15 +58,37 @@ struct fastsum_batch_s {
     int task_cnt[kBatchPhases] = {};
     size_t lds_spread = 0, lds_fft = 0, lds_gather = 0;
     int* flag = nullptr;
+    unsigned* norms = nullptr;         // bound check slots, two per problem
+    bool norms_dirty = false;          // a direct launch stopped before the checks cleared them
     // replay state
     std::vector<fastsum_problem_io> last_io;
     bool have_tasks = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // recorded after every upload from the staging buffers and every launch:
+    // waited for before the staging buffers are rewritten or the graph is
+    // destroyed, on whichever stream the earlier calls ran
+    hipEvent_t last_use = nullptr;
+    bool used = false;
 };
 
 namespace {
+
+// Wait until nothing enqueued earlier still reads the staging buffers or
+// runs the graph.
+hipError_t wait_idle(fastsum_batch_s* b) {
+    if (!b->used) return hipSuccess;
+    const hipError_t e = hipEventSynchronize(b->last_use);
+    if (e == hipSuccess) b->used = false;
+    return e;
+}
+
+hipError_t mark_used(fastsum_batch_s* b, hipStream_t st) {
+    const hipError_t e = hipEventRecord(b->last_use, st);
+    if (e == hipSuccess) b->used = true;
+    return e;
+}
 
 void drop_graph(fastsum_batch_s* b) {
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
@@ -76,12 +99,15 @@ void drop_graph(fastsum_batch_s* b) {
 
 void free_batch(fastsum_batch_s* b) {
     if (!b) return;
+    if (b->last_use) (void)wait_idle(b);
     drop_graph(b);
+    if (b->last_use) (void)hipEventDestroy(b->last_use);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->arena) (void)hipFree(b->arena);
     if (b->d_probs) (void)hipFree(b->d_probs);
     if (b->d_tasks) (void)hipFree(b->d_tasks);
     if (b->flag) (void)hipFree(b->flag);
+    if (b->norms) (void)hipFree(b->norms);
     if (b->h_probs) (void)hipHostFree(b->h_probs);
     if (b->h_tasks) (void)hipHostFree(b->h_tasks);
     delete b;
@@ -186,7 +212,6 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
             d.xt = reinterpret_cast<uint16_t*>(b->arena + pp.off_xproj);
             d.yt = reinterpret_cast<uint16_t*>(b->arena + pp.off_yproj);
             d.pscale = (float)(pp.r.tau * pp.r.p.R);
-            d.inv_r = (float)(1.0 / pp.r.p.R);
             d.norm2_max = pp.norm2_max;
             d.kb = split_kblocks(pp.r.p.d);
         } else {
@@ -194,6 +219,9 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
             d.xproj = reinterpret_cast<float*>(b->arena + pp.off_xproj);
             d.yproj = reinterpret_cast<float*>(b->arena + pp.off_yproj);
         }
+        d.inv_r = (float)(1.0 / pp.r.p.R);
+        d.norms = b->norms + 2 * i;
+        d.norm_lim = pp.norm_lim;
         d.partial = reinterpret_cast<float*>(b->arena + pp.off_partial);
         d.grid = reinterpret_cast<float*>(b->arena + pp.off_grid);
         d.spart = reinterpret_cast<double*>(b->arena + pp.off_spart);
@@ -377,6 +405,8 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
         // |x~| <= tau R for every direction when |x| max|xi| <= R
         const double lim = (1.0 + 1e-5) / xi_norm_max;
         pp.norm2_max = (float)(lim * lim);
+        // |x~ - y~| <= tau max|xi| (|x| + |y|) <= tau R when the bound holds
+        pp.norm_lim = (float)lim;
     }
     b->fused = (common->flags & FASTSUM_FLAG_MATERIALIZE) == 0;
     for (int i = 0; i < n_problems; ++i)
@@ -436,9 +466,11 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_probs, sizeof(BatchProblem) * n_problems);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_tasks, sizeof(BatchTask) * std::max<size_t>(tasks, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&b->flag, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->norms, sizeof(unsigned) * 2 * n_problems);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_probs, sizeof(BatchProblem) * n_problems);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_tasks, sizeof(BatchTask) * std::max<size_t>(tasks, 1));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->last_use, hipEventDisableTiming);
     if (e != hipSuccess) { fastsum_status st = status_of(e); free_batch(b); return st; }
     for (int i = 0; i < n_problems && e == hipSuccess; ++i) {
         const ProblemPlan& pp = b->plans[i];
@@ -454,6 +486,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
                                hipMemcpyHostToDevice, hs);
     }
     if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), hs);
+    if (e == hipSuccess) e = hipMemsetAsync(b->norms, 0, sizeof(unsigned) * 2 * n_problems, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) { free_batch(b); return FASTSUM_EDEVICE; }
     *out = b;
@@ -463,6 +496,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
 fastsum_status fastsum_batch_set_tuning(fastsum_batch b, const fastsum_batch_tuning* tuning) {
     if (!b) return FASTSUM_EINVAL;
     if (validate_tuning(tuning) != FASTSUM_OK) return FASTSUM_EINVAL;
+    if (wait_idle(b) != hipSuccess) return FASTSUM_EDEVICE;
     if (tuning) b->tuning = *tuning;
     else std::memset(&b->tuning, 0, sizeof(b->tuning));
     drop_graph(b);
@@ -484,8 +518,9 @@ fastsum_status fastsum_batch_exec(fastsum_batch b, const fastsum_problem_io* io,
     }
     const bool use_graph = b->tuning.use_graph != -1;
     if (!b->have_tasks || !same_io(b->last_io, io, n)) {
-        // the staging buffers may still feed an earlier upload
-        if (b->have_tasks && hipStreamSynchronize(st) != hipSuccess) return FASTSUM_EDEVICE;
+        // the staging buffers may still feed an earlier upload, the graph an
+        // earlier replay
+        if (wait_idle(b) != hipSuccess) return FASTSUM_EDEVICE;
         drop_graph(b);
         b->have_tasks = false;
         fastsum_status r = build_tasks(b, io);
@@ -497,6 +532,7 @@ fastsum_status fastsum_batch_exec(fastsum_batch b, const fastsum_problem_io* io,
         if (e == hipSuccess && total)
             e = hipMemcpyAsync(b->d_tasks, b->h_tasks, sizeof(BatchTask) * total,
                                hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = mark_used(b, st);
         if (e != hipSuccess) return FASTSUM_EDEVICE;
         b->last_io.assign(io, io + n);
         b->have_tasks = true;
@@ -510,11 +546,21 @@ fastsum_status fastsum_batch_exec(fastsum_batch b, const fastsum_problem_io* io,
             if (e != hipSuccess) { drop_graph(b); b->have_tasks = false; return FASTSUM_EDEVICE; }
         }
     }
+    // every problem's first reduce task checks max |x| + max |y| <= R and
+    // clears its norm slots; a direct launch that stopped early left them set
+    if (b->norms_dirty &&
+        hipMemsetAsync(b->norms, 0, sizeof(unsigned) * 2 * b->nprob, st) != hipSuccess)
+        return FASTSUM_EDEVICE;
+    b->norms_dirty = false;
     if (use_graph) {
         if (hipGraphLaunch(b->graph_exec, st) != hipSuccess) return FASTSUM_EDEVICE;
-        return FASTSUM_OK;
+        return mark_used(b, st) == hipSuccess ? FASTSUM_OK : FASTSUM_EDEVICE;
     }
-    return launch_all(b, st);
+    b->norms_dirty = true;
+    const fastsum_status r = launch_all(b, st);
+    if (r == FASTSUM_OK) b->norms_dirty = false;
+    if (mark_used(b, st) != hipSuccess) return FASTSUM_EDEVICE;
+    return r;
 }
 
 fastsum_status fastsum_batch_check(fastsum_batch b) {

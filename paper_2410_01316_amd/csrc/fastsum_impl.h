@@ -29,14 +29,54 @@ struct GridGeom {
     int nr;
 };
 
+// Bound of App. J, eq. radius_xy: every pair difference stays inside the
+// period of the rescaled kernel only if max ||x|| + max ||y|| <= R.  The
+// kernels that read the points (operand-tile writers, projection GEMMs)
+// record in norms[role] the largest |z / R|^2 of their rows as float bits
+// (role 0 sources, 1 targets; non-finite rows record +inf); the last kernel
+// of an exec compares sqrt(norms[0]) + sqrt(norms[same ? 0 : 1]) with lim,
+// sets *flag when the sum is larger (or not finite) and clears both slots.
+struct BoundCheck {
+    unsigned* norms;   // nullptr: no check in this launch
+    int* flag;
+    float lim;         // (1 + 1e-5) / max_p |xi_p|
+    int same;          // targets are the sources: one slot holds both
+};
+
+// Running max of squared row norms of a wave (every lane active) into *slot.
+__device__ inline void record_norm2(unsigned* slot, float n2) {
+    unsigned u = (n2 <= 3.4e38f) ? __float_as_uint(n2) : 0x7f800000u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) u = max(u, (unsigned)__shfl_xor((int)u, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, u);
+}
+
+// One thread: the comparison and the reset described at BoundCheck.
+__device__ inline void finish_bound_check(const BoundCheck& bc) {
+    if (bc.norms == nullptr) return;
+    const float a = sqrtf(__uint_as_float(bc.norms[0]));
+    const float b = bc.same ? a : sqrtf(__uint_as_float(bc.norms[1]));
+    if (!(a + b <= bc.lim)) atomicOr(bc.flag, 1);
+    bc.norms[0] = 0u;
+    bc.norms[1] = 0u;
+}
+
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 
+// norms[0] = 0, norms[1] = 0 (a fill kernel, so graph capture records no memset)
+hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream);
+// largest |x_n|^2 over the rows of X (N x d) into *slot, one wave per row
+hipError_t launch_point_norms(const float* X, int64_t N, int d, unsigned* slot,
+                              hipStream_t stream);
+
 // out[p*ld + j] = sum_i A[p*dpad + i] * X[j*d + i] for p < P, j < N, with
-// A = tau * Xi^T.  Sets *flag if |out| > bound.
+// A = tau * Xi^T.  Sets *flag if |out| > bound.  norm_slot (nullable):
+// largest |x_n * inv_r|^2, see BoundCheck.
 // FP32 MFMA, d <= 64: A64 is A zero-padded to round_up(P, 64) x 64.
 constexpr int kA64Cols = 64;
 hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64, int P,
-                              float* out, int64_t ld, float bound, int* flag, hipStream_t stream);
+                              float* out, int64_t ld, float bound, int* flag,
+                              unsigned* norm_slot, float inv_r, hipStream_t stream);
 // Tile GEMM, any d: X is first written as operand tiles into xtiles (the
 // tile layout of the fused path below; bf16: one BF16 part per k-block,
 // else f16 hi + lo of x * inv_r), then multiplied with the direction tiles
@@ -45,7 +85,8 @@ hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64
 size_t project_tiles_bytes(int64_t rows, int d, bool bf16);
 hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, const uint16_t* At,
                                 int P, float inv_r, float pscale, uint16_t* xtiles, float* out,
-                                int64_t ld, float bound, int* flag, hipStream_t stream);
+                                int64_t ld, float bound, int* flag, unsigned* norm_slot,
+                                hipStream_t stream);
 
 // partial[(c*P + p)*nr + j - lo] = sum over sources i of chunk c of
 //   w[i] * window(cell j - u(proj[p*ld + i]))
@@ -77,9 +118,10 @@ hipError_t launch_gather(int W, const float* proj, int64_t ld, int64_t M,
                          int64_t ldm, float* tout, int64_t ld_t,
                          hipStream_t stream);
 
-// s[m] = (float)(scale * sum_b spart[b*ldm + m]), b < nb.
+// s[m] = (float)(scale * sum_b spart[b*ldm + m]), b < nb; then the bound
+// check bc (BoundCheck; bc.norms == nullptr: none).
 hipError_t launch_reduce(const double* spart, int nb, int64_t ldm, int64_t M,
-                         double scale, float* s, hipStream_t stream);
+                         double scale, float* s, const BoundCheck& bc, hipStream_t stream);
 
 // grad_y[m*d + i] = v[m] * coef * sum_p tprime[p*ld + m] * A[p*dpad + i]
 hipError_t launch_backproject(const float* tprime, int64_t ld, int64_t M,
@@ -111,9 +153,11 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
 int64_t split_tiles_bytes(int64_t rows, int d);
 
 // tiles of Z * scale (Z: N x d row-major); sets *flag if a row has
-// |Z_row * scale|^2 > norm2_max (or is not finite)
+// |Z_row * scale|^2 > norm2_max (or is not finite); records the largest
+// |Z_row * scale|^2 in *norm_slot (nullable, see BoundCheck)
 hipError_t launch_split_points(const float* Z, int64_t N, int d, float scale, uint16_t* tiles,
-                               float norm2_max, int* flag, hipStream_t stream);
+                               float norm2_max, int* flag, unsigned* norm_slot,
+                               hipStream_t stream);
 
 // As launch_spread, with the projections computed in the kernel from the
 // split tiles of the sources (Xt, scale 1/R) and of the directions (At):
@@ -159,7 +203,7 @@ hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned 
                                 int M, int same_xy, const float* w, double coef, float* V,
                                 int64_t ldm, hipStream_t stream);
 hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
-                                float* s, hipStream_t stream);
+                                float* s, const BoundCheck& bc, hipStream_t stream);
 // Adjoint pieces per direction from an ascending and a descending sort of
 // the rows (sources at i < N with weights w, targets at yoff + m with
 // cotangent v; sign(0) = 0 at equal keys), all P x ldm FP32:
@@ -211,6 +255,10 @@ struct BatchProblem {
     float inv_r;           // 1 / R
     float norm2_max;       // range check of |x / R|^2
     int kb;                // ceil(d / 32)
+    // bound check (BoundCheck): largest |x / R|^2 of the sources and of the
+    // targets, compared with norm_lim by the problem's first reduce task
+    unsigned* norms;
+    float norm_lim;
 };
 
 // One tile of one phase of one problem; a, b, c are phase-specific indices.

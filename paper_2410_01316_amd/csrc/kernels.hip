@@ -311,7 +311,8 @@ template <int KS>
 __device__ __forceinline__ void project_tile_f32_xres(
     ProjSmemXres& sm, const float* __restrict__ X, int64_t N, int d,
     const float* __restrict__ A64, int P, float* __restrict__ out, int64_t ld, float bound,
-    int* __restrict__ flag, int p_begin, int p_end, int64_t n0) {
+    int* __restrict__ flag, int p_begin, int p_end, int64_t n0, unsigned* __restrict__ norm_slot,
+    float inv_r) {
     const int tid = threadIdx.x;
     float4 va[kXresQ4];
     xres_load_a(va, A64, p_begin);
@@ -320,6 +321,17 @@ __device__ __forceinline__ void project_tile_f32_xres(
     for (int e = tid; e < kProjBN * kXresLd; e += kBlock) {
         const int r = e / kXresLd, k = e % kXresLd;
         sm.Xs[r][k] = (k < d && n0 + r < N) ? X[(n0 + r) * d + k] : 0.f;
+    }
+    if (norm_slot != nullptr) {                     // uniform: the bound check's row norms
+        __syncthreads();
+        const int row = tid >> 1;                   // two threads per row (kBlock = 2 kProjBN)
+        float ss = 0.f;
+        for (int k = tid & 1; k < d; k += 2) {
+            const float v = sm.Xs[row][k] * inv_r;
+            ss = fmaf(v, v, ss);
+        }
+        ss += __shfl_xor(ss, 1);
+        record_norm2(norm_slot, ss);
     }
     // steady state: whole 64 x 128 tiles, straight-line code so the wait
     // for the prefetched A tile does not include this tile's stores
@@ -349,23 +361,26 @@ __device__ __forceinline__ void project_tile_f32_xres(
     if (bad) atomicOr(flag, 1);
 }
 
+// workgroup (x, y): point tile x, direction range y; the first range also
+// records the tile's row norms
 template <int KS>
 __global__ __launch_bounds__(kBlock) void project_f32_xres_kernel(
     const float* __restrict__ X, int64_t N, int d, const float* __restrict__ A64,
     int P, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag,
-    int prange) {
+    int prange, unsigned* __restrict__ norm_slot, float inv_r) {
     __shared__ ProjSmemXres sm;
     const int p_begin = blockIdx.y * prange;
     project_tile_f32_xres<KS>(sm, X, N, d, A64, P, out, ld, bound, flag, p_begin,
-                              min(P, p_begin + prange), (int64_t)blockIdx.x * kProjBN);
+                              min(P, p_begin + prange), (int64_t)blockIdx.x * kProjBN,
+                              blockIdx.y == 0 ? norm_slot : nullptr, inv_r);
 }
 
 template <int KS>
 void launch_xres(dim3 grid, hipStream_t stream, const float* X, int64_t N, int d,
                  const float* A64, int P, float* out, int64_t ld, float bound, int* flag,
-                 int prange) {
+                 int prange, unsigned* norm_slot, float inv_r) {
     hipLaunchKernelGGL(project_f32_xres_kernel<KS>, grid, dim3(kBlock), 0, stream, X, N, d, A64,
-                       P, out, ld, bound, flag, prange);
+                       P, out, ld, bound, flag, prange, norm_slot, inv_r);
 }
 
 int project_xres_range(int64_t N, int P) {
@@ -376,18 +391,20 @@ int project_xres_range(int64_t N, int P) {
 }
 
 hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64, int P,
-                              float* out, int64_t ld, float bound, int* flag, hipStream_t stream) {
+                              float* out, int64_t ld, float bound, int* flag,
+                              unsigned* norm_slot, float inv_r, hipStream_t stream) {
     if (d > kXresMaxD || A64 == nullptr) return hipErrorInvalidValue;
     const int prange = project_xres_range(N, P);
     dim3 grid((unsigned)((N + kProjBN - 1) / kProjBN), (unsigned)((P + prange - 1) / prange));
     using L = void (*)(dim3, hipStream_t, const float*, int64_t, int, const float*, int,
-                       float*, int64_t, float, int*, int);
+                       float*, int64_t, float, int*, int, unsigned*, float);
     static const L table[16] = {
         launch_xres<1>, launch_xres<2>, launch_xres<3>, launch_xres<4>,
         launch_xres<5>, launch_xres<6>, launch_xres<7>, launch_xres<8>,
         launch_xres<9>, launch_xres<10>, launch_xres<11>, launch_xres<12>,
         launch_xres<13>, launch_xres<14>, launch_xres<15>, launch_xres<16>};
-    table[(d + 3) / 4 - 1](grid, stream, X, N, d, A64, P, out, ld, bound, flag, prange);
+    table[(d + 3) / 4 - 1](grid, stream, X, N, d, A64, P, out, ld, bound, flag, prange,
+                           norm_slot, inv_r);
     return hipGetLastError();
 }
 
@@ -877,14 +894,16 @@ __device__ __forceinline__ void reduce_tile(const double* __restrict__ spart, in
 
 __global__ __launch_bounds__(kBlock) void reduce_kernel(
     const double* __restrict__ spart, int nb, int64_t ldm, int64_t M,
-    double scale, float* __restrict__ s) {
+    double scale, float* __restrict__ s, BoundCheck bc) {
     reduce_tile(spart, nb, ldm, M, scale, s, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (blockIdx.x == 0 && threadIdx.x == 0) finish_bound_check(bc);
 }
 
 hipError_t launch_reduce(const double* spart, int nb, int64_t ldm, int64_t M,
-                         double scale, float* s, hipStream_t stream) {
+                         double scale, float* s, const BoundCheck& bc, hipStream_t stream) {
     dim3 grid((unsigned)((M + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(reduce_kernel, grid, dim3(kBlock), 0, stream, spart, nb, ldm, M, scale, s);
+    hipLaunchKernelGGL(reduce_kernel, grid, dim3(kBlock), 0, stream, spart, nb, ldm, M, scale, s,
+                       bc);
     return hipGetLastError();
 }
 
@@ -1019,11 +1038,14 @@ __device__ __forceinline__ h8 buffer_load_h8(__amdgpu_buffer_rsrc_t rs, int byte
 // split_points_kernel: one thread per (tile, lane), all k-blocks; rows >= N
 // and columns >= d are zero.  Also the range check of the fused path: a
 // row with |z * scale|^2 > norm2_max sets *flag (z * scale is x / R, and
-// |<xi, x / R>| <= max|xi| |x| / R bounds every projection of the row).
+// |<xi, x / R>| <= max|xi| |x| / R bounds every projection of the row), and
+// the row norms of the bound check (BoundCheck) when norm_slot is given.
+// Called by whole waves (one tile per wave).
 __device__ __forceinline__ void split_points_lane(const float* __restrict__ Z, int64_t N, int d,
                                                   float scale, int KB, int64_t t, int lane,
                                                   u32x4* __restrict__ tiles, float norm2_max,
-                                                  int* __restrict__ flag) {
+                                                  int* __restrict__ flag,
+                                                  unsigned* __restrict__ norm_slot) {
     // The tile's rows as a buffer: a lane reads its eight columns with two
     // 16-byte loads; rows past N read as zero and columns >= d (the next
     // row's values) are masked.
@@ -1055,14 +1077,53 @@ __device__ __forceinline__ void split_points_lane(const float* __restrict__ Z, i
     ss += __shfl_xor(ss, 16);
     ss += __shfl_xor(ss, 32);
     if (!(ss <= norm2_max) && lane < 16) atomicOr(flag, 1);   // NaN also flags
+    if (norm_slot != nullptr) record_norm2(norm_slot, ss);
 }
 
 __global__ __launch_bounds__(kBlock) void split_points_kernel(
     const float* __restrict__ Z, int64_t N, int d, float scale, int KB, int64_t ntiles,
-    u32x4* __restrict__ tiles, float norm2_max, int* __restrict__ flag) {
+    u32x4* __restrict__ tiles, float norm2_max, int* __restrict__ flag,
+    unsigned* __restrict__ norm_slot) {
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (id >= ntiles * 64) return;                    // whole waves
-    split_points_lane(Z, N, d, scale, KB, id >> 6, (int)(id & 63), tiles, norm2_max, flag);
+    split_points_lane(Z, N, d, scale, KB, id >> 6, (int)(id & 63), tiles, norm2_max, flag,
+                      norm_slot);
+}
+
+// One wave per row of X: the largest |x_n|^2 into *slot (bound helper).
+__global__ __launch_bounds__(kBlock) void point_norms_kernel(const float* __restrict__ X,
+                                                             int64_t N, int d,
+                                                             unsigned* __restrict__ slot) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+    float mx = 0.f;
+    for (int64_t n = wave; n < N; n += nwaves) {      // uniform over the wave
+        const float* __restrict__ row = X + n * d;
+        float ss = 0.f;
+        for (int k = lane; k < d; k += 64) ss = fmaf(row[k], row[k], ss);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+        mx = (ss <= 3.4e38f) ? fmaxf(mx, ss) : __builtin_inff();   // NaN -> inf
+    }
+    record_norm2(slot, mx);
+}
+
+__global__ void clear_norms_kernel(unsigned* __restrict__ norms) {
+    if (threadIdx.x < 2) norms[threadIdx.x] = 0u;
+}
+
+hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream) {
+    hipLaunchKernelGGL(clear_norms_kernel, dim3(1), dim3(64), 0, stream, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_point_norms(const float* X, int64_t N, int d, unsigned* slot,
+                              hipStream_t stream) {
+    const int64_t waves = std::min<int64_t>(N, (int64_t)4096);
+    hipLaunchKernelGGL(point_norms_kernel, dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, stream, X, N, d, slot);
+    return hipGetLastError();
 }
 
 // operand of one tile: hi and lo parts of each k-block
@@ -1609,15 +1670,18 @@ __global__ __launch_bounds__(kGemmBlock) void project_tiles_kernel(
     if (bad) atomicOr(flag, 1);
 }
 
-// BF16 point tiles (one part per k-block): bf16(Z) in the tile layout
+// BF16 point tiles (one part per k-block): bf16(Z) in the tile layout; the
+// largest |Z_row * inv_r|^2 into *norm_slot (nullable, see BoundCheck)
 __global__ __launch_bounds__(kBlock) void bf16_points_kernel(
-    const float* __restrict__ Z, int64_t N, int d, int KB, int64_t ntiles, u32x4* __restrict__ tiles) {
+    const float* __restrict__ Z, int64_t N, int d, int KB, int64_t ntiles, u32x4* __restrict__ tiles,
+    float inv_r, unsigned* __restrict__ norm_slot) {
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (id >= ntiles * 64) return;
+    if (id >= ntiles * 64) return;                    // whole waves
     const int lane = (int)(id & 63);
     const int64_t t = id >> 6, r0 = 16 * t;
     const int64_t nrows = N - r0 < 16 ? N - r0 : 16;
     const __amdgpu_buffer_rsrc_t zs = buffer_rsrc(Z + r0 * d, nrows * (int64_t)d * 4);
+    float ss = 0.f;
     for (int kb = 0; kb < KB; ++kb) {
         const int col0 = 32 * kb + 8 * (lane >> 4);
         const int off = ((lane & 15) * d + col0) * 4;
@@ -1625,11 +1689,17 @@ __global__ __launch_bounds__(kBlock) void bf16_points_kernel(
         const u32x4 vb = __builtin_amdgcn_raw_buffer_load_b128(zs, off + 16, 0, 0);
         float v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
+        for (int e = 0; e < 8; ++e) {
             v[e] = col0 + e < d ? __uint_as_float(e < 4 ? va[e] : vb[e - 4]) : 0.f;
+            const float vs = v[e] * inv_r;
+            ss = fmaf(vs, vs, ss);
+        }
         tiles[(t * KB + kb) * 64 + lane] = u32x4{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]),
                                                  pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7])};
     }
+    ss += __shfl_xor(ss, 16);
+    ss += __shfl_xor(ss, 32);
+    if (norm_slot != nullptr) record_norm2(norm_slot, ss);
 }
 
 template <int W, int KB>
@@ -1708,7 +1778,8 @@ size_t project_tiles_bytes(int64_t rows, int d, bool bf16) {
 
 hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, const uint16_t* At,
                                 int P, float inv_r, float pscale, uint16_t* xtiles, float* out,
-                                int64_t ld, float bound, int* flag, hipStream_t stream) {
+                                int64_t ld, float bound, int* flag, unsigned* norm_slot,
+                                hipStream_t stream) {
     // three k-block buffers: 144 KB (f16 hi + lo) or 72 KB (BF16) of LDS
     constexpr int kLds2 = 3 * (kGemmDT + kGemmPT) * 2 * kSplitTileBytes;
     constexpr int kLds1 = 3 * (kGemmDT + kGemmPT) * kSplitTileBytes;
@@ -1725,10 +1796,11 @@ hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, con
     const unsigned sb = (unsigned)((ntiles * 64 + kBlock - 1) / kBlock);
     if (bf16)
         hipLaunchKernelGGL(bf16_points_kernel, dim3(sb), dim3(kBlock), 0, stream, X, N, d, KB, ntiles,
-                           reinterpret_cast<u32x4*>(xtiles));
-    else   // no range check here: the projections are checked when stored
+                           reinterpret_cast<u32x4*>(xtiles), inv_r, norm_slot);
+    else   // no per-point range check here: the projections are checked when stored
         hipLaunchKernelGGL(split_points_kernel, dim3(sb), dim3(kBlock), 0, stream, X, N, d, inv_r,
-                           KB, ntiles, reinterpret_cast<u32x4*>(xtiles), __builtin_inff(), flag);
+                           KB, ntiles, reinterpret_cast<u32x4*>(xtiles), __builtin_inff(), flag,
+                           norm_slot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int ndb = (P + 16 * kGemmDT - 1) / (16 * kGemmDT);
@@ -1754,13 +1826,14 @@ int64_t split_tiles_bytes(int64_t rows, int d) {
 }
 
 hipError_t launch_split_points(const float* Z, int64_t N, int d, float scale, uint16_t* tiles,
-                               float norm2_max, int* flag, hipStream_t stream) {
+                               float norm2_max, int* flag, unsigned* norm_slot,
+                               hipStream_t stream) {
     const int KB = split_kblocks(d);
     const int64_t ntiles = (N + 15) / 16;
     const int64_t threads = ntiles * 64;
     hipLaunchKernelGGL(split_points_kernel, dim3((unsigned)((threads + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, stream, Z, N, d, scale, KB, ntiles,
-                       reinterpret_cast<u32x4*>(tiles), norm2_max, flag);
+                       reinterpret_cast<u32x4*>(tiles), norm2_max, flag, norm_slot);
     return hipGetLastError();
 }
 
@@ -1846,9 +1919,22 @@ __global__ __launch_bounds__(kBlock) void batch_project_kernel(
         const BatchTask tk = tasks[t];
         const BatchProblem& pr = probs[tk.prob];
         const bool is_y = tk.a != 0;
-        project_tile_f32(sm, is_y ? pr.y : pr.x, is_y ? pr.M : pr.N, pr.d, pr.dpad, pr.A, P,
-                         is_y ? pr.yproj : pr.xproj, is_y ? pr.ldy : pr.ldx, pr.bound, flag,
-                         tk.c * kProjBM, (int64_t)tk.b * kProjBN);
+        const float* __restrict__ X = is_y ? pr.y : pr.x;
+        const int64_t n = is_y ? pr.M : pr.N;
+        const int64_t n0 = (int64_t)tk.b * kProjBN;
+        project_tile_f32(sm, X, n, pr.d, pr.dpad, pr.A, P, is_y ? pr.yproj : pr.xproj,
+                         is_y ? pr.ldy : pr.ldx, pr.bound, flag, tk.c * kProjBM, n0);
+        if (tk.c == 0) {   // the point tile's row norms, once (bound check)
+            float ss = 0.f;
+            if (threadIdx.x < kProjBN && n0 + threadIdx.x < n) {
+                const float* __restrict__ row = X + (n0 + threadIdx.x) * pr.d;
+                for (int k = 0; k < pr.d; ++k) {
+                    const float v = row[k] * pr.inv_r;
+                    ss = fmaf(v, v, ss);
+                }
+            }
+            record_norm2(pr.norms + (is_y ? 1 : 0), ss);
+        }
     }
 }
 
@@ -1902,14 +1988,17 @@ __global__ __launch_bounds__(kBlock) void batch_gather_kernel(
     }
 }
 
+// The first reduce task of a problem also finishes its bound check.
 __global__ __launch_bounds__(kBlock) void batch_reduce_kernel(
     const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
-    int P) {
+    int P, int* __restrict__ flag) {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const BatchTask tk = tasks[t];
         const BatchProblem& pr = probs[tk.prob];
         reduce_tile(pr.spart, pr.ngroup, pr.ldm, pr.M, 1.0 / P, pr.s,
                     (int64_t)tk.a * kBlock + threadIdx.x);
+        if (tk.a == 0 && threadIdx.x == 0)
+            finish_bound_check(BoundCheck{pr.norms, flag, pr.norm_lim, pr.same_xy});
     }
 }
 
@@ -1930,7 +2019,8 @@ __global__ __launch_bounds__(kBlock) void batch_split_kernel(
         u32x4* dst = reinterpret_cast<u32x4*>(is_y ? pr.yt : pr.xt);
         for (int64_t id = t0 * 64 + threadIdx.x; id < t1 * 64; id += kBlock)
             split_points_lane(is_y ? pr.y : pr.x, n, pr.d, pr.inv_r, pr.kb, id >> 6,
-                              (int)(id & 63), dst, pr.norm2_max, flag);
+                              (int)(id & 63), dst, pr.norm2_max, flag,
+                              pr.norms + (is_y ? 1 : 0));
     }
 }
 
@@ -2060,7 +2150,8 @@ hipError_t launch_batch_phase(int phase, int W, const BatchProblem* probs,
             }
             break;
         case kBatchReduce:
-            hipLaunchKernelGGL(batch_reduce_kernel, grid, block, 0, stream, probs, tasks, ntasks, P);
+            hipLaunchKernelGGL(batch_reduce_kernel, grid, block, 0, stream, probs, tasks, ntasks, P,
+                               flag);
             break;
         default:
             return hipErrorInvalidValue;

@@ -450,6 +450,9 @@ struct fastsum_plan_s {
     float2* mult_d = nullptr;
     float2* tw = nullptr;
     int* flag = nullptr;
+    unsigned* norms = nullptr;     // bound check: largest |x / R|^2, |y / R|^2 of an exec
+    bool norms_dirty = false;      // an exec stopped before its check cleared them
+    float norm_lim = 1.f;          // (1 + 1e-5) / max_p |xi_p|
     float* slice_max = nullptr;    // per-slice max |w| (fixed-point scaling)
     // sorted plans: rows of stride sort_L, sources at 0, targets at sort_yoff
     float* keys = nullptr;
@@ -485,7 +488,7 @@ void free_plan(fastsum_plan_s* p) {
     void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->gdt, p->gpt, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout, p->keys,
-                    p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx};
+                    p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx, p->norms};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -548,7 +551,7 @@ int chunk_plan(const fastsum_plan_s* pl, int64_t N, int rule_chunks, int64_t& ch
 fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_src,
                         const float* wts, int64_t Nsrc, const float* tgt_proj,
                         int64_t ld_tgt, int64_t Mtgt, float* out, float* grid,
-                        float* grid_d, hipStream_t st) {
+                        float* grid_d, const BoundCheck& bc, hipStream_t st) {
     const int P = pl->P;
     int64_t chunk_len = 0;
     const int nchunk = chunk_plan(pl, Nsrc, spread_chunks(Nsrc, P), chunk_len);
@@ -572,7 +575,7 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
                              pl->win_args, pl->spart, pl->ldm, nullptr, 0, st));
     }
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-    FS_TRY(launch_reduce(pl->spart, ng, pl->ldm, Mtgt, 1.0 / P, out, st));
+    FS_TRY(launch_reduce(pl->spart, ng, pl->ldm, Mtgt, 1.0 / P, out, bc, st));
     return FASTSUM_OK;
 }
 
@@ -585,7 +588,7 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
 // one sliced Fourier sum on split operand tiles.
 fastsum_status fused_sum(fastsum_plan_s* pl, const uint16_t* xt, const float* w, int64_t N,
                          const uint16_t* yt, int64_t M, float* out, float* grid, float* grid_d,
-                         hipStream_t st) {
+                         const BoundCheck& bc, hipStream_t st) {
     const int P = pl->P;
     const float pscale = (float)(pl->r.tau * pl->r.p.R);
     int64_t chunk_len = 0;
@@ -611,12 +614,13 @@ fastsum_status fused_sum(fastsum_plan_s* pl, const uint16_t* xt, const float* w,
                                    prange, pl->win_args, pl->spart, pl->ldm, st));
     }
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-    FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, st));
+    FS_TRY(launch_reduce(pl->spart, nrange, pl->ldm, M, 1.0 / P, out, bc, st));
     return FASTSUM_OK;
 }
 
 fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, int64_t N,
-                          const float* y, int64_t M, float* out, hipStream_t st) {
+                          const float* y, int64_t M, float* out, const BoundCheck& bc,
+                          hipStream_t st) {
     const float inv_r = (float)(1.0 / pl->r.p.R);
     // |x~| <= tau R for every direction when |x| max|xi| <= R (same slack as
     // the stored path's check of each projection)
@@ -625,14 +629,16 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
     const uint16_t* yt = pl->xt;
     {
         PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
-        FS_TRY(launch_split_points(x, N, pl->d, inv_r, pl->xt, norm2_max, pl->flag, st));
+        FS_TRY(launch_split_points(x, N, pl->d, inv_r, pl->xt, norm2_max, pl->flag, pl->norms,
+                                   st));
         if (y != x) {
-            FS_TRY(launch_split_points(y, M, pl->d, inv_r, pl->yt, norm2_max, pl->flag, st));
+            FS_TRY(launch_split_points(y, M, pl->d, inv_r, pl->yt, norm2_max, pl->flag,
+                                       pl->norms + 1, st));
             yt = pl->yt;
         }
     }
     return fused_sum(pl, pl->xt, w, N, yt, M, out, pl->grid,
-                     (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, st);
+                     (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, bc, st);
 }
 
 // direction ranges of the fused adjoint gather: at least three rounds of
@@ -647,20 +653,22 @@ int fused_grad_range(int64_t M, int P, int64_t slots) {
     return (int)round_up((P + ranges - 1) / ranges, kFuseDirs);
 }
 
+// Stored projections of X into out (row stride ld); norm_slot (nullable)
+// receives the rows' largest |x / R|^2 for the bound check.
 fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out, int64_t ld,
-                       hipStream_t st) {
+                       unsigned* norm_slot, hipStream_t st) {
     PhaseTimer t(pl, FASTSUM_PHASE_PROJECT, st);
+    const float inv_r = (float)(1.0 / pl->r.p.R);
     if (pl->tile_gemm) {
         // BF16: bf16(x) . bf16(tau xi); FP32: (x / R) . xi split into f16
         // hi + lo, times tau R
         const bool bf16 = pl->r.p.proj == FASTSUM_PROJ_BF16;
-        return check(launch_project_tiles(X, N, pl->d, bf16, pl->gdt, pl->P,
-                                          (float)(1.0 / pl->r.p.R),
+        return check(launch_project_tiles(X, N, pl->d, bf16, pl->gdt, pl->P, inv_r,
                                           bf16 ? 1.f : (float)(pl->r.tau * pl->r.p.R), pl->gpt,
-                                          out, ld, pl->bound, pl->flag, st));
+                                          out, ld, pl->bound, pl->flag, norm_slot, st));
     }
     return check(launch_project_f32(X, N, pl->d, pl->A64, pl->P, out, ld, pl->bound, pl->flag,
-                                    st));
+                                    norm_slot, inv_r, st));
 }
 
 // Sorted plans (energy kernel): project x and y into the rows of the sort,
@@ -668,12 +676,13 @@ fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out
 // -(c_d / tau) sum_n w_n |x~_n - y~_m| = sum_n w_n f(<xi_p, x_n - y_m>)
 // exactly, and the FP64 mean over the directions finishes s.
 fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, int64_t N,
-                           const float* y, int64_t M, float* out, bool same, hipStream_t st) {
+                           const float* y, int64_t M, float* out, bool same,
+                           const BoundCheck& bc, hipStream_t st) {
     const int64_t L = pl->sort_L, yoff = pl->sort_yoff;
-    fastsum_status r = project(pl, x, N, pl->keys, L, st);
+    fastsum_status r = project(pl, x, N, pl->keys, L, pl->norms, st);
     if (r != FASTSUM_OK) return r;
     if (!same) {
-        r = project(pl, y, M, pl->keys + yoff, L, st);
+        r = project(pl, y, M, pl->keys + yoff, L, pl->norms + 1, st);
         if (r != FASTSUM_OK) return r;
     }
     const double coef = -energy_cd(pl->d) / pl->r.tau;
@@ -686,7 +695,7 @@ fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, i
     pl->last_nchunk = 0;
     pl->last_ngroup = pl->P;
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-    FS_TRY(launch_sorted_reduce(pl->sv, pl->P, pl->ldm, M, 1.0 / pl->P, out, st));
+    FS_TRY(launch_sorted_reduce(pl->sv, pl->P, pl->ldm, M, 1.0 / pl->P, out, bc, st));
     return FASTSUM_OK;
 }
 
@@ -700,7 +709,7 @@ fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, fl
     const int P = pl->P;
     if (!grad_x && !grad_y && !grad_w) return FASTSUM_OK;
     if (pl->last_same) {          // the exec projected one copy; the adjoint needs both roles
-        fastsum_status r = project(pl, pl->last_x, N, pl->keys + yoff, L, st);
+        fastsum_status r = project(pl, pl->last_x, N, pl->keys + yoff, L, nullptr, st);
         if (r != FASTSUM_OK) return r;
     }
     const double coef = -energy_cd(pl->d) / pl->r.tau;
@@ -724,7 +733,7 @@ fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, fl
     }
     if (grad_w) {
         PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-        FS_TRY(launch_sorted_reduce(pl->sv, P, pl->ldm, N, 1.0 / P, grad_w, st));
+        FS_TRY(launch_sorted_reduce(pl->sv, P, pl->ldm, N, 1.0 / P, grad_w, BoundCheck{}, st));
     }
     return FASTSUM_OK;
 }
@@ -842,8 +851,9 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         ? dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->keys, PL) &&
               dev_alloc(&pl->keys_out, PL) && dev_alloc(&pl->vals, PL) &&
               dev_alloc((char**)&pl->sort_temp, pl->sort_temp_bytes) &&
-              dev_alloc(&pl->sv, (size_t)P * pl->ldm) && dev_alloc(&pl->flag, 1)
-        : dev_alloc(&pl->A, (size_t)P * pl->dpad) &&
+              dev_alloc(&pl->sv, (size_t)P * pl->ldm) && dev_alloc(&pl->flag, 1) &&
+              dev_alloc(&pl->norms, 2)
+        : dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->norms, 2) &&
               (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
                                dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&
                                dev_alloc(&pl->at, (size_t)split_tiles_bytes(gtiles * kFuseDirs, pl->d) / 2)
@@ -916,6 +926,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         pl->xi_norm_max = std::max(pl->xi_norm_max, std::sqrt(ss));
     }
     if (!(pl->xi_norm_max > 0.0)) pl->xi_norm_max = 1.0;
+    // |x~ - y~| <= tau max|xi| (|x| + |y|) <= tau R when the bound holds
+    pl->norm_lim = (float)((1.0 + 1e-5) / pl->xi_norm_max);
     hipError_t e = hipMemcpyAsync(pl->A, A.data(), A.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->at)
         e = hipMemcpyAsync(pl->at, at.data(), at.size() * sizeof(uint16_t), hipMemcpyHostToDevice, hs);
@@ -932,10 +944,32 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     if (e == hipSuccess && pl->mult_d)
         e = hipMemcpyAsync(pl->mult_d, mult_d.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemsetAsync(pl->flag, 0, sizeof(int), hs);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->norms, 0, 2 * sizeof(unsigned), hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) { free_plan(pl); return FASTSUM_EDEVICE; }
     *out = pl;
     return FASTSUM_OK;
+}
+
+fastsum_status fastsum_bound(const float* x, int64_t N, const float* y, int64_t M, int32_t d,
+                             void* stream, double* bound_out) {
+    if (!x || !y || !bound_out || N < 1 || M < 1 || d < 1) return FASTSUM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned* slots = nullptr;
+    if (!dev_alloc(&slots, 2)) return FASTSUM_ENOMEM;
+    unsigned h[2] = {0u, 0u};
+    hipError_t e = hipMemsetAsync(slots, 0, 2 * sizeof(unsigned), st);
+    if (e == hipSuccess) e = launch_point_norms(x, N, d, slots, st);
+    if (e == hipSuccess) e = launch_point_norms(y, M, d, slots + 1, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, slots, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(slots);
+    if (e != hipSuccess) return FASTSUM_EDEVICE;
+    float n2[2];
+    std::memcpy(n2, h, sizeof(n2));
+    const double b = std::sqrt((double)n2[0]) + std::sqrt((double)n2[1]);
+    *bound_out = b;
+    return std::isfinite(b) ? FASTSUM_OK : FASTSUM_ERANGE;
 }
 
 void fastsum_destroy(fastsum_plan plan) {
@@ -951,49 +985,33 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
     const bool same = (x == y);
     if (same && N != M) return FASTSUM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    // the exec's last kernel checks max |x| + max |y| <= R and clears the
+    // norm slots; an exec that stopped early left them set
+    if (pl->norms_dirty) FS_TRY(launch_clear_norms(pl->norms, st));
+    pl->norms_dirty = true;
+    const BoundCheck bc{pl->norms, pl->flag, pl->norm_lim, same ? 1 : 0};
+    fastsum_status r = FASTSUM_OK;
     if (pl->sorted) {
-        fastsum_status r = sorted_pass(pl, x, w, N, y, M, s, same, st);
-        if (r != FASTSUM_OK) return r;
-        pl->have_exec = true;
-        pl->have_proj = true;
-        pl->last_same = same;
-        pl->last_x = x;
-        pl->last_w = w;
-        pl->last_y = y;
-        pl->last_N = N;
-        pl->last_M = M;
-        pl->last_stream = st;
-        return FASTSUM_OK;
+        r = sorted_pass(pl, x, w, N, y, M, s, same, bc, st);
+    } else if (pl->fused) {
+        r = fused_pass(pl, x, w, N, y, M, s, bc, st);
+    } else {
+        r = project(pl, x, N, pl->xproj, pl->ld_x, pl->norms, st);
+        const float* yp = pl->xproj;
+        int64_t ldy = pl->ld_x;
+        if (r == FASTSUM_OK && !same) {
+            r = project(pl, y, M, pl->yproj, pl->ld_y, pl->norms + 1, st);
+            yp = pl->yproj;
+            ldy = pl->ld_y;
+        }
+        if (r == FASTSUM_OK)
+            r = sum_pass(pl, pl->xproj, pl->ld_x, w, N, yp, ldy, M, s, pl->grid,
+                         (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, bc, st);
     }
-    if (pl->fused) {
-        fastsum_status r = fused_pass(pl, x, w, N, y, M, s, st);
-        if (r != FASTSUM_OK) return r;
-        pl->have_exec = true;
-        pl->have_proj = false;
-        pl->last_same = same;
-        pl->last_x = x;
-        pl->last_w = w;
-        pl->last_y = y;
-        pl->last_N = N;
-        pl->last_M = M;
-        pl->last_stream = st;
-        return FASTSUM_OK;
-    }
-    fastsum_status r = project(pl, x, N, pl->xproj, pl->ld_x, st);
     if (r != FASTSUM_OK) return r;
-    const float* yp = pl->xproj;
-    int64_t ldy = pl->ld_x;
-    if (!same) {
-        r = project(pl, y, M, pl->yproj, pl->ld_y, st);
-        if (r != FASTSUM_OK) return r;
-        yp = pl->yproj;
-        ldy = pl->ld_y;
-    }
-    r = sum_pass(pl, pl->xproj, pl->ld_x, w, N, yp, ldy, M, s, pl->grid,
-                 (pl->r.p.flags & FASTSUM_FLAG_GRAD) ? pl->grid_d : nullptr, st);
-    if (r != FASTSUM_OK) return r;
+    pl->norms_dirty = false;
     pl->have_exec = true;
-    pl->have_proj = true;
+    pl->have_proj = !pl->fused;
     pl->last_same = same;
     pl->last_x = x;
     pl->last_w = w;
@@ -1028,7 +1046,7 @@ fastsum_status fastsum_grad_xyw(fastsum_plan pl, const float* grad_s, float* gra
         }
         if (grad_w || grad_x) {
             fastsum_status r = fused_sum(pl, yt, grad_s, M, pl->xt, N, uout, pl->grid_w,
-                                         grad_x ? pl->grid_wd : nullptr, st);
+                                         grad_x ? pl->grid_wd : nullptr, BoundCheck{}, st);
             if (r != FASTSUM_OK) return r;
         }
         if (grad_x) {
@@ -1056,7 +1074,7 @@ fastsum_status fastsum_grad_xyw(fastsum_plan pl, const float* grad_s, float* gra
     }
     if (grad_w || grad_x) {
         fastsum_status r = sum_pass(pl, yp, ldy, grad_s, M, pl->xproj, pl->ld_x, N, uout,
-                                    pl->grid_w, grad_x ? pl->grid_wd : nullptr, st);
+                                    pl->grid_w, grad_x ? pl->grid_wd : nullptr, BoundCheck{}, st);
         if (r != FASTSUM_OK) return r;
     }
     if (grad_x) {

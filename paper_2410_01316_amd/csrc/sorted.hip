@@ -313,8 +313,9 @@ __global__ __launch_bounds__(kSortBlock) void sorted_grad_kernel(
 // s[m] = scale * sum_p V[p ldm + m], FP64 over the directions in order.
 __global__ __launch_bounds__(256) void sorted_reduce_kernel(const float* __restrict__ V, int P,
                                                             int64_t ldm, int64_t M, double scale,
-                                                            float* __restrict__ s) {
+                                                            float* __restrict__ s, BoundCheck bc) {
     const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m == 0) finish_bound_check(bc);
     if (m >= M) return;
     double acc = 0.0;
     for (int p = 0; p < P; ++p) acc += (double)V[(int64_t)p * ldm + m];
@@ -324,9 +325,9 @@ __global__ __launch_bounds__(256) void sorted_reduce_kernel(const float* __restr
 }  // namespace
 
 hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
-                                float* s, hipStream_t stream) {
+                                float* s, const BoundCheck& bc, hipStream_t stream) {
     hipLaunchKernelGGL(sorted_reduce_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0,
-                       stream, V, P, ldm, M, scale, s);
+                       stream, V, P, ldm, M, scale, s, bc);
     return hipGetLastError();
 }
 

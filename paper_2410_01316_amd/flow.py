@@ -16,7 +16,7 @@ rebuilt with a margin whenever they leave it.
 import numpy as np
 import torch
 
-from .api import Plan
+from .api import Plan, bound
 
 
 class MMDFlow:
@@ -49,17 +49,13 @@ class MMDFlow:
                             torch.full((M,), -1.0 / (M * N), dtype=torch.float32, device=dev)])
         self.ones = torch.ones(N, dtype=torch.float32, device=dev)
         self.s = torch.empty(N, dtype=torch.float32, device=dev)
-        self.y_norm = float(self.y.norm(dim=1).max())
         self.plan, self.R, self.rebuilds = None, 0.0, 0
 
-    def _bound(self, x):
-        # sources [x; y] and targets x about the origin (App. I, Step 1)
-        xn = float(x.norm(dim=1).max())
-        return max(xn, self.y_norm) + xn
-
     def _ensure_plan(self, x):
-        need = self._bound(x)
-        if self.plan is not None and need <= self.R:
+        # sources z = [x; y] and targets x about the origin (App. J,
+        # eq. radius_xy), on the device; z already holds the particles
+        need = bound(self.z, x)
+        if self.plan is not None and need * (1.0 + 1e-4) <= self.R:
             return
         if self.plan is not None:
             self.plan.close()
@@ -72,8 +68,8 @@ class MMDFlow:
 
     def gradient(self, x):
         """grad G_y at the particles x (N x d); returns a new tensor."""
-        self._ensure_plan(x)
         self.z[: self.N].copy_(x)
+        self._ensure_plan(x)
         self.plan(self.z, self.w, x, out=self.s)
         gy, _ = self.plan.grad(self.ones, want_y=True, want_w=False)
         return gy

@@ -12,6 +12,13 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def max_rel(a, b):
+    """max_i |a_i - b_i| / max_i |b_i|: the element-wise companion of rel_l2."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
 def err_scale(a, b, s_abs):
     """||a - b|| / ||s_abs||, s_abs_m = sum_n |w_n| |F(||x_n - y_m||)|:
     relative error that stays meaningful when s cancels under signed weights."""

@@ -1,0 +1,288 @@
+"""The adjoint (grad_y, grad_w, grad_x) against the FP64 oracle at the
+dimensions the workloads use, on both projection paths, and against central
+finite differences of the GPU's own FP32 forward.
+
+Oracle bars: the GPU adjoint and the oracle's analytic gradient of the same
+truncated Fourier series (eq. Fourier-slicing, differentiated through
+x~ = tau <xi, x>) differ by the window error and FP32 rounding, measured at
+1e-5..2e-5 (grad_y), ~2e-6 (grad_w) and 2e-5 (grad_x, Gauss); the bar is
+1e-4.  The energy kernel's grad_x is the exception (bar 1e-3): where the
+sources include the targets its derivative, a sign function, is
+interpolated at its jump, where the truncated series and the window
+converge slowest (3e-4 measured).
+
+Gauss at N_ft = 1024 as in the workloads: at N_ft = 128 (a 256-cell grid)
+the width-4 window's aliasing, weighted up by the derivative's 2 pi i k,
+leaves 1e-4..3e-4 in grad_y and grad_x (measured).
+
+Finite differences (h = 1e-3, central) of the FP32 forward against the
+adjoint: the rounding of each s_m to FP32 makes the difference quotient
+noisy by about 6e-8 N F/(2 h |F'|) relative, ~2e-3 with N = 64 sources; the
+bar is 2e-2."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import directions
+from workloads.points import median_rule_sigma, image_like, mmd_particles
+from helpers import rel_l2, max_rel, gpu_plan, to_dev, oracle_inputs, DEFAULT_T
+
+pytestmark = pytest.mark.gpu
+
+
+def _tau(cfg):
+    return O.rescale_tau(cfg["kernel"], cfg["R"], cfg["scale"], DEFAULT_T[cfg["kernel"]])
+
+
+def _mmd_cfg(kernel, d, n, P, seed, n_ft):
+    """One MMD flow step's sum (App. MMD flows) in dimension d: particles
+    x ~ N(3 1, 0.5 I), targets y ~ N(0, I), sources [x; y] with weights
+    [1/n^2, -1/n^2], evaluated at the particles."""
+    rng = np.random.default_rng(seed)
+    part, targ = mmd_particles(n, n, d, rng)
+    src = np.concatenate([part, targ])
+    w = np.concatenate([np.full(n, 1.0 / n ** 2), np.full(n, -1.0 / n ** 2)])
+    scale = median_rule_sigma(part, targ, rng) if kernel == "gauss" else 1.0
+    R = float(np.linalg.norm(src, axis=1).max() + np.linalg.norm(part, axis=1).max())
+    xi = directions("distance" if d <= 64 else "orth", d, P, seed)
+    return dict(x=src, y=part, w=w, xi=xi, kernel=kernel, scale=scale, n_ft=n_ft, R=R)
+
+
+def _mixture_cfg(d, N, M, P, seed, n_ft):
+    """Gauss kernel on a 4-component mixture with signed weights w ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    means = rng.standard_normal((4, d)) * 1.5
+    x = means[rng.integers(0, 4, N)] + rng.standard_normal((N, d))
+    y = means[rng.integers(0, 4, M)] + rng.standard_normal((M, d))
+    w = rng.standard_normal(N)
+    R = float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max())
+    return dict(x=x, y=y, w=w, xi=directions("distance", d, P, seed), kernel="gauss",
+                scale=median_rule_sigma(x, y, rng), n_ft=n_ft, R=R)
+
+
+def _gpu_grads(cfg, v, materialize=False, proj="fp32", window_w=0):
+    plan = gpu_plan(cfg, grad=True, materialize=materialize, proj=proj, window_w=window_w)
+    xd, yd, wd, vd = to_dev(cfg["x"], cfg["y"], cfg["w"], v)
+    plan(xd, wd, yd)
+    gx, gy, gw = plan.grad(vd, want_x=True)
+    plan.check()
+    fused = plan.info()["fused"]
+    out = [g.cpu().numpy().astype(np.float64) for g in (gx, gy, gw)]
+    plan.close()
+    return out, fused
+
+
+def _oracle_grads(cfg, v, ys=None, xs=None, w=None):
+    """O3 gradients; ys / xs restrict grad_y to target rows and grad_x,
+    grad_w to source rows (each row depends on all others only through the
+    sums the oracle forms in full); w replaces the weights."""
+    x, y, w0, xi = oracle_inputs(cfg)
+    w = w0 if w is None else w
+    k, sc, nft, tau = cfg["kernel"], cfg["scale"], cfg["n_ft"], _tau(cfg)
+    ys = np.arange(y.shape[0]) if ys is None else ys
+    xs = np.arange(x.shape[0]) if xs is None else xs
+    gy = O.grad_y_fourier(k, x, y[ys], w, xi, sc, nft, tau) * v[ys, None]
+    gw = O.grad_w_fourier(k, x[xs], y, v, xi, sc, nft, tau)
+    gx = O.grad_x_fourier(k, x[xs], y, w[xs], v, xi, sc, nft, tau)
+    return gx, gy, gw
+
+
+def _check(tag, got, ref, tol_x):
+    (gx, gy, gw), (rx, ry, rw) = got, ref
+    ex, ey, ew = rel_l2(gx, rx), rel_l2(gy, ry), rel_l2(gw, rw)
+    mx, my, mw = max_rel(gx, rx), max_rel(gy, ry), max_rel(gw, rw)
+    print(f"{tag}: grad_y {ey:.2e} grad_w {ew:.2e} grad_x {ex:.2e} "
+          f"(max element {my:.2e} {mw:.2e} {mx:.2e})")
+    assert ey < 1e-4 and ew < 1e-4 and ex < tol_x
+    assert my < 1e-3 and mw < 1e-3 and mx < 10 * tol_x
+
+
+@pytest.mark.parametrize("kernel,d,materialize", [
+    ("gauss", 50, False), ("gauss", 50, True), ("gauss", 64, False), ("gauss", 64, True),
+    ("energy", 50, False), ("energy", 64, False)],
+    ids=["gauss-d50-fused", "gauss-d50-stored", "gauss-d64-fused", "gauss-d64-stored",
+         "energy-d50-stored", "energy-d64-stored"])
+def test_adjoint_matches_oracle_d50_d64(kernel, d, materialize):
+    """MMD-step sums at d = 50 (the scale workload's dimension) and 64 (the
+    widest fused operand): ragged target tiles, two 32-coordinate chunks of
+    the stored back-projection (blockIdx.y > 0), two fused k-blocks.  The
+    cotangent is positive (v = 1 in a flow), so grad_w does not cancel."""
+    n = 900
+    cfg = _mmd_cfg(kernel, d, n, 16, seed=d + len(kernel), n_ft=1024)
+    v = np.random.default_rng(d).uniform(0.5, 1.5, n)
+    got, fused = _gpu_grads(cfg, v, materialize)
+    # Gauss fuses for d <= 64 unless materialized; the energy grids are too wide
+    assert fused == (1 if kernel == "gauss" and not materialize else 0)
+    _check(f"{kernel} d={d} fused={fused}", got, _oracle_grads(cfg, v),
+           1e-4 if kernel == "gauss" else 1e-3)
+
+
+@pytest.mark.parametrize("materialize", [False, True], ids=["fused", "stored"])
+def test_adjoint_signed_weights_d50(materialize):
+    """Signed weights and cotangent (w, v ~ N(0, 1)) on a d = 50 mixture: the
+    gradients cancel (grad_w = sum_m v_m K, a sum of terms of random sign),
+    so the error is measured against the size of the terms, the O3 gradient
+    with |w| and |v| (as err_scale does for sums), bar 2e-5."""
+    cfg = _mixture_cfg(50, 1500, 1100, 40, seed=77, n_ft=128)
+    v = np.random.default_rng(78).standard_normal(1100)
+    (gx, gy, gw), fused = _gpu_grads(cfg, v, materialize)
+    assert fused == (0 if materialize else 1)
+    rx, ry, rw = _oracle_grads(cfg, v)
+    ax, ay, aw = _oracle_grads(cfg, np.abs(v), w=np.abs(oracle_inputs(cfg)[2]))
+    es = [float(np.linalg.norm(g - r) / np.linalg.norm(a))
+          for g, r, a in ((gy, ry, ay), (gw, rw, aw), (gx, rx, ax))]
+    print("signed d=50 fused=%d: err_scale grad_y %.2e grad_w %.2e grad_x %.2e; rel-L2 "
+          "%.2e %.2e %.2e" % (fused, *es, rel_l2(gy, ry), rel_l2(gw, rw), rel_l2(gx, rx)))
+    assert max(es) < 2e-5
+
+
+@pytest.mark.parametrize("kernel,proj", [("gauss", "fp32"), ("energy", "fp32"), ("energy", "bf16")])
+def test_adjoint_matches_oracle_d100_tile_gemm(kernel, proj):
+    """MMD-step sums at d = 100: projections by the tile GEMM (f16 hi + lo
+    operands, or BF16 for the precision form, whose adjoint then
+    differentiates the sum of the rounded projections), back-projection over
+    four coordinate chunks."""
+    cfg = _mmd_cfg(kernel, 100, 700, 16, seed=100 + len(kernel), n_ft=1024)
+    v = np.random.default_rng(5).uniform(0.5, 1.5, 700)
+    got, fused = _gpu_grads(cfg, v, proj=proj)
+    assert fused == 0
+    ref = _oracle_grads(cfg, v)
+    if proj == "bf16":
+        # coordinates and directions rounded to 8 mantissa bits move every
+        # projection by ~2^-9 relative: a coarse bar on the same gradients
+        es = [rel_l2(g, r) for g, r in zip(got, ref)]
+        print("energy bf16 d=100: grad_x %.2e grad_y %.2e grad_w %.2e" % tuple(es))
+        assert max(es) < 3e-2
+    else:
+        _check(f"{kernel} d=100", got, ref, 1e-4 if kernel == "gauss" else 1e-3)
+
+
+def test_adjoint_flow_shape_d3072():
+    """The MMD flow at the paper's CIFAR10 shape (App. MMD flows): energy
+    kernel, d = 3072, particles N = 50000 (standard normal) and image-like
+    targets M = 50000, sources [x; y] with weights [1/N^2, -1/(MN)], targets
+    x.  A plan on 4 orthonormal directions (the estimator is a mean over
+    directions, so this is the same computation at full N, M and grid):
+    grad_y on 12 sampled particles and grad_x, grad_w on 12 sampled sources
+    against the O3 gradients, the cotangent of the flow (v = 1).  With 4
+    directions the window errors do not average out over directions as they
+    do over P = 1000, so the width-6 window keeps them below the bar."""
+    rng = np.random.default_rng(8)
+    N = M = 50000
+    d, P = 3072, 4
+    y = image_like(M, d, rng)
+    x = rng.standard_normal((N, d))
+    z = np.concatenate([x, y])
+    w = np.concatenate([np.full(N, 1.0 / N ** 2), np.full(M, -1.0 / (M * N))])
+    R = float(np.linalg.norm(z, axis=1).max() + np.linalg.norm(x, axis=1).max())
+    cfg = dict(x=z, y=x, w=w, xi=directions("orth", d, P, 9), kernel="energy", scale=1.0,
+               n_ft=1024, R=R)
+    v = np.ones(N)
+    (gx, gy, gw), fused = _gpu_grads(cfg, v, window_w=6)
+    assert fused == 0
+    ys = np.sort(rng.choice(N, 12, replace=False))
+    xs = np.sort(np.concatenate([rng.choice(N, 6, replace=False), N + rng.choice(M, 6, replace=False)]))
+    rx, ry, rw = _oracle_grads(cfg, v, ys=ys, xs=xs)
+    ex, ey, ew = rel_l2(gx[xs], rx), rel_l2(gy[ys], ry), rel_l2(gw[xs], rw)
+    print(f"energy d=3072 N=M=50000 P=4: grad_y {ey:.2e} grad_w {ew:.2e} grad_x {ex:.2e}")
+    assert ey < 1e-4 and ew < 1e-4 and ex < 1e-3
+
+
+def _fd_problem(kernel, seed=21):
+    rng = np.random.default_rng(seed)
+    N, M, d, P = 64, 96, 6, 48
+    x = rng.standard_normal((N, d)) * 0.8
+    y = rng.standard_normal((M, d)) * 0.8 + 0.3
+    w = rng.uniform(0.5, 1.5, N)
+    R = 1.3 * float(np.linalg.norm(x, axis=1).max() + np.linalg.norm(y, axis=1).max())
+    cfg = dict(x=x, y=y, w=w, xi=directions("distance", d, P, seed), kernel=kernel,
+               scale=1.0, n_ft=256 if kernel == "gauss" else 1024, R=R)
+    # a positive cotangent, as in a flow (v = 1): the x-derivative sums
+    # coherently over the targets, above the FP32 rounding of the sums
+    return cfg, rng.uniform(0.5, 1.5, M)
+
+
+@pytest.mark.parametrize("kernel,materialize", [("gauss", False), ("gauss", True),
+                                                ("energy", False)],
+                         ids=["gauss-fused", "gauss-stored", "energy-stored"])
+def test_adjoint_matches_gpu_finite_differences(kernel, materialize):
+    """Central differences (h = 1e-3) of L = v . s, the FP32 GPU forward
+    summed in FP64, on 24 seeded coordinates of y, of x and entries of w,
+    against the GPU adjoint of the same plan."""
+    import torch
+    cfg, v = _fd_problem(kernel)
+    plan = gpu_plan(cfg, grad=True, materialize=materialize)
+    xd, yd, wd, vd = to_dev(cfg["x"], cfg["y"], cfg["w"], v)
+    plan(xd, wd, yd)
+    gx, gy, gw = (g.cpu().numpy().astype(np.float64) for g in plan.grad(vd, want_x=True))
+    h = 1e-3
+
+    def L(x, y, w):
+        s = plan(x, w, y).cpu().numpy().astype(np.float64)
+        return float(v @ s)
+
+    rng = np.random.default_rng(3)
+    res = {}
+    for name, base, g in (("y", yd, gy), ("x", xd, gx), ("w", wd, gw)):
+        flat = base.reshape(-1)
+        idx = rng.choice(flat.numel(), 24, replace=False)
+        fd = []
+        for i in idx:
+            old = float(flat[i])
+            vals, pts = [], []
+            for sgn in (1.0, -1.0):
+                flat[i] = old + sgn * h
+                pts.append(float(flat[i]))          # the FP32 value actually used
+                vals.append(L(xd, yd, wd))
+            flat[i] = old
+            fd.append((vals[0] - vals[1]) / (pts[0] - pts[1]))
+        res[name] = rel_l2(np.array(fd), g.reshape(-1)[idx])
+    torch.cuda.synchronize()
+    plan.check()
+    plan.close()
+    print(kernel, "fused" if not materialize and kernel == "gauss" else "stored",
+          "FD vs adjoint: " + " ".join(f"{k} {e:.2e}" for k, e in res.items()))
+    for k, e in res.items():
+        assert e < 2e-2, k
+
+
+def test_autograd_sources_constant():
+    """FastSum with x constant (the ds/dy, ds/dw use), then with x and w
+    constant: the gradients equal the plan's own adjoint, bit for bit."""
+    import torch
+    import paper_2410_01316_amd as F
+    cfg, v = _fd_problem("gauss", seed=31)
+    plan = gpu_plan(cfg, grad=True)
+    xd, yd, wd, vd = to_dev(cfg["x"], cfg["y"], cfg["w"], v)
+    plan(xd, wd, yd)
+    gy_ref, gw_ref = plan.grad(vd)
+    ya, wa = yd.clone().requires_grad_(True), wd.clone().requires_grad_(True)
+    s = F.FastSum.apply(plan, xd, ya, wa)
+    (s * vd).sum().backward()
+    assert torch.equal(ya.grad, gy_ref) and torch.equal(wa.grad, gw_ref)
+    yb = yd.clone().requires_grad_(True)
+    s = F.FastSum.apply(plan, xd, yb, wd)
+    (s * vd).sum().backward()
+    assert torch.equal(yb.grad, gy_ref)
+    plan.close()
+
+
+def test_autograd_two_sums_on_one_plan():
+    """Two FastSum calls on one plan in one graph: each backward uses its own
+    inputs (the plan is re-run for the earlier one)."""
+    import torch
+    import paper_2410_01316_amd as F
+    cfg, v = _fd_problem("gauss", seed=41)
+    plan = gpu_plan(cfg, grad=True)
+    xd, yd, wd, vd = to_dev(cfg["x"], cfg["y"], cfg["w"], v)
+    y2 = (yd * 0.5).contiguous()
+    refs = []
+    for yy in (yd, y2):
+        plan(xd, wd, yy)
+        refs.append(plan.grad(vd))
+    ya, yb = yd.clone().requires_grad_(True), y2.clone().requires_grad_(True)
+    s1 = F.FastSum.apply(plan, xd, ya, wd)
+    s2 = F.FastSum.apply(plan, xd, yb, wd)
+    ((s1 + s2) * vd).sum().backward()
+    assert torch.equal(ya.grad, refs[0][0]) and torch.equal(yb.grad, refs[1][0])
+    plan.close()

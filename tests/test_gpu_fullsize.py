@@ -106,7 +106,7 @@ def test_mmd_full_size_gradients(kernel):
         msg += f", fused vs stored s {rel_l2(s_f, s_m):.2e} grad_y {rel_l2(g_f, g_m):.2e}"
         assert rel_l2(s_f, s_m) < 1e-5 and rel_l2(g_f, g_m) < 1e-4
     print(msg)
-    assert e3 < 1e-3
+    assert e3 < 1e-4
     assert e1 < 0.1
 
 

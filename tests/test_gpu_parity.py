@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 from workloads import make_config, directions
-from helpers import rel_l2, err_scale, gpu_plan, to_dev, oracle_inputs, DEFAULT_T
+from helpers import rel_l2, max_rel, err_scale, gpu_plan, to_dev, oracle_inputs, DEFAULT_T
 
 pytestmark = pytest.mark.gpu
 
@@ -300,11 +300,16 @@ def test_gradients_match_oracle(kernel, materialize):
     gy = y.grad.cpu().numpy()
     gw = w.grad.cpu().numpy()
     gx = x.grad.cpu().numpy()
-    print(kernel, "grad_y %.2e grad_w %.2e grad_x %.2e"
-          % (rel_l2(gy, gy_ref), rel_l2(gw, gw_ref), rel_l2(gx, gx_ref)))
-    assert rel_l2(gy, gy_ref) < 1e-3
-    assert rel_l2(gw, gw_ref) < 1e-4
-    assert rel_l2(gx, gx_ref) < 1e-3
+    print(kernel, "grad_y %.2e grad_w %.2e grad_x %.2e (max element %.2e %.2e %.2e)"
+          % (rel_l2(gy, gy_ref), rel_l2(gw, gw_ref), rel_l2(gx, gx_ref),
+             max_rel(gy, gy_ref), max_rel(gw, gw_ref), max_rel(gx, gx_ref)))
+    # window error and FP32 rounding: 1e-5..2e-5 measured; the energy
+    # kernel's grad_x is interpolated at the jump of its sign derivative
+    # (sources include the targets), 3e-4 measured
+    tol_x = 1e-4 if kernel == "gauss" else 1e-3
+    assert rel_l2(gy, gy_ref) < 1e-4 and max_rel(gy, gy_ref) < 1e-3
+    assert rel_l2(gw, gw_ref) < 1e-4 and max_rel(gw, gw_ref) < 1e-3
+    assert rel_l2(gx, gx_ref) < tol_x and max_rel(gx, gx_ref) < 10 * tol_x
 
 
 def test_kernel_sum_one_shot():
