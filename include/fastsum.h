@@ -411,6 +411,25 @@ FASTSUM_API fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t it
                                                 float* xi, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * iteration as fastsum_distance_qmc, same arguments and the same result bit
+ * for bit, with its workspace (Adam moments and partial gradient sums) in a
+ * static device array of 5 Mi floats (20 MiB) that the library holds on
+ * each GPU it runs on until the process ends.  It calls no allocator and
+ * does not synchronise: the steps are only enqueued on `stream`.
+ * Requires 2 P d + the partial sums (at most 65 P ceil(2048 / ceil(P/64))
+ * floats) <= 5 Mi floats, which holds for every P <= 2048 at any d <= 64;
+ * larger requests return EINVAL.  Calls on one GPU share the array, so
+ * calls that overlap in time on one GPU (other streams, other threads)
+ * race; serialise them.  Nothing needs clearing between calls.
+ * Errors: EINVAL (arguments, or the workspace would exceed the array),
+ * EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_distance_qmc_noalloc(int32_t d, int32_t P, int32_t iters,
+                                                        double lr, float* xi, void* stream);
+
+/*
  * Host-only N_ft selection rule: the smallest candidate N_ft whose discarded
  * Fourier mass sum_{|k| > N_ft/2} |c_k| is at most tol * sum_k |c_k| (FP64,
  * c_k of prm's kernel, d, scale, T, R; tails summed to |k| = 4096).  Falls

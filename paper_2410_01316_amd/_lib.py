@@ -82,6 +82,8 @@ SIGNATURES = {
     "fastsum_distance_qmc": (_st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                    _vp, _vp]),
     "fastsum_bound": (_st, [_vp, _i64, _vp, _i64, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "fastsum_distance_qmc_noalloc": (_st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_double, _vp, _vp]),
 }
 
 _lib = None

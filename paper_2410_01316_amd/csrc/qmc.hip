@@ -11,10 +11,12 @@
 // q of one q-chunk stream through LDS in tiles of 64, read as broadcasts;
 // a second kernel, one wave per row, sums the chunks in order and takes the
 // Adam step.
+#include "fastsum.h"
 #include "fastsum_impl.h"
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace fastsum {
 
@@ -163,3 +165,54 @@ hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* m,
 }
 
 }  // namespace fastsum
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the Adam moments and the chunk partials live in a
+// static device array of fixed size.  Nothing in it needs clearing between
+// calls: the first step takes the moments as zero without reading them and
+// every step overwrites every partial it reads.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kQmcScratchFloats = (size_t)5 << 20;    // 20 MiB per device
+static __device__ __align__(256) float scratch[kQmcScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per
+// device; the host-side name is not a device address).
+hipError_t scratch_on_current_device(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (ptr == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" fastsum_status fastsum_distance_qmc_noalloc(int32_t d, int32_t P, int32_t iters,
+                                                       double lr, float* xi, void* stream) {
+    if (!xi || d < 1 || d > 64 || P < 1 || iters < 0 || !(lr > 0.0) || !std::isfinite(lr))
+        return FASTSUM_EINVAL;
+    const size_t n = (size_t)P * d;
+    if (2 * n + fastsum::distance_qmc_part_floats(P) > kQmcScratchFloats) return FASTSUM_EINVAL;
+    float* base = nullptr;
+    if (scratch_on_current_device(&base) != hipSuccess) return FASTSUM_EDEVICE;
+    const hipError_t e = fastsum::distance_qmc(xi, P, d, iters, lr, base, base + n, base + 2 * n,
+                                               (hipStream_t)stream);
+    if (e == hipErrorInvalidValue) return FASTSUM_EINVAL;
+    return e == hipSuccess ? FASTSUM_OK : FASTSUM_EDEVICE;
+}
