@@ -149,30 +149,92 @@ def measured_traffic(phase, P):
         return None
 
 
-def cpu_baseline(cfg, s_gpu, n_sample, seed=123):
-    """FP64 direct sum (the oracle, untuned) on a seeded sample of targets,
-    single BLAS thread; also the GPU error on the same targets."""
-    import oracle as O
+def host_threads():
+    """Worker threads for the CPU references: the host cores this process may
+    use, at most 16 (the CPU share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_over_targets(fn, y, threads):
+    """fn(y_block) for blocks of targets on `threads` host threads (one BLAS
+    thread each; numpy releases the GIL in its array loops), concatenated in
+    order: the oracle as it is, run on every core."""
+    from concurrent.futures import ThreadPoolExecutor
     from threadpoolctl import threadpool_limits
+    blocks = [b for b in np.array_split(np.arange(y.shape[0]), 4 * threads) if len(b)]
+    with threadpool_limits(limits=1), ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda b: fn(y[b]), blocks))
+    return np.concatenate(parts)
+
+
+def sample_targets(M, n, seed, exclude=None):
+    """n seeded target indices, disjoint from `exclude` when given."""
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(cfg["M"], size=min(n_sample, cfg["M"]), replace=False))
+    pool = np.arange(M) if exclude is None else np.setdiff1d(np.arange(M), exclude)
+    return np.sort(rng.choice(pool, size=min(n, len(pool)), replace=False))
+
+
+_REFS = {}
+
+
+def direct_reference(cfg, idx):
+    """FP64 direct sums (O1) s and s_abs (|w|) at the targets idx, on every
+    host core; the Gram-identity form for d >= 16 (one matrix product per
+    block instead of an array of differences).  Cached per workload."""
+    import oracle as O
+    key = (cfg["name"], cfg["kernel"], cfg["N"], cfg["M"], len(idx), int(idx.sum()))
+    if key not in _REFS:
+        d64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+        x, y, w = d64(cfg["x"]), d64(cfg["y"])[idx], d64(cfg["w"])
+        fn = O.kernel_sum_direct_gram if cfg["d"] >= 16 else O.kernel_sum_direct
+        th = host_threads()
+        s1 = oracle_over_targets(lambda yb: fn(cfg["kernel"], x, yb, w, cfg["scale"]), y, th)
+        sa = oracle_over_targets(lambda yb: fn(cfg["kernel"], x, yb, np.abs(w), cfg["scale"]),
+                                 y, th)
+        _REFS[key] = (s1, sa)
+    return _REFS[key]
+
+
+def cpu_baseline(cfg, n_sample, seed=123):
+    """The FP64 direct sum (the oracle, untuned) on a seeded sample of
+    targets, run on every host core (target blocks on threads); its result
+    is also the reference for the GPU error on those targets."""
+    import oracle as O
+    idx = sample_targets(cfg["M"], n_sample, seed)
     d64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
     x, y, w = d64(cfg["x"]), d64(cfg["y"])[idx], d64(cfg["w"])
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        s1 = O.kernel_sum_direct(cfg["kernel"], x, y, w, cfg["scale"])
-        dt = time.perf_counter() - t0
-    sg = np.asarray(s_gpu, np.float64)[idx]
-    err = float(np.linalg.norm(sg - s1) / np.linalg.norm(s1))
+    th = host_threads()
+    t0 = time.perf_counter()
+    s1 = oracle_over_targets(lambda yb: O.kernel_sum_direct(cfg["kernel"], x, yb, w, cfg["scale"]),
+                             y, th)
+    dt = time.perf_counter() - t0
     pairs = len(idx) * cfg["N"]
-    return dict(value=pairs / dt, unit="pairs/s", cores=1, kind="oracle",
-                sample=f"FP64 direct sum, {len(idx)} seeded targets x all {cfg['N']} sources "
-                       f"(d={cfg['d']}), {dt:.1f} s"), err, idx, s1
+    return dict(value=pairs / dt, unit="pairs/s", cores=th, kind="oracle",
+                cpu_model=cpu_model(), os_cpu_count=os.cpu_count(),
+                sample=f"FP64 direct sum (explicit differences), {len(idx)} seeded targets x "
+                       f"all {cfg['N']} sources (d={cfg['d']}), {dt:.1f} s on {th} threads"), \
+        idx, s1
 
 
-def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, err_kind=None,
-             sorting=False):
-    """Time one more form; returns a dict (ms, pairs/s, optional error)."""
+def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0,
+             grad_targets=0, sorting=False):
+    """Time one more form; returns a dict (ms, pairs/s, errors against the
+    FP64 direct sum on err_targets sampled targets and, with grad, of grad_y
+    on grad_targets)."""
     import torch
     import oracle as O
     plan = make_plan(cfg, proj=proj, grad=grad, sorting=sorting)
@@ -181,10 +243,12 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, e
     out = torch.empty(cfg["M"], dtype=torch.float32, device="cuda")
     ones = torch.ones(cfg["M"], dtype=torch.float32, device="cuda")
 
+    last = {}
+
     def step():
         plan(x, w, y, out=out)
         if grad:
-            plan.grad(ones, want_y=True, want_w=False)
+            last["gy"], _ = plan.grad(ones, want_y=True, want_w=False)
 
     ms = timed_steps(step, steps, warmup) * 1e3
     plan.check()
@@ -218,16 +282,25 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0, e
                                       frac=flops / t / 1e12 / peak, note=note,
                                       includes="operand-tile writing and the GEMM")
     if err_targets:
-        rng = np.random.default_rng(7)
-        idx = np.sort(rng.choice(cfg["M"], size=err_targets, replace=False))
-        d64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
-        xo, yo, wo = d64(cfg["x"]), d64(cfg["y"])[idx], d64(cfg["w"])
-        s1 = O.kernel_sum_direct(cfg["kernel"], xo, yo, wo, cfg["scale"])
+        # FP64 direct sums on a seeded target subsample (precision workload:
+        # 2000 targets, as its definition asks), on every host core
+        idx = sample_targets(cfg["M"], err_targets, 7)
+        s1, s_abs = direct_reference(cfg, idx)
         sg = out.cpu().numpy().astype(np.float64)[idx]
         res["rel_l2_vs_fp64_direct"] = float(np.linalg.norm(sg - s1) / np.linalg.norm(s1))
-        s_abs = O.kernel_sum_direct(cfg["kernel"], xo, yo, np.abs(wo), cfg["scale"])
         res["err_scale_vs_fp64_direct"] = float(np.linalg.norm(sg - s1) / np.linalg.norm(s_abs))
-        res["error_sample_targets"] = int(err_targets)
+        res["error_sample_targets"] = int(len(idx))
+    if grad and grad_targets:
+        # grad_y (cotangent 1) against the FP64 direct gradient of O1
+        idx = sample_targets(cfg["M"], grad_targets, 8)
+        d64 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+        x64, w64 = d64(cfg["x"]), d64(cfg["w"])
+        g1 = oracle_over_targets(lambda yb: O.grad_y_direct(cfg["kernel"], x64, yb, w64,
+                                                            cfg["scale"]),
+                                 d64(cfg["y"])[idx], host_threads())
+        gg = last["gy"].cpu().numpy().astype(np.float64)[idx]
+        res["grad_y_rel_l2_vs_fp64_direct"] = float(np.linalg.norm(gg - g1) / np.linalg.norm(g1))
+        res["grad_error_sample_targets"] = int(len(idx))
     plan.close()
     del x, w, y, out
     torch.cuda.empty_cache()
@@ -382,17 +455,19 @@ def form_runners(fsteps):
     def matern(kern):
         cfgm = make_config("scale", kernel=kern)
         cfgm["n_ft"] = 512                      # App. I value for the Matern kernel
-        return run_form(kern, cfgm, fsteps, 2, err_targets=64)
+        return run_form(kern, cfgm, fsteps, 2, err_targets=1000)
 
     def precision(**kw):
-        return run_form("precision", make_config("precision"), fsteps, 1, err_targets=16, **kw)
+        # error against the FP64 direct sum on a 2000-target subsample
+        return run_form("precision", make_config("precision"), fsteps, 1, err_targets=2000, **kw)
 
     def mmd(kernel, **kw):
-        return run_form("mmd", make_config("mmd", kernel=kernel), fsteps, 2, **kw)
+        return run_form("mmd", make_config("mmd", kernel=kernel), fsteps, 2, err_targets=2000,
+                        grad_targets=256 if kw.get("grad") else 0, **kw)
 
     return [
         ("laplace_fp32", lambda: run_form("laplace", make_config("scale", kernel="laplace"),
-                                          fsteps, 2, err_targets=64)),
+                                          fsteps, 2, err_targets=1000)),
         ("matern32_fp32", lambda: matern("matern32")),
         ("matern72_fp32", lambda: matern("matern72")),
         ("precision_fp32", lambda: precision(proj="fp32")),
@@ -400,7 +475,7 @@ def form_runners(fsteps):
         ("precision_sorted", lambda: precision(sorting=True)),
         ("mmd_gauss_fwd_grad", lambda: mmd("gauss", grad=True)),
         ("mmd_energy_fwd_grad", lambda: mmd("energy", grad=True)),
-        ("mmd_energy_sorted", lambda: mmd("energy", err_targets=32, sorting=True)),
+        ("mmd_energy_sorted", lambda: mmd("energy", sorting=True)),
         ("mmd_energy_sorted_fwd_grad", lambda: mmd("energy", grad=True, sorting=True)),
         ("mmd_flow_energy_d3072", lambda: mmd_flow_form(fsteps)),
         ("batched_256", lambda: batched_form(fsteps, None)),
@@ -460,7 +535,7 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         log(f"bench: FP64 direct sum (CPU oracle) on {args.cpu_sample} targets")
-        base, _, idx, s1 = cpu_baseline(cfg, np.zeros(M), args.cpu_sample)
+        base, idx, s1 = cpu_baseline(cfg, args.cpu_sample)
 
     def err_of(out):
         sg = out.cpu().numpy().astype(np.float64)[idx]
@@ -529,6 +604,16 @@ def main():
     plan.profile(False)
     plan.check()
     err_at_P = err_of(s) if base is not None else None
+    confirm = None
+    if base is not None:
+        # the operating point was chosen on the sample idx; its error on a
+        # disjoint sample of as many targets confirms it
+        idx_b = sample_targets(M, len(idx), 321, exclude=idx)
+        s1b, _ = direct_reference(dict(cfg, name="scale-confirm"), idx_b)
+        sgb = s.cpu().numpy().astype(np.float64)[idx_b]
+        confirm = dict(sample_targets=int(len(idx_b)), seed=321,
+                       rel_l2_vs_fp64_direct=float(np.linalg.norm(sgb - s1b) / np.linalg.norm(s1b)),
+                       note="disjoint from the targets the ladder was evaluated on")
     info = plan.info()
     ms_per_step = elapsed / args.steps * 1e3
     value = N * M * args.steps / elapsed
@@ -617,6 +702,7 @@ def main():
         result["cpu_baseline"] = base
         result["accuracy"] = {"rel_l2_vs_fp64_direct": err_at_P, "sample_targets": len(idx),
                               "target": TARGET_ERR, "ladder": ladder,
+                              "confirmation_sample": confirm,
                               "note": "slicing (QMC) error of the method dominates; window "
                                       "and FP32 error of the GPU path <= 1e-4"}
         if nominal is not None:

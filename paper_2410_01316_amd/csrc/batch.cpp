@@ -58,7 +58,7 @@ struct fastsum_batch_s {
     int task_cnt[kBatchPhases] = {};
     size_t lds_spread = 0, lds_fft = 0, lds_gather = 0;
     int* flag = nullptr;
-    unsigned* norms = nullptr;         // bound check slots, two per problem
+    unsigned* norms = nullptr;         // bound check slots, kNormUints per problem
     bool norms_dirty = false;          // a direct launch stopped before the checks cleared them
     // replay state
     std::vector<fastsum_problem_io> last_io;
@@ -220,7 +220,7 @@ fastsum_status build_tasks(fastsum_batch_s* b, const fastsum_problem_io* io) {
             d.yproj = reinterpret_cast<float*>(b->arena + pp.off_yproj);
         }
         d.inv_r = (float)(1.0 / pp.r.p.R);
-        d.norms = b->norms + 2 * i;
+        d.norms = b->norms + (size_t)kNormUints * i;
         d.norm_lim = pp.norm_lim;
         d.partial = reinterpret_cast<float*>(b->arena + pp.off_partial);
         d.grid = reinterpret_cast<float*>(b->arena + pp.off_grid);
@@ -466,7 +466,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_probs, sizeof(BatchProblem) * n_problems);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_tasks, sizeof(BatchTask) * std::max<size_t>(tasks, 1));
     if (e == hipSuccess) e = hipMalloc((void**)&b->flag, sizeof(int));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->norms, sizeof(unsigned) * 2 * n_problems);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->norms, sizeof(unsigned) * kNormUints * n_problems);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_probs, sizeof(BatchProblem) * n_problems);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_tasks, sizeof(BatchTask) * std::max<size_t>(tasks, 1));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
@@ -486,7 +486,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
                                hipMemcpyHostToDevice, hs);
     }
     if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), hs);
-    if (e == hipSuccess) e = hipMemsetAsync(b->norms, 0, sizeof(unsigned) * 2 * n_problems, hs);
+    if (e == hipSuccess) e = hipMemsetAsync(b->norms, 0, sizeof(unsigned) * kNormUints * n_problems, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) { free_batch(b); return FASTSUM_EDEVICE; }
     *out = b;
@@ -549,7 +549,7 @@ fastsum_status fastsum_batch_exec(fastsum_batch b, const fastsum_problem_io* io,
     // every problem's first reduce task checks max |x| + max |y| <= R and
     // clears its norm slots; a direct launch that stopped early left them set
     if (b->norms_dirty &&
-        hipMemsetAsync(b->norms, 0, sizeof(unsigned) * 2 * b->nprob, st) != hipSuccess)
+        hipMemsetAsync(b->norms, 0, sizeof(unsigned) * kNormUints * b->nprob, st) != hipSuccess)
         return FASTSUM_EDEVICE;
     b->norms_dirty = false;
     if (use_graph) {

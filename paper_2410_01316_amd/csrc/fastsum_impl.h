@@ -32,41 +32,63 @@ struct GridGeom {
 // Bound of App. J, eq. radius_xy: every pair difference stays inside the
 // period of the rescaled kernel only if max ||x|| + max ||y|| <= R.  The
 // kernels that read the points (operand-tile writers, projection GEMMs)
-// record in norms[role] the largest |z / R|^2 of their rows as float bits
-// (role 0 sources, 1 targets; non-finite rows record +inf); the last kernel
-// of an exec compares sqrt(norms[0]) + sqrt(norms[same ? 0 : 1]) with lim,
-// sets *flag when the sum is larger (or not finite) and clears both slots.
+// record the largest |z / R|^2 of their rows as float bits (non-finite rows
+// record +inf) into the norm slots of a role (0 sources, 1 targets); the
+// last kernel of an exec compares sqrt(max role 0) + sqrt(max role 1) (role
+// 0 twice when the targets are the sources) with lim, sets *flag when the
+// sum is larger (or not finite) and clears every slot.  A role has
+// kNormSlots slots on separate 64-byte lines, picked by workgroup, so the
+// atomics of thousands of waves do not queue on one address.
+constexpr int kNormSlots = 64;
+constexpr int kNormStride = 16;                              // unsigned ints
+constexpr int kNormRoleUints = kNormSlots * kNormStride;
+constexpr int kNormUints = 2 * kNormRoleUints;               // both roles
+
 struct BoundCheck {
-    unsigned* norms;   // nullptr: no check in this launch
+    unsigned* norms;   // kNormUints slots; nullptr: no check in this launch
     int* flag;
     float lim;         // (1 + 1e-5) / max_p |xi_p|
-    int same;          // targets are the sources: one slot holds both
+    int same;          // targets are the sources: role 0 holds both
 };
 
-// Running max of squared row norms of a wave (every lane active) into *slot.
-__device__ inline void record_norm2(unsigned* slot, float n2) {
+// Running max of squared row norms of a wave (every lane active) into the
+// role's slot of this workgroup (role = norms of one role).
+__device__ inline void record_norm2(unsigned* role, float n2) {
     unsigned u = (n2 <= 3.4e38f) ? __float_as_uint(n2) : 0x7f800000u;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) u = max(u, (unsigned)__shfl_xor((int)u, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(slot, u);
+    if ((threadIdx.x & 63) == 0) atomicMax(role + (blockIdx.x % kNormSlots) * kNormStride, u);
 }
 
-// One thread: the comparison and the reset described at BoundCheck.
+__device__ inline unsigned wave_max_u32(unsigned u) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) u = max(u, (unsigned)__shfl_xor((int)u, o));
+    return u;
+}
+
+// One full wave (64 lanes, kNormSlots == 64): the comparison and the reset
+// described at BoundCheck.
 __device__ inline void finish_bound_check(const BoundCheck& bc) {
     if (bc.norms == nullptr) return;
-    const float a = sqrtf(__uint_as_float(bc.norms[0]));
-    const float b = bc.same ? a : sqrtf(__uint_as_float(bc.norms[1]));
-    if (!(a + b <= bc.lim)) atomicOr(bc.flag, 1);
-    bc.norms[0] = 0u;
-    bc.norms[1] = 0u;
+    const int lane = threadIdx.x & 63;
+    unsigned* s0 = bc.norms + lane * kNormStride;
+    unsigned* s1 = s0 + kNormRoleUints;
+    const unsigned ua = wave_max_u32(*s0), ub = wave_max_u32(*s1);
+    const float a = sqrtf(__uint_as_float(ua));
+    const float b = bc.same ? a : sqrtf(__uint_as_float(ub));
+    if (lane == 0 && !(a + b <= bc.lim)) atomicOr(bc.flag, 1);
+    *s0 = 0u;
+    *s1 = 0u;
 }
 
 // ---- launchers (kernels.hip); all asynchronous on `stream` ----
 
-// norms[0] = 0, norms[1] = 0 (a fill kernel, so graph capture records no memset)
+// clears the kNormUints norm slots (a fill kernel, so a graph capture
+// records no memset)
 hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream);
-// largest |x_n|^2 over the rows of X (N x d) into *slot, one wave per row
-hipError_t launch_point_norms(const float* X, int64_t N, int d, unsigned* slot,
+// largest |x_n|^2 over the rows of X (N x d) into the slots of `role`, one
+// wave per row
+hipError_t launch_point_norms(const float* X, int64_t N, int d, unsigned* role,
                               hipStream_t stream);
 
 // out[p*ld + j] = sum_i A[p*dpad + i] * X[j*d + i] for p < P, j < N, with
@@ -255,8 +277,9 @@ struct BatchProblem {
     float inv_r;           // 1 / R
     float norm2_max;       // range check of |x / R|^2
     int kb;                // ceil(d / 32)
-    // bound check (BoundCheck): largest |x / R|^2 of the sources and of the
-    // targets, compared with norm_lim by the problem's first reduce task
+    // bound check (BoundCheck): kNormUints slots of the largest |x / R|^2 of
+    // the sources and of the targets, compared with norm_lim by the
+    // problem's first reduce task
     unsigned* norms;
     float norm_lim;
 };

@@ -896,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(
     const double* __restrict__ spart, int nb, int64_t ldm, int64_t M,
     double scale, float* __restrict__ s, BoundCheck bc) {
     reduce_tile(spart, nb, ldm, M, scale, s, (int64_t)blockIdx.x * kBlock + threadIdx.x);
-    if (blockIdx.x == 0 && threadIdx.x == 0) finish_bound_check(bc);
+    if (blockIdx.x == 0 && threadIdx.x < 64) finish_bound_check(bc);
 }
 
 hipError_t launch_reduce(const double* spart, int nb, int64_t ldm, int64_t M,
@@ -1110,11 +1110,11 @@ __global__ __launch_bounds__(kBlock) void point_norms_kernel(const float* __rest
 }
 
 __global__ void clear_norms_kernel(unsigned* __restrict__ norms) {
-    if (threadIdx.x < 2) norms[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < kNormUints; i += kBlock) norms[i] = 0u;
 }
 
 hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream) {
-    hipLaunchKernelGGL(clear_norms_kernel, dim3(1), dim3(64), 0, stream, norms);
+    hipLaunchKernelGGL(clear_norms_kernel, dim3(1), dim3(kBlock), 0, stream, norms);
     return hipGetLastError();
 }
 
@@ -1933,7 +1933,7 @@ __global__ __launch_bounds__(kBlock) void batch_project_kernel(
                     ss = fmaf(v, v, ss);
                 }
             }
-            record_norm2(pr.norms + (is_y ? 1 : 0), ss);
+            record_norm2(pr.norms + (is_y ? kNormRoleUints : 0), ss);
         }
     }
 }
@@ -1997,7 +1997,7 @@ __global__ __launch_bounds__(kBlock) void batch_reduce_kernel(
         const BatchProblem& pr = probs[tk.prob];
         reduce_tile(pr.spart, pr.ngroup, pr.ldm, pr.M, 1.0 / P, pr.s,
                     (int64_t)tk.a * kBlock + threadIdx.x);
-        if (tk.a == 0 && threadIdx.x == 0)
+        if (tk.a == 0 && threadIdx.x < 64)
             finish_bound_check(BoundCheck{pr.norms, flag, pr.norm_lim, pr.same_xy});
     }
 }
@@ -2020,7 +2020,7 @@ __global__ __launch_bounds__(kBlock) void batch_split_kernel(
         for (int64_t id = t0 * 64 + threadIdx.x; id < t1 * 64; id += kBlock)
             split_points_lane(is_y ? pr.y : pr.x, n, pr.d, pr.inv_r, pr.kb, id >> 6,
                               (int)(id & 63), dst, pr.norm2_max, flag,
-                              pr.norms + (is_y ? 1 : 0));
+                              pr.norms + (is_y ? kNormRoleUints : 0));
     }
 }
 

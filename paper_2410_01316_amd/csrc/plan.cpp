@@ -450,7 +450,7 @@ struct fastsum_plan_s {
     float2* mult_d = nullptr;
     float2* tw = nullptr;
     int* flag = nullptr;
-    unsigned* norms = nullptr;     // bound check: largest |x / R|^2, |y / R|^2 of an exec
+    unsigned* norms = nullptr;     // bound check slots (kNormUints): largest |x / R|^2, |y / R|^2
     bool norms_dirty = false;      // an exec stopped before its check cleared them
     float norm_lim = 1.f;          // (1 + 1e-5) / max_p |xi_p|
     float* slice_max = nullptr;    // per-slice max |w| (fixed-point scaling)
@@ -633,7 +633,7 @@ fastsum_status fused_pass(fastsum_plan_s* pl, const float* x, const float* w, in
                                    st));
         if (y != x) {
             FS_TRY(launch_split_points(y, M, pl->d, inv_r, pl->yt, norm2_max, pl->flag,
-                                       pl->norms + 1, st));
+                                       pl->norms + kNormRoleUints, st));
             yt = pl->yt;
         }
     }
@@ -682,7 +682,7 @@ fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, i
     fastsum_status r = project(pl, x, N, pl->keys, L, pl->norms, st);
     if (r != FASTSUM_OK) return r;
     if (!same) {
-        r = project(pl, y, M, pl->keys + yoff, L, pl->norms + 1, st);
+        r = project(pl, y, M, pl->keys + yoff, L, pl->norms + kNormRoleUints, st);
         if (r != FASTSUM_OK) return r;
     }
     const double coef = -energy_cd(pl->d) / pl->r.tau;
@@ -852,8 +852,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
               dev_alloc(&pl->keys_out, PL) && dev_alloc(&pl->vals, PL) &&
               dev_alloc((char**)&pl->sort_temp, pl->sort_temp_bytes) &&
               dev_alloc(&pl->sv, (size_t)P * pl->ldm) && dev_alloc(&pl->flag, 1) &&
-              dev_alloc(&pl->norms, 2)
-        : dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->norms, 2) &&
+              dev_alloc(&pl->norms, kNormUints)
+        : dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->norms, kNormUints) &&
               (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
                                dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&
                                dev_alloc(&pl->at, (size_t)split_tiles_bytes(gtiles * kFuseDirs, pl->d) / 2)
@@ -944,7 +944,7 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     if (e == hipSuccess && pl->mult_d)
         e = hipMemcpyAsync(pl->mult_d, mult_d.data(), n * sizeof(float2), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess) e = hipMemsetAsync(pl->flag, 0, sizeof(int), hs);
-    if (e == hipSuccess) e = hipMemsetAsync(pl->norms, 0, 2 * sizeof(unsigned), hs);
+    if (e == hipSuccess) e = hipMemsetAsync(pl->norms, 0, kNormUints * sizeof(unsigned), hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) { free_plan(pl); return FASTSUM_EDEVICE; }
     *out = pl;
@@ -956,17 +956,22 @@ fastsum_status fastsum_bound(const float* x, int64_t N, const float* y, int64_t 
     if (!x || !y || !bound_out || N < 1 || M < 1 || d < 1) return FASTSUM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     unsigned* slots = nullptr;
-    if (!dev_alloc(&slots, 2)) return FASTSUM_ENOMEM;
-    unsigned h[2] = {0u, 0u};
-    hipError_t e = hipMemsetAsync(slots, 0, 2 * sizeof(unsigned), st);
+    if (!dev_alloc(&slots, kNormUints)) return FASTSUM_ENOMEM;
+    std::vector<unsigned> h(kNormUints, 0u);
+    hipError_t e = hipMemsetAsync(slots, 0, kNormUints * sizeof(unsigned), st);
     if (e == hipSuccess) e = launch_point_norms(x, N, d, slots, st);
-    if (e == hipSuccess) e = launch_point_norms(y, M, d, slots + 1, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h, slots, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = launch_point_norms(y, M, d, slots + kNormRoleUints, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), slots, kNormUints * sizeof(unsigned), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(slots);
     if (e != hipSuccess) return FASTSUM_EDEVICE;
+    // float bits of non-negative values (and +inf / NaN) order as integers
+    unsigned u[2] = {0u, 0u};
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < kNormRoleUints; k += kNormStride) u[r] = std::max(u[r], h[r * kNormRoleUints + k]);
     float n2[2];
-    std::memcpy(n2, h, sizeof(n2));
+    std::memcpy(n2, u, sizeof(n2));
     const double b = std::sqrt((double)n2[0]) + std::sqrt((double)n2[1]);
     *bound_out = b;
     return std::isfinite(b) ? FASTSUM_OK : FASTSUM_ERANGE;
@@ -1000,7 +1005,7 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
         const float* yp = pl->xproj;
         int64_t ldy = pl->ld_x;
         if (r == FASTSUM_OK && !same) {
-            r = project(pl, y, M, pl->yproj, pl->ld_y, pl->norms + 1, st);
+            r = project(pl, y, M, pl->yproj, pl->ld_y, pl->norms + kNormRoleUints, st);
             yp = pl->yproj;
             ldy = pl->ld_y;
         }

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void sorted_reduce_kernel(const float* __restr
                                                             int64_t ldm, int64_t M, double scale,
                                                             float* __restrict__ s, BoundCheck bc) {
     const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (m == 0) finish_bound_check(bc);
+    if (blockIdx.x == 0 && threadIdx.x < 64) finish_bound_check(bc);
     if (m >= M) return;
     double acc = 0.0;
     for (int p = 0; p < P; ++p) acc += (double)V[(int64_t)p * ldm + m];

@@ -279,6 +279,29 @@ def test_direct_energy_and_laplace_1d_integrals():
     assert np.abs(lap - ref).max() < 1e-8
 
 
+@pytest.mark.parametrize("kernel", ["gauss", "laplace", "energy", "matern52"])
+@pytest.mark.parametrize("d", [1, 3, 50, 784])
+def test_direct_gram_form_equals_explicit_differences(kernel, d):
+    """The Gram-identity O1 against the explicit-difference O1 (itself pinned
+    above), on image-like and Gaussian points; a target chunk smaller than M
+    exercises the blocking; coincident points (sources = targets) leave
+    r ~ 1e-8 |x| instead of 0, bounded against the terms' size."""
+    rng = np.random.default_rng(d)
+    x = np.where(rng.random((300, d)) < 0.8, 0.0, rng.random((300, d))) if d > 50 else \
+        rng.standard_normal((300, d))
+    y = rng.standard_normal((70, d)) * 0.5 + 0.2
+    w = rng.standard_normal(300)
+    sc = 0.7 * np.sqrt(d)
+    ref = O.kernel_sum_direct(kernel, x, y, w, sc)
+    got = O.kernel_sum_direct_gram(kernel, x, y, w, sc, budget=300 * 16)
+    s_abs = O.kernel_sum_direct(kernel, x, y, np.abs(w), sc)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(s_abs).max()
+    same = O.kernel_sum_direct_gram(kernel, x, x, w, sc)
+    ref_same = O.kernel_sum_direct(kernel, x, x, w, sc)
+    s_abs = O.kernel_sum_direct(kernel, x, x, np.abs(w), sc)
+    assert np.abs(same - ref_same).max() < 1e-6 * np.abs(s_abs).max()
+
+
 def test_energy_distance_of_identical_sets_is_zero():
     rng = np.random.default_rng(3)
     X = rng.random((40, 7))
