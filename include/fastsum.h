@@ -296,9 +296,10 @@ FASTSUM_API fastsum_status fastsum_debug_read(fastsum_plan plan, int32_t which,
 /*
  * Launch shape of later execs (results do not depend on it beyond FP32
  * rounding of the per-chunk partial grids):
- *   chunk_len   sources per spreading workgroup, a multiple of 4096, or 0
- *               for the plan's rule; raised if N / chunk_len would exceed
- *               the workspace sized at plan time
+ *   chunk_len   sources per spreading workgroup, a multiple of 16 (plans
+ *               that store projections round it up to a multiple of 4096),
+ *               or 0 for the plan's rule; raised if N / chunk_len would
+ *               exceed the workspace sized at plan time
  *   dir_range   directions per gathering workgroup of a fused plan, a
  *               multiple of 16, or 0 for the plan's rule
  * Errors: EINVAL (NULL plan, negative or misaligned values).

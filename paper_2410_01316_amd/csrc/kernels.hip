@@ -1194,7 +1194,7 @@ __device__ __forceinline__ void spread_fused_body(
     __syncthreads();
     int* gcol = cells + c * g.nr;                     // grid of direction p0 + c
     const WinEval<W> ev(g, win, pscale);
-    const int64_t i0 = (int64_t)chunk * chunk_len;   // multiple of kSlice
+    const int64_t i0 = (int64_t)chunk * chunk_len;   // multiple of 16
     const int len = (int)min(N - i0, chunk_len);           // <= 2^20 sources
     // the chunk's tiles and a few beyond (prefetch), within the tile array;
     // the weights of the chunk only, so sources past it spread nothing
@@ -1216,10 +1216,13 @@ __device__ __forceinline__ void spread_fused_body(
         for (int i = 0; i < 4; ++i) wv[i] = buffer_load_f32(ws, (n0 + 4 * r + i) * 4);
         load_split<KB>(xo, xs, n0 / 16, lane);
     };
-    for (int s0 = 0; s0 < len; s0 += kSlice) {
-        const int k = slice_exponent(slice_max[(i0 + s0) / kSlice]);
+    // the chunk's pieces inside fixed-point slices, [s0, s1) relative to i0
+    // (chunks need not start on a slice; every piece starts on a batch of 16)
+    for (int s0 = 0; s0 < len;) {
+        const int64_t slice = (i0 + s0) / kSlice;
+        const int k = slice_exponent(slice_max[slice]);
         const float scale = ldexpf(1.f, k);
-        const int s1 = min(len, s0 + kSlice);
+        const int s1 = (int)min((int64_t)len, (slice + 1) * kSlice - i0);
         // batches of 16 sources, wave-strided, two in flight: while one is
         // spread the other's operands load.  Each buffer is reloaded only
         // after its batch is done, so loads land in place (no copies that
@@ -1247,6 +1250,7 @@ __device__ __forceinline__ void spread_fused_body(
             }
         }
         __syncthreads();
+        s0 = s1;
     }
     // cells j = dir * nr + (cell - lo): the block's rows of partial are contiguous
     const int nvalid = min(kFuseDirs, P - p0) * g.nr;
@@ -1866,7 +1870,8 @@ hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, cons
                                const float* w, int P, GridGeom g, float pscale, int nchunk,
                                int64_t chunk_len, float* slice_max, const WindowArgs& win,
                                float* partial, hipStream_t stream) {
-    if (!fused_supported(d, g.nr) || chunk_len % kSlice != 0) return hipErrorInvalidValue;
+    if (!fused_supported(d, g.nr) || chunk_len % 16 != 0 || chunk_len <= 0)
+        return hipErrorInvalidValue;
     using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*,
                        const float*, int, const GridGeom&, float, int64_t, const float*,
                        const WindowArgs&, float*);

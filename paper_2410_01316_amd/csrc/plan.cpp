@@ -299,21 +299,29 @@ static double round_efficiency(int64_t blocks, int64_t slots) {
     return (double)blocks / (double)(rounds * slots);
 }
 
-int fused_chunks(int64_t N, int P, int64_t slots) {
-    // whole slices per chunk; at least two rounds of workgroups, then the
-    // chunk count whose rounds are fullest (fewest chunks among near ties)
+int64_t fused_chunk_len(int64_t N, int nchunk) {
+    return round_up((N + nchunk - 1) / nchunk, 16);
+}
+
+int fused_chunks(int64_t N, int P, int64_t slots, int nr) {
+    // Every workgroup spreads one chunk of sources on 16 directions, so the
+    // spread takes ceil(groups * nc / slots) rounds of N / nc sources, and
+    // the FFT convolution reads nc partial grids of P * nr cells.  The chunk
+    // count minimises the sum of the two, with a source costing 9.6 ns per
+    // resident workgroup and a partial cell 4 B at 3.2 TB/s (both measured
+    // on MI355X at N = 60000, P = 3500, W = 4); fewer chunks among near ties.
+    constexpr double kSrc = 9.6e-9, kCell = 4.0 / 3.2e12;
     const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
-    const int64_t slices = (N + kSliceLen - 1) / kSliceLen;
     const int64_t cmin = std::max<int64_t>(1, (N + kMaxChunk - 1) / kMaxChunk);
+    const int64_t cmax = std::max(cmin, std::min<int64_t>(kFusedMaxChunks, (N + 255) / 256));
     int64_t best = cmin;
-    double best_eff = -1.0;
-    const int64_t cmax = std::max(cmin, std::min<int64_t>(slices, kFusedMaxChunks));
+    double best_t = 1e300;
     for (int64_t nc = cmin; nc <= cmax; ++nc) {
-        const int64_t actual = (N + spread_chunk_len(N, (int)nc) - 1) / spread_chunk_len(N, (int)nc);
-        const int64_t blocks = groups * actual;
-        if (blocks < 2 * slots && nc < cmax) continue;
-        const double eff = round_efficiency(blocks, slots);
-        if (eff > best_eff + 0.02) { best_eff = eff; best = actual; }
+        const int64_t len = fused_chunk_len(N, (int)nc);
+        const int64_t actual = (N + len - 1) / len;
+        const int64_t rounds = (groups * actual + slots - 1) / slots;
+        const double t = (double)rounds * (double)len * kSrc + (double)actual * P * nr * kCell;
+        if (t < best_t * 0.98) { best_t = t; best = actual; }
     }
     return (int)best;
 }
@@ -538,11 +546,16 @@ fastsum_status check(hipError_t e) { return status_of(e); }
     } while (0)
 
 // Spreading chunks: the plan's rule (rule_chunks) unless fastsum_set_launch
-// gave a chunk length; never more chunks than the workspace holds.
-int chunk_plan(const fastsum_plan_s* pl, int64_t N, int rule_chunks, int64_t& chunk_len) {
-    chunk_len = pl->tune_chunk_len > 0 ? pl->tune_chunk_len : spread_chunk_len(N, rule_chunks);
-    const int64_t min_len = spread_chunk_len(N, pl->nchunk_cap);
-    chunk_len = std::max(chunk_len, min_len);
+// gave a chunk length; never more chunks than the workspace holds.  Chunks
+// of the stored-projection spread start on fixed-point slices (multiples of
+// kChunkAlign), those of the fused spread on batches of 16 sources.
+int chunk_plan(const fastsum_plan_s* pl, int64_t N, int rule_chunks, bool fused,
+               int64_t& chunk_len) {
+    auto len_of = [&](int nc) { return fused ? fused_chunk_len(N, nc) : spread_chunk_len(N, nc); };
+    chunk_len = pl->tune_chunk_len > 0
+                    ? round_up(pl->tune_chunk_len, fused ? 16 : kChunkAlign)
+                    : len_of(rule_chunks);
+    chunk_len = std::max(chunk_len, len_of(pl->nchunk_cap));
     return (int)((N + chunk_len - 1) / chunk_len);
 }
 
@@ -554,7 +567,7 @@ fastsum_status sum_pass(fastsum_plan_s* pl, const float* src_proj, int64_t ld_sr
                         float* grid_d, const BoundCheck& bc, hipStream_t st) {
     const int P = pl->P;
     int64_t chunk_len = 0;
-    const int nchunk = chunk_plan(pl, Nsrc, spread_chunks(Nsrc, P), chunk_len);
+    const int nchunk = chunk_plan(pl, Nsrc, spread_chunks(Nsrc, P), false, chunk_len);
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
         FS_TRY(launch_spread(pl->W, src_proj, ld_src, wts, Nsrc, P, pl->geom, nchunk, chunk_len,
@@ -592,7 +605,8 @@ fastsum_status fused_sum(fastsum_plan_s* pl, const uint16_t* xt, const float* w,
     const int P = pl->P;
     const float pscale = (float)(pl->r.tau * pl->r.p.R);
     int64_t chunk_len = 0;
-    const int nchunk = chunk_plan(pl, N, fused_chunks(N, P, pl->spread_slots), chunk_len);
+    const int nchunk = chunk_plan(pl, N, fused_chunks(N, P, pl->spread_slots, pl->geom.nr), true,
+                                  chunk_len);
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SPREAD, st);
         FS_TRY(launch_spread_fused(pl->W, xt, N, pl->d, pl->at, w, P, pl->geom, pscale, nchunk,
@@ -1178,7 +1192,7 @@ fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t iters, double 
 }
 
 fastsum_status fastsum_set_launch(fastsum_plan pl, int64_t chunk_len, int32_t dir_range) {
-    if (!pl || chunk_len < 0 || chunk_len % kChunkAlign != 0 || chunk_len > kMaxChunk ||
+    if (!pl || chunk_len < 0 || chunk_len % 16 != 0 || chunk_len > kMaxChunk ||
         dir_range < 0 || dir_range % kFuseDirs != 0)
         return FASTSUM_EINVAL;
     pl->tune_chunk_len = chunk_len;

@@ -84,8 +84,12 @@ def test_fused_scale_workload_sample():
     assert rel_l2(s_f, _o3(cfg)) < 1e-4         # mixture data: little cancellation
 
 
-@pytest.mark.parametrize("chunk_len,dir_range", [(4096, 16), (8192, 32), (4096 * 3, 48), (0, 0)])
+@pytest.mark.parametrize("chunk_len,dir_range", [(4096, 16), (8192, 32), (4096 * 3, 48), (0, 0),
+                                               (3008, 16), (5008, 32)])
 def test_fused_launch_shapes(chunk_len, dir_range):
+    """Chunk lengths that are not whole fixed-point slices (3008, 5008 = 16 k)
+    put slice boundaries inside chunks: each piece is scaled by its own
+    slice's exponent."""
     cfg = _ragged(20, 20000, 3000, 100, seed=9, n_ft=256)
     x, y, w = to_dev(cfg["x"], cfg["y"], cfg["w"])
     plan = gpu_plan(cfg)
@@ -153,3 +157,25 @@ def test_fused_adjoint_equals_stored(d, N, M, P, same):
     ey, ew, ex = [rel_l2(a, b) for a, b in zip(res[False], res[True])]
     print(f"d={d} N={N} M={M} P={P} same={same} grad_y {ey:.2e} grad_w {ew:.2e} grad_x {ex:.2e}")
     assert ey < 2e-5 and ew < 2e-5 and ex < 2e-5
+
+
+@pytest.mark.parametrize("chunk_len", [0, 3008])
+def test_weights_spanning_decades_within_slices(chunk_len):
+    """Spreading rounds each term to 2^-19 of its slice's largest |w|: weights
+    log-uniform over six decades, in random order inside every 4096-source
+    slice (signed), against the exact Fourier sum (err_scale) and the stored
+    path; with chunk boundaries inside slices too."""
+    rng = np.random.default_rng(23)
+    cfg = _ragged(10, 12000, 2500, 48, seed=23, n_ft=256)
+    w = np.exp(rng.uniform(np.log(1e-4), np.log(1e2), 12000)) * rng.choice([-1.0, 1.0], 12000)
+    cfg["w"] = w
+    x, y, wd = to_dev(cfg["x"], cfg["y"], w)
+    fused = gpu_plan(cfg)
+    fused.set_launch(chunk_len, 0)
+    s_f = fused(x, wd, y).cpu().numpy()
+    stored = gpu_plan(cfg, materialize=True)
+    s_m = stored(x, wd, y).cpu().numpy()
+    em = err_scale(s_f, s_m, _sabs(cfg))
+    e3 = _err3(cfg, s_f)
+    print("decades: fused-stored %.2e fused-O3 %.2e (err_scale)" % (em, e3))
+    assert em < 1e-6 and e3 < 2e-5
