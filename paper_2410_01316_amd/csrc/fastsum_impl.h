@@ -215,15 +215,24 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
 // in keys_in[p L + i], i < N, and (same_xy == 0) of the M targets at
 // i = yoff + m; entries in [N, yoff) are padding of any value.  Each row's
 // first yoff + M (same_xy: N) entries are sorted (keys_out, vals_out =
-// original positions p L + i) and V[p ldm + m] = coef * sum_n w_n |x~_n - y~_m|
-// is written for every target (FP32; launch_sorted_reduce takes the FP64
-// mean s[m] = scale * sum_p V[p ldm + m]).  P * L < 2^32.  temp holds
-// sorted_energy_temp_bytes(L, P) bytes.
+// original positions p L + i) and each target's per-direction sum
+// coef * sum_n w_n |x~_n - y~_m| is computed in FP64 and staged in FP32 by
+// 4096-target bucket (stv, with the target's offset in its bucket in sti,
+// both P x ldm).  P * L < 2^32.  temp holds sorted_energy_temp_bytes(L, P)
+// bytes.  launch_sorted_bucket_reduce then takes the FP64 mean over the
+// directions, s[m] = scale * sum_p (per-direction sum), over at most
+// kSortMaxRanges direction ranges summed into part (kSortMaxRanges x ldm
+// doubles), and finishes with the bound check bc.
+constexpr int kSortMaxRanges = 48;
 size_t sorted_energy_temp_bytes(int64_t L, int P);
 hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,
                                 void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
-                                int M, int same_xy, const float* w, double coef, float* V,
-                                int64_t ldm, hipStream_t stream);
+                                int M, int same_xy, const float* w, double coef, float* stv,
+                                unsigned short* sti, int64_t ldm, hipStream_t stream);
+hipError_t launch_sorted_bucket_reduce(const float* stv, const unsigned short* sti, int P,
+                                       int64_t ldm, int M, double* part, double scale, float* s,
+                                       const BoundCheck& bc, hipStream_t stream);
+// s[m] = scale * sum_p V[p ldm + m] (FP64, directions in order), then bc
 hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
                                 float* s, const BoundCheck& bc, hipStream_t stream);
 // Adjoint pieces per direction from an ascending and a descending sort of

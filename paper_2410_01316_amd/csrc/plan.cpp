@@ -468,7 +468,8 @@ struct fastsum_plan_s {
     unsigned int* vals = nullptr;
     void* sort_temp = nullptr;
     size_t sort_temp_bytes = 0;
-    float* sv = nullptr;           // per-direction exact sums, P x ldm
+    float* sv = nullptr;           // per-direction exact sums, P x ldm (bucketed, see sti)
+    unsigned short* sti = nullptr; // each staged sum's target offset in its 4096-target bucket
     float* sty = nullptr;          // sorted adjoint: d/dy~ and d/dx~ per direction, P x ldm
     float* stx = nullptr;
     int64_t sort_L = 0, sort_yoff = 0;
@@ -496,7 +497,8 @@ void free_plan(fastsum_plan_s* p) {
     void* bufs[] = {p->A, p->A64, p->at, p->xt, p->yt, p->gdt, p->gpt, p->xproj, p->yproj, p->partial, p->grid, p->grid_d,
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout, p->keys,
-                    p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx, p->norms};
+                    p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx, p->norms,
+                    p->sti};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -704,12 +706,13 @@ fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, i
         PhaseTimer t(pl, FASTSUM_PHASE_SORT, st);
         FS_TRY(launch_sorted_energy(pl->keys, pl->keys_out, pl->vals, pl->sort_temp,
                                     pl->sort_temp_bytes, L, pl->P, (int)N, (int)yoff, (int)M,
-                                    same ? 1 : 0, w, coef, pl->sv, pl->ldm, st));
+                                    same ? 1 : 0, w, coef, pl->sv, pl->sti, pl->ldm, st));
     }
     pl->last_nchunk = 0;
     pl->last_ngroup = pl->P;
     PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-    FS_TRY(launch_sorted_reduce(pl->sv, pl->P, pl->ldm, M, 1.0 / pl->P, out, bc, st));
+    FS_TRY(launch_sorted_bucket_reduce(pl->sv, pl->sti, pl->P, pl->ldm, (int)M, pl->spart,
+                                       1.0 / pl->P, out, bc, st));
     return FASTSUM_OK;
 }
 
@@ -865,8 +868,9 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         ? dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->keys, PL) &&
               dev_alloc(&pl->keys_out, PL) && dev_alloc(&pl->vals, PL) &&
               dev_alloc((char**)&pl->sort_temp, pl->sort_temp_bytes) &&
-              dev_alloc(&pl->sv, (size_t)P * pl->ldm) && dev_alloc(&pl->flag, 1) &&
-              dev_alloc(&pl->norms, kNormUints)
+              dev_alloc(&pl->sv, (size_t)P * pl->ldm) && dev_alloc(&pl->sti, (size_t)P * pl->ldm) &&
+              dev_alloc(&pl->spart, (size_t)kSortMaxRanges * pl->ldm) &&
+              dev_alloc(&pl->flag, 1) && dev_alloc(&pl->norms, kNormUints)
         : dev_alloc(&pl->A, (size_t)P * pl->dpad) && dev_alloc(&pl->norms, kNormUints) &&
               (pl->fused ? dev_alloc(&pl->xt, (size_t)split_tiles_bytes(n_max, pl->d) / 2) &&
                                dev_alloc(&pl->yt, (size_t)split_tiles_bytes(m_max, pl->d) / 2) &&

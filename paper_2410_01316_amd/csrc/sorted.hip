@@ -11,6 +11,8 @@
 // grid: the only approximation left is the slicing.
 #include "fastsum_impl.h"
 
+#include <algorithm>
+
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
 #include <rocprim/iterator/transform_iterator.hpp>
@@ -23,6 +25,11 @@ constexpr int kSortBlock = 512;                // 8 waves per direction
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kSortItems = 16;                 // consecutive sorted keys per thread and chunk
 constexpr int kSortChunk = kSortBlock * kSortItems;
+constexpr int kEnergyItems = 8;                // the forward scan: fewer registers, more workgroups
+constexpr int kEnergyChunk = kSortBlock * kEnergyItems;
+constexpr int kBucketShift = 12;               // targets per output bucket: 4096
+constexpr int kBucket = 1 << kBucketShift;
+constexpr int kBucketThreads = 256;
 
 // offset of row p: p * L + add
 struct RowOffset {
@@ -56,16 +63,59 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// This thread's share of W = sum_n w_n and S = sum_n w_n x~_n over a row of
+// N sources: 16-byte loads, two pairs in flight, then the tail.
+__device__ __forceinline__ void row_totals(const float* __restrict__ xr,
+                                           const float* __restrict__ w, int N, double& A,
+                                           double& B) {
+    constexpr int kU = 2;
+    const int n4 = N / 4;
+    const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xr);
+    const float4* __restrict__ w4 = reinterpret_cast<const float4*>(w);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(xr) | reinterpret_cast<uintptr_t>(w)) & 15) == 0;
+    int n0 = 0;
+    if (aligned) {
+        int q = threadIdx.x;
+        for (; q + (kU - 1) * kSortBlock < n4; q += kU * kSortBlock) {
+            float4 xv[kU], wq[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                xv[u] = x4[q + u * kSortBlock];
+                wq[u] = w4[q + u * kSortBlock];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                A += (double)wq[u].x + (double)wq[u].y + (double)wq[u].z + (double)wq[u].w;
+                B += (double)wq[u].x * (double)xv[u].x + (double)wq[u].y * (double)xv[u].y +
+                     (double)wq[u].z * (double)xv[u].z + (double)wq[u].w * (double)xv[u].w;
+            }
+        }
+        for (; q < n4; q += kSortBlock) {
+            const float4 xv = x4[q], wq = w4[q];
+            A += (double)wq.x + (double)wq.y + (double)wq.z + (double)wq.w;
+            B += (double)wq.x * (double)xv.x + (double)wq.y * (double)xv.y +
+                 (double)wq.z * (double)xv.z + (double)wq.w * (double)xv.w;
+        }
+        n0 = 4 * n4;
+    }
+    for (int n = n0 + threadIdx.x; n < N; n += kSortBlock) {
+        const double wn = w[n];
+        A += wn;
+        B += wn * (double)xr[n];
+    }
+}
+
 // Keys and row positions of the kSortItems sorted entries from i0 (16-byte
 // loads where the whole group lies in the row; ii = -1 past its end or for
 // a position outside the row).
+template <int ITEMS>
 __device__ __forceinline__ void load_sorted(const float* __restrict__ kr,
                                             const unsigned int* __restrict__ vr, int64_t base,
-                                            int i0, int n_tot, float (&kk)[kSortItems],
-                                            int (&ii)[kSortItems]) {
-    if (i0 + kSortItems <= n_tot) {
+                                            int i0, int n_tot, float (&kk)[ITEMS],
+                                            int (&ii)[ITEMS]) {
+    if (i0 + ITEMS <= n_tot) {
 #pragma unroll
-        for (int q = 0; q < kSortItems / 4; ++q) {
+        for (int q = 0; q < ITEMS / 4; ++q) {
             const float4 kq = *reinterpret_cast<const float4*>(kr + i0 + 4 * q);
             const uint4 vq = *reinterpret_cast<const uint4*>(vr + i0 + 4 * q);
             kk[4 * q] = kq.x; kk[4 * q + 1] = kq.y; kk[4 * q + 2] = kq.z; kk[4 * q + 3] = kq.w;
@@ -76,14 +126,14 @@ __device__ __forceinline__ void load_sorted(const float* __restrict__ kr,
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
+        for (int j = 0; j < ITEMS; ++j) {
             const int i = i0 + j;
             kk[j] = i < n_tot ? kr[i] : 0.f;
             ii[j] = i < n_tot ? (int)((int64_t)vr[i] - base) : -1;
         }
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j)
+    for (int j = 0; j < ITEMS; ++j)
         if (ii[j] < 0 || ii[j] >= n_tot) ii[j] = -1;
 }
 
@@ -97,59 +147,68 @@ __device__ __forceinline__ void load_sorted(const float* __restrict__ kr,
 // the mean over the directions is taken in FP64 by sorted_reduce_kernel).
 // The writes are scattered (targets in sorted order); the workgroups of
 // different directions run spread over the whole device, which measured
-// faster than grouping the chunks of a few directions per XCD.
-__global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
+// The results are not written at their targets' positions (targets arrive
+// in sorted order, and scattered 4-byte stores cost whole memory lines):
+// target m belongs to bucket m >> kBucketShift, and each bucket of a row
+// has a region of exactly its size (every target occurs once per
+// direction).  Per chunk, LDS counters give each target a slot after the
+// bucket's earlier entries, and the value goes to
+// stv[p ldm + (bucket << kBucketShift) + slot], the target's offset in the
+// bucket to sti at the same place: runs of consecutive stores.  The slot
+// order follows the LDS atomics; sorted_bucket_reduce_kernel places every
+// value by its offset, so the results do not depend on it.
+// at most 128 VGPRs: two workgroups per CU
+__global__ __launch_bounds__(kSortBlock) __attribute__((amdgpu_waves_per_eu(4))) void
+sorted_energy_kernel(
     const float* __restrict__ keys_in, const float* __restrict__ keys,
     const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M, int same_xy,
-    const float* __restrict__ w, double coef, float* __restrict__ V, int64_t ldm) {
+    const float* __restrict__ w, double coef, float* __restrict__ stv,
+    unsigned short* __restrict__ sti, int64_t ldm) {
     __shared__ double sa[2][kSortWaves], sb[2][kSortWaves];
+    __shared__ float cval[kEnergyChunk];     // the chunk's values, ordered by bucket
+    __shared__ int ctgt[kEnergyChunk];       // and their targets
+    // [0, nb) this chunk's counts, [nb, 2 nb) the runs of the earlier chunks,
+    // [2 nb, 3 nb] this chunk's bucket offsets
+    extern __shared__ unsigned int bcnt[];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_tot = same_xy ? N : yoff + M;
+    const int nb = (M + kBucket - 1) >> kBucketShift;
+    unsigned int* coff = bcnt + 2 * nb;
     const int64_t base = (int64_t)p * L;
     const float* __restrict__ kr = keys + base;
     const unsigned int* __restrict__ vr = vals + base;
-    float* __restrict__ vrow = V + (int64_t)p * ldm;
+    float* __restrict__ vrow = stv + (int64_t)p * ldm;
+    unsigned short* __restrict__ irow = sti + (int64_t)p * ldm;
+    for (int b = tid; b < 2 * nb; b += kSortBlock) bcnt[b] = 0u;
     // totals W = sum w_n and S = sum w_n x~_n over the unsorted sources
     double A = 0.0, B = 0.0;
-    {
-        const float* __restrict__ xr = keys_in + base;
-        for (int n = tid; n < N; n += kSortBlock) {
-            const double wn = w[n];
-            A += wn;
-            B += wn * (double)xr[n];
-        }
-        A = wave_sum(A);
-        B = wave_sum(B);
-        if (lane == 0) { sa[1][wave] = A; sb[1][wave] = B; }
-        __syncthreads();
-        A = B = 0.0;
+    row_totals(keys_in + base, w, N, A, B);
+    A = wave_sum(A);
+    B = wave_sum(B);
+    if (lane == 0) { sa[1][wave] = A; sb[1][wave] = B; }
+    __syncthreads();
+    A = B = 0.0;
 #pragma unroll
-        for (int k = 0; k < kSortWaves; ++k) { A += sa[1][k]; B += sb[1][k]; }
-    }
+    for (int k = 0; k < kSortWaves; ++k) { A += sa[1][k]; B += sb[1][k]; }
     // exclusive prefix sums W_<, S_< over the sources in sorted order, chunk
-    // by chunk: each thread holds kSortItems consecutive keys, waves scan by
+    // by chunk: each thread holds kEnergyItems consecutive keys, waves scan by
     // shuffles, the wave totals go through LDS (two buffers: one barrier per
     // chunk suffices)
     double ca = 0.0, cb = 0.0;                        // sums of the earlier chunks
     int par = 0;
-    for (int c0 = 0; c0 < n_tot; c0 += kSortChunk, par ^= 1) {
-        const int i0 = c0 + tid * kSortItems;
-        float kk[kSortItems];
-        int ii[kSortItems];
-        load_sorted(kr, vr, base, i0, n_tot, kk, ii);
-        double la[kSortItems], lb[kSortItems];
+    for (int c0 = 0; c0 < n_tot; c0 += kEnergyChunk, par ^= 1) {
+        const int i0 = c0 + tid * kEnergyItems;
+        float kk[kEnergyItems];
+        int ii[kEnergyItems];
+        load_sorted<kEnergyItems>(kr, vr, base, i0, n_tot, kk, ii);
+        float wv[kEnergyItems];                         // source weights (0 for targets, padding)
         double ta = 0.0, tb = 0.0;
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
+        for (int j = 0; j < kEnergyItems; ++j) {
             if (ii[j] < 0 || ii[j] >= n_tot) ii[j] = -1;        // not a position of this row
-            la[j] = 0.0;
-            lb[j] = 0.0;
-            if (ii[j] >= 0 && ii[j] < N) {
-                la[j] = w[ii[j]];
-                lb[j] = la[j] * (double)kk[j];
-            }
-            ta += la[j];
-            tb += lb[j];
+            wv[j] = (ii[j] >= 0 && ii[j] < N) ? w[ii[j]] : 0.f;
+            ta += (double)wv[j];
+            tb += (double)wv[j] * (double)kk[j];
         }
         const double ia = wave_incl_scan(ta), ib = wave_incl_scan(tb);
         if (lane == 63) { sa[par][wave] = ia; sb[par][wave] = ib; }
@@ -164,17 +223,117 @@ __global__ __launch_bounds__(kSortBlock) void sorted_energy_kernel(
         }
         pa += ia - ta;                                  // exclusive prefix of item 0
         pb += ib - tb;
+        // slots first (the targets' values follow once the chunk's counts
+        // are complete, from the same running prefix sums)
+        int slot[kEnergyItems];
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
+        for (int j = 0; j < kEnergyItems; ++j) {
             const bool tgt = same_xy ? (ii[j] >= 0 && ii[j] < N) : ii[j] >= yoff;   // < n_tot
+            slot[j] = -1;
             if (tgt) {
                 const int m = same_xy ? ii[j] : ii[j] - yoff;
-                const double y = kk[j];
-                vrow[m] = (float)(coef * (y * (2.0 * pa - A) - (2.0 * pb - B)));
+                slot[j] = (int)atomicAdd(&bcnt[m >> kBucketShift], 1u);
             }
-            pa += la[j];
-            pb += lb[j];
         }
+        __syncthreads();                              // this chunk's counts are complete
+        // the chunk's bucket offsets: exclusive scan of the counts by wave 0,
+        // 64 buckets per step
+        if (wave == 0) {
+            unsigned int run = 0u;
+            for (int b0 = 0; b0 < nb; b0 += 64) {
+                const unsigned int c = (b0 + lane < nb) ? bcnt[b0 + lane] : 0u;
+                unsigned int incl = c;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const unsigned int t = (unsigned int)__shfl_up((int)incl, o, 64);
+                    if (lane >= o) incl += t;
+                }
+                if (b0 + lane < nb) coff[b0 + lane] = run + incl - c;
+                run += (unsigned int)__shfl((int)incl, 63, 64);
+            }
+            if (lane == 0) coff[nb] = run;
+        }
+        __syncthreads();
+        // values in LDS by bucket (chunk offset + slot), with their targets
+#pragma unroll
+        for (int j = 0; j < kEnergyItems; ++j) {
+            if (slot[j] >= 0) {
+                const int m = same_xy ? ii[j] : ii[j] - yoff;
+                const int k = (int)coff[m >> kBucketShift] + slot[j];
+                const double y = kk[j];
+                cval[k] = (float)(coef * (y * (2.0 * pa - A) - (2.0 * pb - B)));
+                ctgt[k] = m;
+            }
+            pa += (double)wv[j];
+            pb += (double)wv[j] * (double)kk[j];
+        }
+        __syncthreads();
+        // consecutive LDS entries of a bucket go to consecutive positions of
+        // its region: the stores of a wave cover whole runs
+        const int nchunk = (int)coff[nb];
+        for (int k = tid; k < nchunk; k += kSortBlock) {
+            const int m = ctgt[k];
+            const int bk = m >> kBucketShift;
+            const int64_t pos = ((int64_t)bk << kBucketShift) + bcnt[nb + bk] + (k - (int)coff[bk]);
+            vrow[pos] = cval[k];
+            irow[pos] = (unsigned short)(m & (kBucket - 1));
+        }
+        __syncthreads();                              // every entry has been stored
+        for (int bk = tid; bk < nb; bk += kSortBlock) {
+            bcnt[nb + bk] += bcnt[bk];
+            bcnt[bk] = 0u;
+        }
+        // the next chunk's atomics follow its scan barrier
+    }
+}
+
+// Mean over directions of the bucketed per-direction sums: workgroup
+// (bucket b, direction range r) places each direction's values of the
+// bucket into LDS by their target offsets, then adds them into FP64
+// accumulators in direction order; part[r ldm + m] receives the range's sum.
+__global__ __launch_bounds__(kBucketThreads) void sorted_bucket_reduce_kernel(
+    const float* __restrict__ stv, const unsigned short* __restrict__ sti, int P, int prange,
+    int64_t ldm, int M, double* __restrict__ part) {
+    __shared__ float vals_lds[kBucket];
+    constexpr int kPer = kBucket / kBucketThreads;
+    const int tid = threadIdx.x, bk = blockIdx.x;
+    const int64_t m0 = (int64_t)bk << kBucketShift;
+    const int size = (int)min((int64_t)kBucket, (int64_t)M - m0);
+    const int p0 = blockIdx.y * prange, p1 = min(P, p0 + prange);
+    double acc[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) acc[k] = 0.0;
+    // direction p's entries in registers while p - 1's are summed
+    float v[kPer];
+    unsigned short ix[kPer];
+    auto load = [&](int p) {
+        const int64_t base = (int64_t)p * ldm + m0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = tid + k * kBucketThreads;
+            const bool in = e < size && p < p1;
+            v[k] = in ? stv[base + e] : 0.f;
+            ix[k] = in ? sti[base + e] : (unsigned short)0;
+        }
+    };
+    load(p0);
+    for (int p = p0; p < p1; ++p) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (tid + k * kBucketThreads < size) vals_lds[ix[k]] = v[k];
+        __syncthreads();
+        load(p + 1);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = tid + k * kBucketThreads;
+            if (e < size) acc[k] += (double)vals_lds[e];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int e = tid + k * kBucketThreads;
+        if (e < size) part[(int64_t)blockIdx.y * ldm + m0 + e] = acc[k];
     }
 }
 
@@ -252,7 +411,7 @@ __global__ __launch_bounds__(kSortBlock) void sorted_grad_kernel(
         const int i0 = c0 + tid * kSortItems;
         float kk[kSortItems];
         int ii[kSortItems];
-        load_sorted(kr, vr, base, i0, n_tot, kk, ii);
+        load_sorted<kSortItems>(kr, vr, base, i0, n_tot, kk, ii);
         // x entries ii < N, y entries ii >= yoff, padding otherwise
         double lw[kSortItems], lv[kSortItems], lsv[kSortItems];
         double tw = 0.0, tv = 0.0, tsv = 0.0;
@@ -369,10 +528,17 @@ hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned in
     return hipSuccess;
 }
 
+int sorted_reduce_ranges(int64_t M, int P) {
+    // about 2048 workgroups (8 per CU) over the buckets and direction ranges
+    const int64_t nb = (M + kBucket - 1) / kBucket;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSortMaxRanges, (int64_t)P,
+                                                         (2048 + nb - 1) / nb}));
+}
+
 hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,
                                 void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
-                                int M, int same_xy, const float* w, double coef, float* V,
-                                int64_t ldm, hipStream_t stream) {
+                                int M, int same_xy, const float* w, double coef, float* stv,
+                                unsigned short* sti, int64_t ldm, hipStream_t stream) {
     const int n_tot = same_xy ? N : yoff + M;
     if (N < 1 || M < 1 || (!same_xy && yoff < N) || n_tot > L || M > ldm ||
         (int64_t)P * L >= ((int64_t)1 << 32))
@@ -380,9 +546,24 @@ hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned 
     size_t bytes = temp_bytes;
     hipError_t e = run_sort(temp, bytes, keys_in, keys_out, vals_out, L, P, n_tot, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sorted_energy_kernel, dim3((unsigned)P), dim3(kSortBlock), 0, stream,
-                       keys_in, keys_out, vals_out, L, N, yoff, M, same_xy, w, coef, V, ldm);
+    const int nb = (M + kBucket - 1) >> kBucketShift;
+    hipLaunchKernelGGL(sorted_energy_kernel, dim3((unsigned)P), dim3(kSortBlock),
+                       (size_t)(3 * nb + 1) * sizeof(unsigned int), stream, keys_in, keys_out, vals_out,
+                       L, N, yoff, M, same_xy, w, coef, stv, sti, ldm);
     return hipGetLastError();
+}
+
+hipError_t launch_sorted_bucket_reduce(const float* stv, const unsigned short* sti, int P,
+                                       int64_t ldm, int M, double* part, double scale, float* s,
+                                       const BoundCheck& bc, hipStream_t stream) {
+    const int nb = (M + kBucket - 1) >> kBucketShift;
+    const int nr = sorted_reduce_ranges(M, P);
+    const int prange = (P + nr - 1) / nr;
+    hipLaunchKernelGGL(sorted_bucket_reduce_kernel, dim3((unsigned)nb, (unsigned)((P + prange - 1) / prange)),
+                       dim3(kBucketThreads), 0, stream, stv, sti, P, prange, ldm, M, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce(part, (P + prange - 1) / prange, ldm, M, scale, s, bc, stream);
 }
 
 }  // namespace fastsum

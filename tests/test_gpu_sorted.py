@@ -85,11 +85,12 @@ def test_sorted_ties_and_smaller_calls():
     of the second."""
     big = _points(3000, 2500, 4, seed=3, ties=40)
     big["xi"] = directions("distance", 4, 48, 6)
-    plan = _plan(big)
-    s_big = _gpu(plan, big)
     small = _points(1100, 700, 4, seed=4, ties=25)
     small["xi"] = big["xi"]
-    small["R"] = big["R"]
+    # one plan bound R >= max|x| + max|y| for both point sets
+    big["R"] = small["R"] = max(big["R"], small["R"])
+    plan = _plan(big)
+    s_big = _gpu(plan, big)
     s_small = _gpu(plan, small)
     plan.close()
     for s, cfg in ((s_big, big), (s_small, small)):
