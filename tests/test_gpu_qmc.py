@@ -81,3 +81,25 @@ def test_register_widths():
         assert abs(e_gpu - e_ref) < 1e-6 * e_ref, d
         g = _run(_start(d, d, d + 1), 1500, 0.05)
         assert np.abs(g @ g.T - np.eye(d)).max() < 2e-3, d
+
+
+@pytest.mark.parametrize("d", [33, 48])
+def test_one_step_elementwise_48_wide_rows(d):
+    """One step at d = 33 and 48 (the 48-wide register rows), element by
+    element.  The first Adam step moves every coordinate by +-lr (m/sqrt(v)
+    is the sign of the gradient), so a coordinate whose tangent gradient is
+    at FP32 noise level may flip; the rows compared are those whose every
+    coordinate's gradient is clear of that level, and they must agree to
+    FP32 rounding."""
+    P = 130
+    x0 = _start(P, d, 1000 + d)
+    lr = 0.05 * P ** (-1.0 / (d - 1))
+    g = O.distance_energy_grad(x0)
+    g -= (g * x0).sum(1, keepdims=True) * x0
+    stable = np.abs(g).min(axis=1) > 1e-3 * np.abs(g).max()
+    assert stable.sum() >= P // 2
+    g1 = _run(x0, 1, lr)
+    o1 = O.projected_adam(x0, 1, lr)
+    err = np.abs(g1 - o1)[stable].max()
+    print("d=%d: one step on %d of %d rows, max |gpu - oracle| %.1e" % (d, stable.sum(), P, err))
+    assert err < 2e-6
