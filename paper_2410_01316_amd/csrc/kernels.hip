@@ -13,15 +13,13 @@
 // blockIdx to one tile; the batched kernels are persistent and walk a task
 // list of tiles drawn from many problems (one launch per phase).
 #include "fastsum_impl.h"
+#include "device_common.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 namespace fastsum {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
 // window weights
@@ -113,15 +111,6 @@ struct ProjSmemF32 {
     float As[kProjBM][kProjKC + 1];
     float Xs[kProjBN][kProjKC + 1];
 };
-
-typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
-typedef float f32x2v __attribute__((ext_vector_type(2)));
-
-// Two floats to BF16, round to nearest even (one v_cvt_pk_bf16_f32 on
-// gfx950), packed low half first.
-__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
-    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2v){a, b}, bf16x2v));
-}
 
 // The MFMAs compute C^T: acc[bi][bj] holds rows n = wave*32 + bj*16 +
 // 4*(lane/16) + r (r = 0..3) of direction column p = bi*16 + lane%16, i.e.
@@ -218,20 +207,6 @@ __device__ __forceinline__ void project_tile_f32(
     }
     project_store(acc, p0, n0, P, N, out, ld, bound, flag);
 }
-
-// XCD-aware tile order for the stored projection grids: workgroups are
-// dispatched round-robin over the 8 XCDs, so block b runs on XCD b % 8.
-// Point tile pt and all direction tiles of it go to one XCD (its L2 keeps the
-// point tile while every direction tile reads it): b = 8 (g * ndt + dt) + x
-// with pt = 8 g + x.  Returns false for the padding blocks.
-__device__ __forceinline__ bool proj_tile_of_block(int b, int ndt, int npt, int& dt, int& pt) {
-    const int x = b & 7, j = b >> 3;
-    dt = j % ndt;
-    pt = (j / ndt) * 8 + x;
-    return pt < npt;
-}
-
-unsigned proj_grid_blocks(int ndt, int npt) { return (unsigned)(8 * ndt * ((npt + 7) / 8)); }
 
 // d <= 64: the block keeps its 128-point X tile in LDS for its whole life
 // and walks a range of 64-direction tiles, so X is read from memory once per
@@ -1015,26 +990,6 @@ constexpr int kGatherNB = 8;                               // 16-target batches 
 constexpr int kGatherTargets = kGatherWaves * kGatherNB * 16;
 constexpr int kDmaBytes = 64 * 16;                         // one wave's 16-byte LDS-direct loads
 
-typedef __attribute__((address_space(3))) void lds_void;
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// Raw buffer resource over [p, p + bytes) (bytes < 2^31): loads outside it
-// return zero without touching memory (checked per dword).  Third
-// descriptor word: 32-bit data format, no swizzle (gfx9).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
-                                             0x00020000);
-}
-
-__device__ __forceinline__ float buffer_load_f32(__amdgpu_buffer_rsrc_t rs, int byte_off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0));
-}
-
-__device__ __forceinline__ h8 buffer_load_h8(__amdgpu_buffer_rsrc_t rs, int byte_off) {
-    return __builtin_bit_cast(h8, __builtin_amdgcn_raw_buffer_load_b128(rs, byte_off, 0, 0));
-}
-
 // split_points_kernel: one thread per (tile, lane), all k-blocks; rows >= N
 // and columns >= d are zero.  Also the range check of the fused path: a
 // row with |z * scale|^2 > norm2_max sets *flag (z * scale is x / R, and
@@ -1549,163 +1504,6 @@ __global__ __launch_bounds__(kBlock) void grad_reduce_kernel(
     grad_y[e] = coef * v[m] * s;
 }
 
-// ---------------------------------------------------------------------------
-// stored projections from operand tiles (any d): out[p * ld + n] = pscale *
-// sum_k A[p][k] X[n][k], both operands in the tile layout above with PARTS
-// parts per k-block (2: f16 hi / lo, three v_mfma_f32_16x16x32_f16 per tile
-// pair; 1: BF16, one v_mfma_f32_16x16x32_bf16).  A workgroup of 8 waves owns
-// 8 direction tiles x 16 point tiles (128 x 256); wave w multiplies direction
-// tiles 4 (w & 1) .. +3 with point tiles 4 (w >> 1) .. +3.  The k-blocks
-// stream through three LDS buffers filled by LDS-direct loads (one 1 KB tile
-// part per wave instruction), two k-blocks ahead of the MFMAs, so a wave
-// waits only for the oldest of its two stages in flight.  Per k-block a
-// workgroup moves 24 KB per part and issues 128 (x3) MFMAs.
-// ---------------------------------------------------------------------------
-
-constexpr int kGemmBlock = 512;
-constexpr int kGemmWaves = kGemmBlock / 64;
-constexpr int kGemmDT = 8;                 // direction tiles per workgroup
-constexpr int kGemmPT = 16;                // point tiles per workgroup
-
-template <int PARTS>
-__global__ __launch_bounds__(kGemmBlock) void project_tiles_kernel(
-    const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At, int P, int KB,
-    float pscale, float* __restrict__ out, int64_t ld, float bound, int* __restrict__ flag,
-    int ndb, int npb) {
-    extern __shared__ __attribute__((aligned(16))) char gsm[];
-    constexpr int kPieces = (kGemmDT + kGemmPT) * PARTS;     // 1 KB pieces per k-block
-    constexpr int kBufBytes = kPieces * kSplitTileBytes;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int db, pb;
-    if (!proj_tile_of_block(blockIdx.x, ndb, npb, db, pb)) return;
-    const int64_t dt0 = (int64_t)db * kGemmDT, pt0 = (int64_t)pb * kGemmPT;
-    const int64_t ndtiles = (P + 15) / 16, nptiles = (N + 15) / 16;
-    // tiles past the ends re-read the last tile (their results are not stored)
-    auto stage = [&](int kb, char* buf) {
-        for (int piece = wave; piece < kPieces; piece += kGemmWaves) {
-            const int t = piece / PARTS, q = piece - t * PARTS;
-            const bool is_dir = t < kGemmDT;
-            const int64_t tile = is_dir ? min(dt0 + t, ndtiles - 1) : min(pt0 + t - kGemmDT, nptiles - 1);
-            const char* src = reinterpret_cast<const char*>(is_dir ? At : Xt) +
-                              ((tile * KB + kb) * PARTS + q) * kSplitTileBytes + lane * 16;
-            __builtin_amdgcn_global_load_lds(src, (lds_void*)(buf + piece * kSplitTileBytes), 16, 0, 0);
-        }
-    };
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int wd = 4 * (wave & 1), wp = kGemmDT + 4 * (wave >> 1);   // first tiles of this wave
-    auto compute = [&](const char* buf) {
-        h8 dop[4][PARTS], xop[4][PARTS];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < PARTS; ++q) {
-                dop[i][q] = *reinterpret_cast<const h8*>(buf + ((wd + i) * PARTS + q) * kSplitTileBytes + lane * 16);
-                xop[i][q] = *reinterpret_cast<const h8*>(buf + ((wp + i) * PARTS + q) * kSplitTileBytes + lane * 16);
-            }
-        // C[point][dir]: lane (c, r) holds points 4r .. 4r+3 of direction c
-        if constexpr (PARTS == 2) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xop[j][0], dop[i][1], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xop[j][1], dop[i][0], acc[i][j], 0, 0, 0);
-                }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(xop[j][0], dop[i][0], acc[i][j], 0, 0, 0);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, xop[j][0]), __builtin_bit_cast(bf16x8, dop[i][0]),
-                        acc[i][j], 0, 0, 0);
-        }
-    };
-    stage(0, gsm);
-    if (KB > 1) stage(1, gsm + kBufBytes);
-    int cur = 0;                               // buffer of k-block kb
-    for (int kb = 0; kb < KB; ++kb) {
-        // this wave's loads of k-block kb have landed (those of kb + 1, the
-        // last 3 * PARTS it issued, may still run); after the barrier every
-        // wave's have, and no wave still reads the buffer of k-block kb - 1,
-        // which k-block kb + 2 goes into
-        if (kb + 1 < KB) {
-            if constexpr (PARTS == 2) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-            else asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
-        } else {
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        }
-        // a bare s_barrier: __syncthreads() would also wait for the loads
-        // still in flight
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        const int nxt2 = cur == 0 ? 2 : cur - 1;   // (cur + 2) % 3
-        if (kb + 2 < KB) stage(kb + 2, gsm + nxt2 * kBufBytes);
-        compute(gsm + cur * kBufBytes);
-        cur = cur == 2 ? 0 : cur + 1;
-    }
-    const int c = lane & 15, r = lane >> 4;
-    bool bad = false;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t p = (dt0 + wd + i) * 16 + c;
-        if (p >= P) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            // points past N (zero rows, inside the padded row) are stored too
-            const int64_t n = (pt0 + wp - kGemmDT + j) * 16 + 4 * r;
-            if (n >= nptiles * 16) continue;
-            const f32x4 v = acc[i][j] * pscale;
-            *reinterpret_cast<float4*>(out + p * ld + n) = make_float4(v[0], v[1], v[2], v[3]);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bad |= !(fabsf(v[e]) <= bound);
-        }
-    }
-    if (bad) atomicOr(flag, 1);
-}
-
-// BF16 point tiles (one part per k-block): bf16(Z) in the tile layout; the
-// largest |Z_row * inv_r|^2 into *norm_slot (nullable, see BoundCheck)
-__global__ __launch_bounds__(kBlock) void bf16_points_kernel(
-    const float* __restrict__ Z, int64_t N, int d, int KB, int64_t ntiles, u32x4* __restrict__ tiles,
-    float inv_r, unsigned* __restrict__ norm_slot) {
-    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (id >= ntiles * 64) return;                    // whole waves
-    const int lane = (int)(id & 63);
-    const int64_t t = id >> 6, r0 = 16 * t;
-    const int64_t nrows = N - r0 < 16 ? N - r0 : 16;
-    const __amdgpu_buffer_rsrc_t zs = buffer_rsrc(Z + r0 * d, nrows * (int64_t)d * 4);
-    float ss = 0.f;
-    for (int kb = 0; kb < KB; ++kb) {
-        const int col0 = 32 * kb + 8 * (lane >> 4);
-        const int off = ((lane & 15) * d + col0) * 4;
-        const u32x4 va = __builtin_amdgcn_raw_buffer_load_b128(zs, off, 0, 0);
-        const u32x4 vb = __builtin_amdgcn_raw_buffer_load_b128(zs, off + 16, 0, 0);
-        float v[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            v[e] = col0 + e < d ? __uint_as_float(e < 4 ? va[e] : vb[e - 4]) : 0.f;
-            const float vs = v[e] * inv_r;
-            ss = fmaf(vs, vs, ss);
-        }
-        tiles[(t * KB + kb) * 64 + lane] = u32x4{pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]),
-                                                 pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7])};
-    }
-    ss += __shfl_xor(ss, 16);
-    ss += __shfl_xor(ss, 32);
-    if (norm_slot != nullptr) record_norm2(norm_slot, ss);
-}
-
 template <int W, int KB>
 void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Xt,
                            int64_t N, const uint16_t* At, const float* w, int P,
@@ -1773,49 +1571,6 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((M * d + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, stream, gpart, nrange, ldg, DC, M, d, coef, v, grad_y);
-    return hipGetLastError();
-}
-
-size_t project_tiles_bytes(int64_t rows, int d, bool bf16) {
-    return (size_t)split_tiles_bytes(rows, d) / (bf16 ? 2 : 1);
-}
-
-hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, const uint16_t* At,
-                                int P, float inv_r, float pscale, uint16_t* xtiles, float* out,
-                                int64_t ld, float bound, int* flag, unsigned* norm_slot,
-                                hipStream_t stream) {
-    // three k-block buffers: 144 KB (f16 hi + lo) or 72 KB (BF16) of LDS
-    constexpr int kLds2 = 3 * (kGemmDT + kGemmPT) * 2 * kSplitTileBytes;
-    constexpr int kLds1 = 3 * (kGemmDT + kGemmPT) * kSplitTileBytes;
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&project_tiles_kernel<2>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLds2);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&project_tiles_kernel<1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLds1);
-        attr_set = true;
-    }
-    const int KB = split_kblocks(d);
-    const int64_t ntiles = (N + 15) / 16;
-    const unsigned sb = (unsigned)((ntiles * 64 + kBlock - 1) / kBlock);
-    if (bf16)
-        hipLaunchKernelGGL(bf16_points_kernel, dim3(sb), dim3(kBlock), 0, stream, X, N, d, KB, ntiles,
-                           reinterpret_cast<u32x4*>(xtiles), inv_r, norm_slot);
-    else   // no per-point range check here: the projections are checked when stored
-        hipLaunchKernelGGL(split_points_kernel, dim3(sb), dim3(kBlock), 0, stream, X, N, d, inv_r,
-                           KB, ntiles, reinterpret_cast<u32x4*>(xtiles), __builtin_inff(), flag,
-                           norm_slot);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int ndb = (P + 16 * kGemmDT - 1) / (16 * kGemmDT);
-    const int npb = (int)((N + 16 * kGemmPT - 1) / (16 * kGemmPT));
-    const dim3 grid(proj_grid_blocks(ndb, npb));
-    if (bf16)
-        hipLaunchKernelGGL(project_tiles_kernel<1>, grid, dim3(kGemmBlock), kLds1, stream, xtiles,
-                           N, At, P, KB, pscale, out, ld, bound, flag, ndb, npb);
-    else
-        hipLaunchKernelGGL(project_tiles_kernel<2>, grid, dim3(kGemmBlock), kLds2, stream, xtiles,
-                           N, At, P, KB, pscale, out, ld, bound, flag, ndb, npb);
     return hipGetLastError();
 }
 
