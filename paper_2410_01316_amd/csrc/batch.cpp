@@ -456,7 +456,7 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     }
     b->arena_bytes = off;
     b->task_cap = tasks;
-    b->lds_spread = b->fused ? fused_spread_lds(max_nr) : (size_t)max_nr * (sizeof(double) + sizeof(int));
+    b->lds_spread = b->fused ? fused_spread_lds(max_nr) : stored_spread_lds(max_nr);
     b->lds_fft = fftconv_lds_bytes(max_n, false);
     b->lds_gather = b->fused ? fused_gather_lds(max_nr) : (size_t)b->pstage * max_nr * sizeof(float);
 

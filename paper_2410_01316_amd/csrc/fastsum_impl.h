@@ -331,6 +331,8 @@ hipError_t launch_batch_phase_fused(int phase, int W, const BatchProblem* probs,
                                     size_t lds_bytes, hipStream_t stream);
 // LDS bytes of the fused batch spread / gather workgroups for grids of nr cells
 size_t fused_spread_lds(int nr);
+// LDS bytes of the stored-projection spread (one direction's int32 cells)
+size_t stored_spread_lds(int nr);
 size_t fused_gather_lds(int nr);
 
 }  // namespace fastsum

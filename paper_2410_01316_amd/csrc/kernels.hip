@@ -391,12 +391,14 @@ hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64
 // w * phi is scaled by 2^k (|w| 2^k < 2^18 for the slice's largest |w|),
 // rounded to an integer and added with an integer LDS atomic.  A cell of a
 // slice then holds at most 4096 terms below 2^18 * 1.01 in magnitude, so its
-// sum is exact in 32 bits.  After each slice the cells are moved into an
-// FP64 LDS accumulator (fixed order).  Grids are bitwise reproducible.
+// sum is exact in 32 bits.  After each slice the cells are moved into FP32
+// accumulators in registers (thread t owns cells t + kBlock q, fixed order).
+// Grids are bitwise reproducible.
 // ---------------------------------------------------------------------------
 
 constexpr int kSlice = 4096;                       // sources per fixed-point slice
 constexpr int kSliceSteps = kSlice / (4 * kBlock); // float4 steps per thread and slice
+constexpr int kSpreadAcc = 2048 / kBlock;          // cell accumulators per thread (nr <= 2048)
 
 // slice_max[s] = max |w_i| over sources i of slice s
 __device__ __forceinline__ void slice_max_tile(float* red, const float* __restrict__ w,
@@ -462,14 +464,13 @@ __device__ __forceinline__ void spread_tile(
     const float* __restrict__ w, int64_t N, int P, const GridGeom& g, int64_t chunk_len,
     const float* __restrict__ slice_max, const WindowArgs& win, float* __restrict__ partial,
     int p, int c) {
-    double* acc = reinterpret_cast<double*>(lds_raw);          // nr doubles
-    int* lds32 = reinterpret_cast<int*>(acc + g.nr);          // nr ints
+    int* lds32 = reinterpret_cast<int*>(lds_raw);             // nr ints
     const WinEval<W> ev(g, win);
+    float acc[kSpreadAcc];
+#pragma unroll
+    for (int q = 0; q < kSpreadAcc; ++q) acc[q] = 0.f;
     __syncthreads();               // LDS may still be read by a previous tile
-    for (int j = threadIdx.x; j < g.nr; j += kBlock) {
-        acc[j] = 0.0;
-        lds32[j] = 0;
-    }
+    for (int j = threadIdx.x; j < g.nr; j += kBlock) lds32[j] = 0;
     __syncthreads();
     const int64_t i0 = (int64_t)c * chunk_len;          // multiple of kSlice
     const int64_t i1 = min(N, i0 + chunk_len);
@@ -495,15 +496,23 @@ __device__ __forceinline__ void spread_tile(
             spread_point<W>(xv[q].w, wv[q][3] * scale, ev, win, lds32);
         }
         __syncthreads();
-        const double unscale = ldexp(1.0, -k);
-        for (int j = threadIdx.x; j < g.nr; j += kBlock) {
-            acc[j] += (double)lds32[j] * unscale;
-            lds32[j] = 0;
+        const float unscale = ldexpf(1.f, -k);
+#pragma unroll
+        for (int q = 0; q < kSpreadAcc; ++q) {
+            const int j = threadIdx.x + q * kBlock;
+            if (j < g.nr) {
+                acc[q] = fmaf((float)lds32[j], unscale, acc[q]);
+                lds32[j] = 0;
+            }
         }
         __syncthreads();
     }
     float* __restrict__ dst = partial + ((int64_t)c * P + p) * g.nr;
-    for (int j = threadIdx.x; j < g.nr; j += kBlock) dst[j] = (float)acc[j];
+#pragma unroll
+    for (int q = 0; q < kSpreadAcc; ++q) {
+        const int j = threadIdx.x + q * kBlock;
+        if (j < g.nr) dst[j] = acc[q];
+    }
 }
 
 template <int W>
@@ -511,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(
     const float* __restrict__ proj, int64_t ld, const float* __restrict__ w,
     int64_t N, int P, GridGeom g, int64_t chunk_len, const float* __restrict__ slice_max,
     WindowArgs win, float* __restrict__ partial) {
-    extern __shared__ double lds_spread[];
+    extern __shared__ int lds_spread[];
     spread_tile<W>(lds_spread, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial,
                    blockIdx.x, blockIdx.y);
 }
@@ -523,7 +532,7 @@ hipError_t launch_spread(int W, const float* proj, int64_t ld, const float* w,
     hipLaunchKernelGGL(slice_max_kernel, dim3((unsigned)((N + kSlice - 1) / kSlice)), dim3(kBlock),
                        0, stream, w, N, slice_max);
     dim3 grid((unsigned)P, (unsigned)nchunk);
-    const size_t lds = (size_t)g.nr * (sizeof(double) + sizeof(int));
+    const size_t lds = stored_spread_lds(g.nr);
     switch (W) {
         case 4: hipLaunchKernelGGL(spread_kernel<4>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial); break;
         case 6: hipLaunchKernelGGL(spread_kernel<6>, grid, dim3(kBlock), lds, stream, proj, ld, w, N, P, g, chunk_len, slice_max, win, partial); break;
@@ -1712,7 +1721,7 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void batch_spread_kernel(
     const BatchProblem* __restrict__ probs, const BatchTask* __restrict__ tasks, int ntasks,
     int P, WindowArgs win) {
-    extern __shared__ double lds_bspread[];
+    extern __shared__ int lds_bspread[];
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const BatchTask tk = tasks[t];
         const BatchProblem& pr = probs[tk.prob];
@@ -1826,6 +1835,8 @@ __global__ __launch_bounds__(kGatherBlock) void batch_gather_fused_kernel(
 }
 
 size_t fused_spread_lds(int nr) { return (size_t)kFuseDirs * nr * sizeof(int); }
+
+size_t stored_spread_lds(int nr) { return (size_t)nr * sizeof(int); }
 
 size_t fused_gather_lds(int nr) {
     const int stage = (kFuseDirs * nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
