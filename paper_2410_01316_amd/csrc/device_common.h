@@ -42,8 +42,15 @@ __device__ __forceinline__ h8 buffer_load_h8(__amdgpu_buffer_rsrc_t rs, int byte
 // dispatched round-robin over the 8 XCDs, so block b runs on XCD b % 8.
 // Point tile pt and all direction tiles of it go to one XCD (its L2 keeps the
 // point tile while every direction tile reads it): b = 8 (g * ndt + dt) + x
-// with pt = 8 g + x.  Returns false for the padding blocks.
+// with pt = 8 g + x.  With fewer than 8 point tiles the order is plain
+// (b = pt * ndt + dt), which spreads the direction tiles over the XCDs.
+// Returns false for the padding blocks.
 __device__ __forceinline__ bool proj_tile_of_block(int b, int ndt, int npt, int& dt, int& pt) {
+    if (npt < 8) {
+        dt = b % ndt;
+        pt = b / ndt;
+        return pt < npt;
+    }
     const int x = b & 7, j = b >> 3;
     dt = j % ndt;
     pt = (j / ndt) * 8 + x;
@@ -51,7 +58,7 @@ __device__ __forceinline__ bool proj_tile_of_block(int b, int ndt, int npt, int&
 }
 
 inline unsigned proj_grid_blocks(int ndt, int npt) {
-    return (unsigned)(8 * ndt * ((npt + 7) / 8));
+    return npt < 8 ? (unsigned)(ndt * npt) : (unsigned)(8 * ndt * ((npt + 7) / 8));
 }
 
 }  // namespace fastsum

@@ -105,6 +105,17 @@ hipError_t launch_project_f32(const float* X, int64_t N, int d, const float* A64
 // At (bf16: BF16 tau xi; else f16 hi + lo of xi); out = pscale * product.
 // The split form has FP32-level accuracy.
 size_t project_tiles_bytes(int64_t rows, int d, bool bf16);
+// Back-projection on the tile GEMM (d above the fused range):
+// grad[m * d + i] = coef v[m] sum_p T[p * ld + m] tau xi_p[i], T: P x M.
+// xit: split tiles of xi^T (rows i, columns p; xi_transpose_tiles_host);
+// ttiles: backproject_tiles_bytes(M, P) bytes of scratch; scratch:
+// backproject_scratch_bytes() bytes.
+size_t backproject_tiles_bytes(int64_t rows, int P);
+size_t backproject_scratch_bytes();
+hipError_t launch_backproject_tiles(const float* T, int64_t ld, int64_t M, int P, int d,
+                                    const uint16_t* xit, float tau, float coef, const float* v,
+                                    float* grad, uint16_t* ttiles, void* scratch,
+                                    hipStream_t stream);
 hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, const uint16_t* At,
                                 int P, float inv_r, float pscale, uint16_t* xtiles, float* out,
                                 int64_t ld, float bound, int* flag, unsigned* norm_slot,

@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace fastsum {
 
 namespace {
@@ -100,7 +102,8 @@ template <int PARTS>
 __global__ __launch_bounds__(GemmGeom<PARTS>::kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void project_tiles_kernel(const uint16_t* __restrict__ Xt, int64_t N,
                           const uint16_t* __restrict__ At, int P, int KB, float pscale,
-                          float* __restrict__ out, int64_t ld, float bound,
+                          const float* __restrict__ row_scale, const float* __restrict__ gscale,
+                          float* __restrict__ out, int64_t ld, int64_t ncols, float bound,
                           int* __restrict__ flag, int ndb, int npb) {
     using S = GemmShape<PARTS>;
     using G = GemmGeom<PARTS>;
@@ -211,24 +214,35 @@ void project_tiles_kernel(const uint16_t* __restrict__ Xt, int64_t N,
     }
     if (dt0 + wd >= ndtiles || pt0 + wp >= nptiles) return;
 
+    // out row p, column n: pscale (* gscale[0]) (* row_scale[p]) times the
+    // product; columns n >= ncols are not stored
     const int c = lane & 15, r = lane >> 4;
+    const float gs = gscale != nullptr ? pscale * gscale[0] : pscale;
+    const bool vec4 = ((ncols | ld) & 3) == 0;
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < TD; ++i) {
         const int64_t p = (dt0 + wd + i) * 16 + c;
         if (p >= P) continue;
+        const float rs = row_scale != nullptr ? gs * row_scale[p] : gs;
+        float* __restrict__ orow = out + p * ld;
 #pragma unroll
         for (int j = 0; j < TP; ++j) {
-            // points past N (zero rows, inside the padded row) are stored too
             const int64_t n = (pt0 + wp + j) * 16 + 4 * r;
-            if (n >= nptiles * 16) continue;
-            const f32x4 v = acc[i][j] * pscale;
-            *reinterpret_cast<float4*>(out + p * ld + n) = make_float4(v[0], v[1], v[2], v[3]);
+            if (n >= ncols) continue;
+            const f32x4 v = acc[i][j] * rs;
+            if (vec4) {
+                *reinterpret_cast<float4*>(orow + n) = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (n + e < ncols) orow[n + e] = v[e];
+            }
 #pragma unroll
             for (int e = 0; e < 4; ++e) bad |= !(fabsf(v[e]) <= bound);
         }
     }
-    if (bad) atomicOr(flag, 1);
+    if (bad && flag != nullptr) atomicOr(flag, 1);
 }
 
 // BF16 point tiles (one part per k-block): bf16(Z) in the tile layout; the
@@ -265,8 +279,8 @@ __global__ __launch_bounds__(kBlock) void bf16_points_kernel(
 
 template <int PARTS>
 hipError_t launch_gemm(const uint16_t* Xt, int64_t N, const uint16_t* At, int P, int KB,
-                       float pscale, float* out, int64_t ld, float bound, int* flag,
-                       hipStream_t stream) {
+                       float pscale, const float* row_scale, const float* gscale, float* out,
+                       int64_t ld, int64_t ncols, float bound, int* flag, hipStream_t stream) {
     using G = GemmGeom<PARTS>;
     static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
     if (!attr_set) {
@@ -277,9 +291,89 @@ hipError_t launch_gemm(const uint16_t* Xt, int64_t N, const uint16_t* At, int P,
     const int ndb = (P + 16 * G::kDT - 1) / (16 * G::kDT);
     const int npb = (int)((N + 16 * G::kPT - 1) / (16 * G::kPT));
     hipLaunchKernelGGL(project_tiles_kernel<PARTS>, dim3(proj_grid_blocks(ndb, npb)),
-                       dim3(G::kThreads), G::kLdsBytes, stream, Xt, N, At, P, KB, pscale, out,
-                       ld, bound, flag, ndb, npb);
+                       dim3(G::kThreads), G::kLdsBytes, stream, Xt, N, At, P, KB, pscale,
+                       row_scale, gscale, out, ld, ncols, bound, flag, ndb, npb);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Back-projection on the tile GEMM (any d, used above the fused range):
+//   grad[m][i] = coef v[m] sum_p T[p][m] (tau xi_p)_i,
+// the chain rule through x~_{m,p} = tau <xi_p, y_m> (eq. kernel_sum_sliced
+// differentiated in y_m), T[p][m] the derivative of the 1-D sum of
+// direction p at target m.  T (P x M, row stride ld) becomes split-f16 tiles
+// with rows m and columns p, scaled by 2^-e so that max |T| 2^-e < 1 (the
+// f16 parts then keep FP32-level accuracy relative to the largest entry);
+// xi^T is a split tile operand with rows i and columns p (built once per
+// plan); the GEMM's epilogue applies coef v[m] tau 2^e.
+// ---------------------------------------------------------------------------
+
+constexpr int kAbsSlots = 64;
+constexpr int kAbsStride = 16;                     // one 64-byte line per slot
+
+__global__ __launch_bounds__(kBlock) void clear_slots_kernel(unsigned* __restrict__ slots) {
+    for (int j = threadIdx.x; j < kAbsSlots * kAbsStride; j += kBlock) slots[j] = 0u;
+}
+
+// largest |T[p][m]| (p < P, m < M) as float bits into the slots (a
+// non-finite entry records +inf); workgroup (x, y) walks rows y + k gridDim.y
+__global__ __launch_bounds__(kBlock) void abs_max_kernel(const float* __restrict__ T, int64_t ld,
+                                                         int P, int64_t M,
+                                                         unsigned* __restrict__ slots) {
+    float mx = 0.f;
+    for (int p = blockIdx.y; p < P; p += gridDim.y) {
+        const float* __restrict__ row = T + (int64_t)p * ld;
+        for (int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x; m < M;
+             m += (int64_t)gridDim.x * kBlock) {
+            const float a = fabsf(row[m]);
+            mx = (a <= 3.4e38f) ? fmaxf(mx, a) : __builtin_inff();
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    const int b = blockIdx.x + gridDim.x * blockIdx.y;
+    if ((threadIdx.x & 63) == 0) atomicMax(slots + (b % kAbsSlots) * kAbsStride, __float_as_uint(mx));
+}
+
+// e with max 2^-e < 1 from the slots (0 for an all-zero or non-finite T)
+__device__ __forceinline__ int slots_exponent(const unsigned* __restrict__ slots, int lane) {
+    float mx = __uint_as_float(slots[lane * kAbsStride]);      // 64 lanes, 64 slots
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    int e = 0;
+    if (mx > 0.f && mx <= 3.4e38f) (void)frexpf(mx, &e);     // mx < 2^e
+    return e;
+}
+
+// Split tiles of T^T: tile t (rows m = 16 t + c), k-block kb (columns
+// p = 32 kb + 8 j + q), lane c + 16 j; one wave per (tile, k-block).  Entry
+// 0 of gscale_out receives tau 2^e.
+__global__ __launch_bounds__(kBlock) void split_cols_kernel(
+    const float* __restrict__ T, int64_t ld, int P, int64_t M, int KB, int64_t ntiles,
+    const unsigned* __restrict__ slots, float tau, u32x4* __restrict__ tiles,
+    float* __restrict__ gscale_out) {
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id >= ntiles * KB * 64) return;               // whole waves
+    const int lane = (int)(id & 63);
+    const int64_t w = id >> 6;
+    const int64_t t = w / KB;
+    const int kb = (int)(w - t * KB);
+    const int e = slots_exponent(slots, lane);
+    const float s = ldexpf(1.f, -e);
+    if (id == 0) gscale_out[0] = ldexpf(tau, e);
+    const int64_t m = 16 * t + (lane & 15);
+    const int p0 = 32 * kb + 8 * (lane >> 4);
+    h8 hi, lo;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float v = (m < M && p0 + q < P) ? T[(int64_t)(p0 + q) * ld + m] * s : 0.f;
+        const _Float16 h = (_Float16)v;
+        hi[q] = h;
+        lo[q] = (_Float16)(v - (float)h);
+    }
+    const int64_t base = (t * KB + kb) * 2 * 64 + lane;   // in 16-byte units
+    tiles[base] = __builtin_bit_cast(u32x4, hi);
+    tiles[base + 64] = __builtin_bit_cast(u32x4, lo);
 }
 
 }  // namespace
@@ -304,8 +398,39 @@ hipError_t launch_project_tiles(const float* X, int64_t N, int d, bool bf16, con
         e = launch_split_points(X, N, d, inv_r, xtiles, __builtin_inff(), flag, norm_slot, stream);
     }
     if (e != hipSuccess) return e;
-    return bf16 ? launch_gemm<1>(xtiles, N, At, P, KB, pscale, out, ld, bound, flag, stream)
-                : launch_gemm<2>(xtiles, N, At, P, KB, pscale, out, ld, bound, flag, stream);
+    const int64_t ncols = (N + 15) / 16 * 16;          // the padded rows are stored too
+    return bf16 ? launch_gemm<1>(xtiles, N, At, P, KB, pscale, nullptr, nullptr, out, ld, ncols,
+                                 bound, flag, stream)
+                : launch_gemm<2>(xtiles, N, At, P, KB, pscale, nullptr, nullptr, out, ld, ncols,
+                                 bound, flag, stream);
+}
+
+size_t backproject_tiles_bytes(int64_t rows, int P) { return (size_t)split_tiles_bytes(rows, P); }
+
+size_t backproject_scratch_bytes() { return (size_t)kAbsSlots * kAbsStride * 4 + 256; }
+
+hipError_t launch_backproject_tiles(const float* T, int64_t ld, int64_t M, int P, int d,
+                                    const uint16_t* xit, float tau, float coef, const float* v,
+                                    float* grad, uint16_t* ttiles, void* scratch,
+                                    hipStream_t stream) {
+    if (M < 1 || P < 1 || d < 1) return hipErrorInvalidValue;
+    unsigned* slots = static_cast<unsigned*>(scratch);
+    float* gscale = reinterpret_cast<float*>(slots + kAbsSlots * kAbsStride);
+    hipLaunchKernelGGL(clear_slots_kernel, dim3(1), dim3(kBlock), 0, stream, slots);
+    const dim3 mg((unsigned)std::min<int64_t>(64, (M + kBlock - 1) / kBlock),
+                  (unsigned)std::min(P, 32));
+    hipLaunchKernelGGL(abs_max_kernel, mg, dim3(kBlock), 0, stream, T, ld, P, M, slots);
+    const int KB = split_kblocks(P);
+    const int64_t ntiles = (M + 15) / 16;
+    const unsigned sb = (unsigned)((ntiles * KB * 64 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(split_cols_kernel, dim3(sb), dim3(kBlock), 0, stream, T, ld, P, M, KB,
+                       ntiles, slots, tau, reinterpret_cast<u32x4*>(ttiles), gscale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // rows m of the T^T tiles in the direction role, rows i of the xi^T
+    // tiles in the point role: out[m d + i]
+    return launch_gemm<2>(xit, d, ttiles, (int)M, KB, coef, v, gscale, grad, d, d,
+                          __builtin_inff(), nullptr, stream);
 }
 
 }  // namespace fastsum

@@ -399,6 +399,27 @@ void bf16_dirs_host(const std::vector<float>& A, int dpad, int d, int P,
                 }
 }
 
+// Split tiles of xi^T for the back-projection GEMM: rows i (coordinates),
+// columns p (directions), same layout as split_dirs_host.
+void split_xit_host(const float* xi, int d, int P, std::vector<uint16_t>& out) {
+    const int KB = split_kblocks(P);
+    const int64_t tiles = (d + 15) / 16;
+    out.assign((size_t)(tiles * KB * 2 * kSplitTileBytes / 2), 0);
+    for (int64_t t = 0; t < tiles; ++t)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t i = 16 * t + (lane & 15);
+                    const int p = 32 * kb + 8 * (lane >> 4) + e;
+                    const float v = (i < d && p < P) ? xi[(size_t)i * P + p] : 0.f;
+                    const _Float16 hi = (_Float16)v;
+                    const _Float16 lo = (_Float16)(v - (float)hi);
+                    const size_t base = (size_t)((t * KB + kb) * 2) * (kSplitTileBytes / 2) + 8 * lane + e;
+                    std::memcpy(&out[base], &hi, 2);
+                    std::memcpy(&out[base + kSplitTileBytes / 2], &lo, 2);
+                }
+}
+
 fastsum_status status_of(hipError_t e) {
     if (e == hipSuccess) return FASTSUM_OK;
     if (e == hipErrorOutOfMemory) return FASTSUM_ENOMEM;
@@ -473,6 +494,11 @@ struct fastsum_plan_s {
     float* sty = nullptr;          // sorted adjoint: d/dy~ and d/dx~ per direction, P x ldm
     float* stx = nullptr;
     int64_t sort_L = 0, sort_yoff = 0;
+    // back-projection on the tile GEMM (d above the fused range): split
+    // tiles of xi^T, the derivative matrix as tiles, abs-max slots
+    uint16_t* xit = nullptr;
+    uint16_t* bp_tiles = nullptr;
+    unsigned* bp_scratch = nullptr;
     // last exec
     bool have_exec = false, last_same = false;
     const float* last_x = nullptr;
@@ -498,6 +524,7 @@ void free_plan(fastsum_plan_s* p) {
                     p->grid_w, p->spart, p->tprime, p->mult, p->mult_d, p->tw, p->flag,
                     p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout, p->keys,
                     p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx, p->norms,
+                    p->xit, p->bp_tiles, p->bp_scratch,
                     p->sti};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -687,6 +714,16 @@ fastsum_status project(fastsum_plan_s* pl, const float* X, int64_t N, float* out
                                     norm_slot, inv_r, st));
 }
 
+// grad[m * d + i] = coef v[m] sum_p T[p * ld + m] tau xi_p[i]: on the tile
+// GEMM above the fused range, else the FP32-MFMA back-projection kernel
+fastsum_status backproject(fastsum_plan_s* pl, const float* T, int64_t ld, int64_t M, float coef,
+                           const float* v, float* grad, hipStream_t st) {
+    if (pl->xit)
+        return check(launch_backproject_tiles(T, ld, M, pl->P, pl->d, pl->xit, (float)pl->r.tau,
+                                              coef, v, grad, pl->bp_tiles, pl->bp_scratch, st));
+    return check(launch_backproject(T, ld, M, pl->P, pl->d, pl->A, pl->dpad, coef, v, grad, st));
+}
+
 // Sorted plans (energy kernel): project x and y into the rows of the sort,
 // then per direction sort + FP64 prefix sums give
 // -(c_d / tau) sum_n w_n |x~_n - y~_m| = sum_n w_n f(<xi_p, x_n - y_m>)
@@ -740,13 +777,13 @@ fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, fl
     const float inv_p = (float)(1.0 / P);
     if (grad_y) {
         PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
-        FS_TRY(launch_backproject(pl->sty, pl->ldm, M, P, pl->d, pl->A, pl->dpad, inv_p, v,
-                                  grad_y, st));
+        fastsum_status r = backproject(pl, pl->sty, pl->ldm, M, inv_p, v, grad_y, st);
+        if (r != FASTSUM_OK) return r;
     }
     if (grad_x) {
         PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
-        FS_TRY(launch_backproject(pl->stx, pl->ldm, N, P, pl->d, pl->A, pl->dpad, inv_p,
-                                  pl->last_w, grad_x, st));
+        fastsum_status r = backproject(pl, pl->stx, pl->ldm, N, inv_p, pl->last_w, grad_x, st);
+        if (r != FASTSUM_OK) return r;
     }
     if (grad_w) {
         PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
@@ -901,6 +938,12 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
              (pl->fused ? dev_alloc(&pl->ab, (size_t)gtiles * 4 * DC * 64) &&
                               dev_alloc(&pl->gpart, (size_t)kGradMaxRanges * pl->ldg * 16 * DC)
                         : dev_alloc(&pl->tprime, (size_t)P * std::max(pl->ld_x, pl->ld_y)));
+    if (ok && grad && pl->d > kSplitMaxD) {
+        const int64_t rows = pl->sorted ? pl->ldm : std::max(pl->ld_x, pl->ld_y);
+        ok = dev_alloc(&pl->xit, backproject_tiles_bytes(pl->d, P) / 2) &&
+             dev_alloc(&pl->bp_tiles, backproject_tiles_bytes(rows, P) / 2) &&
+             dev_alloc(&pl->bp_scratch, backproject_scratch_bytes() / sizeof(unsigned));
+    }
     if (!ok) { free_plan(pl); return FASTSUM_ENOMEM; }
 
     // tables
@@ -915,7 +958,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         for (int p = 0; p < P; ++p)
             for (int i = 0; i < pl->d; ++i) A64[(size_t)p * kA64Cols + i] = A[(size_t)p * pl->dpad + i];
     }
-    std::vector<uint16_t> at, gdt;
+    std::vector<uint16_t> at, gdt, xit;
+    if (pl->xit) split_xit_host(xi, pl->d, P, xit);
     if (pl->at) split_dirs_host(xi, pl->d, P, at);
     if (pl->gdt) {
         if (r.p.proj == FASTSUM_PROJ_BF16) bf16_dirs_host(A, pl->dpad, pl->d, P, gdt);
@@ -953,6 +997,8 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
         e = hipMemcpyAsync(pl->ab, ab.data(), ab.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->gdt)
         e = hipMemcpyAsync(pl->gdt, gdt.data(), gdt.size() * 2, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && pl->xit)
+        e = hipMemcpyAsync(pl->xit, xit.data(), xit.size() * 2, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->A64)
         e = hipMemcpyAsync(pl->A64, A64.data(), A64.size() * sizeof(float), hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && pl->mult)
@@ -1092,8 +1138,8 @@ fastsum_status fastsum_grad_xyw(fastsum_plan pl, const float* grad_s, float* gra
                                  pl->win_args, nullptr, 0, pl->tprime, pl->ld_y, st));
         }
         PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
-        FS_TRY(launch_backproject(pl->tprime, pl->ld_y, M, P, pl->d, pl->A, pl->dpad, coef, grad_s,
-                                  grad_y, st));
+        fastsum_status r = backproject(pl, pl->tprime, pl->ld_y, M, coef, grad_s, grad_y, st);
+        if (r != FASTSUM_OK) return r;
     }
     if (grad_w || grad_x) {
         fastsum_status r = sum_pass(pl, yp, ldy, grad_s, M, pl->xproj, pl->ld_x, N, uout,
@@ -1108,8 +1154,8 @@ fastsum_status fastsum_grad_xyw(fastsum_plan pl, const float* grad_s, float* gra
                                  pl->pstage, pl->win_args, nullptr, 0, pl->tprime, pl->ld_x, st));
         }
         PhaseTimer t(pl, FASTSUM_PHASE_BACKPROJECT, st);
-        FS_TRY(launch_backproject(pl->tprime, pl->ld_x, N, P, pl->d, pl->A, pl->dpad, coef,
-                                  pl->last_w, grad_x, st));
+        fastsum_status r = backproject(pl, pl->tprime, pl->ld_x, N, coef, pl->last_w, grad_x, st);
+        if (r != FASTSUM_OK) return r;
     }
     return FASTSUM_OK;
 }

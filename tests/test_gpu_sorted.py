@@ -268,6 +268,26 @@ def test_sorted_gradients_qmc_directions():
     assert e[0] < 2e-3 and e[1] < 2e-3 and e[2] < 1e-5
 
 
+@pytest.mark.parametrize("d,P", [(100, 40), (102, 72)])
+def test_sorted_gradients_tile_gemm_backprojection(d, P):
+    """Above the fused range the derivative matrices are back-projected on
+    the split-f16 tile GEMM (rows scaled by a power of two, FP32-level
+    products): d = 100 takes the 16-byte stores, d = 102 the element stores
+    of the ragged row end; P is not a whole number of 32-column k-blocks.
+    Bars as for the QMC case (FP32 key order at near-ties)."""
+    N, M = 1500, 1300
+    cfg = _points(N, M, d, seed=43 + d)
+    x, y, w = cfg["x"], cfg["y"], cfg["w"]
+    v = np.random.default_rng(44).standard_normal(M).astype(np.float32).astype(np.float64)
+    xi = directions("orth", d, P, 9)
+    s, gx, gy, gw = _sorted_grads(x, y, w, v, xi)
+    xo, yo, wo, xio = oracle_inputs(dict(x=x, y=y, w=w, xi=xi))
+    ox, oy, ow = O.grad_sliced_energy(xo, yo, wo, v, xio)
+    e = [rel_l2(gx, ox), rel_l2(gy, oy), rel_l2(gw, ow)]
+    print("sorted grads, d=%d P=%d: gx %.1e gy %.1e gw %.1e" % (d, P, *e))
+    assert e[0] < 2e-3 and e[1] < 2e-3 and e[2] < 1e-5
+
+
 def test_sorted_autograd_matches_plan_grad():
     import paper_2410_01316_amd as F
     import torch
