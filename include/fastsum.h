@@ -189,9 +189,10 @@ FASTSUM_API void fastsum_destroy(fastsum_plan plan);
 
 /*
  * s_m ~ sum_n w_n F(||x_n - y_m||) by Fourier slicing.
- *   x  device, N x d;  w  device, N;  y  device, M x d, may equal x (then the
- *   projections are computed once);  s  device, M (written).
- *   1 <= N <= n_max, 1 <= M <= m_max.
+ *   x  device, N x d;  w  device, N;  y  device, M x d, may equal x with
+ *   M <= N: the targets are then the first M sources and their projections
+ *   are computed once (FASTSUM_EINVAL for y == x with M > N);
+ *   s  device, M (written).  1 <= N <= n_max, 1 <= M <= m_max.
  * Asynchronous on `stream`.  The projections (fused plans: the split
  * operand tiles of x and y) and the grids of the call are kept in the plan
  * for a following fastsum_grad.  If a projected point exceeds the bound

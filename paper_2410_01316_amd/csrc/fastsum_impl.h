@@ -86,9 +86,9 @@ __device__ inline void finish_bound_check(const BoundCheck& bc) {
 // clears the kNormUints norm slots (a fill kernel, so a graph capture
 // records no memset)
 hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream);
-// largest |x_n|^2 over the rows of X (N x d) into the slots of `role`, one
-// wave per row
-hipError_t launch_point_norms(const float* X, int64_t N, int d, unsigned* role,
+// largest |x_n * scale|^2 over the rows of X (N x d) into the slots of
+// `role`, one wave per row
+hipError_t launch_point_norms(const float* X, int64_t N, int d, float scale, unsigned* role,
                               hipStream_t stream);
 
 // out[p*ld + j] = sum_i A[p*dpad + i] * X[j*d + i] for p < P, j < N, with

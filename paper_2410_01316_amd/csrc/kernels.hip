@@ -1054,9 +1054,10 @@ __global__ __launch_bounds__(kBlock) void split_points_kernel(
                       norm_slot);
 }
 
-// One wave per row of X: the largest |x_n|^2 into *slot (bound helper).
+// One wave per row of X: the largest |x_n * scale|^2 into *slot (bound
+// helper, scale 1; targets shared with the sources, scale 1 / R).
 __global__ __launch_bounds__(kBlock) void point_norms_kernel(const float* __restrict__ X,
-                                                             int64_t N, int d,
+                                                             int64_t N, int d, float scale,
                                                              unsigned* __restrict__ slot) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
@@ -1065,7 +1066,10 @@ __global__ __launch_bounds__(kBlock) void point_norms_kernel(const float* __rest
     for (int64_t n = wave; n < N; n += nwaves) {      // uniform over the wave
         const float* __restrict__ row = X + n * d;
         float ss = 0.f;
-        for (int k = lane; k < d; k += 64) ss = fmaf(row[k], row[k], ss);
+        for (int k = lane; k < d; k += 64) {
+            const float v = row[k] * scale;
+            ss = fmaf(v, v, ss);
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
         mx = (ss <= 3.4e38f) ? fmaxf(mx, ss) : __builtin_inff();   // NaN -> inf
@@ -1082,11 +1086,11 @@ hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_point_norms(const float* X, int64_t N, int d, unsigned* slot,
+hipError_t launch_point_norms(const float* X, int64_t N, int d, float scale, unsigned* slot,
                               hipStream_t stream) {
     const int64_t waves = std::min<int64_t>(N, (int64_t)4096);
     hipLaunchKernelGGL(point_norms_kernel, dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, stream, X, N, d, slot);
+                       dim3(kBlock), 0, stream, X, N, d, scale, slot);
     return hipGetLastError();
 }
 

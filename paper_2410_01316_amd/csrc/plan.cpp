@@ -1023,8 +1023,8 @@ fastsum_status fastsum_bound(const float* x, int64_t N, const float* y, int64_t 
     if (!dev_alloc(&slots, kNormUints)) return FASTSUM_ENOMEM;
     std::vector<unsigned> h(kNormUints, 0u);
     hipError_t e = hipMemsetAsync(slots, 0, kNormUints * sizeof(unsigned), st);
-    if (e == hipSuccess) e = launch_point_norms(x, N, d, slots, st);
-    if (e == hipSuccess) e = launch_point_norms(y, M, d, slots + kNormRoleUints, st);
+    if (e == hipSuccess) e = launch_point_norms(x, N, d, 1.f, slots, st);
+    if (e == hipSuccess) e = launch_point_norms(y, M, d, 1.f, slots + kNormRoleUints, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h.data(), slots, kNormUints * sizeof(unsigned), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1051,17 +1051,25 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
                             const float* y, int64_t M, float* s, void* stream) {
     if (!pl || !x || !w || !y || !s) return FASTSUM_EINVAL;
     if (N < 1 || M < 1 || N > pl->n_max || M > pl->m_max) return FASTSUM_EINVAL;
+    // y == x: the targets are the first M <= N sources, whose projections
+    // (or operand tiles) serve both roles
     const bool same = (x == y);
-    if (same && N != M) return FASTSUM_EINVAL;
+    if (same && M > N) return FASTSUM_EINVAL;
+    const bool prefix = same && M < N;
     hipStream_t st = (hipStream_t)stream;
     // the exec's last kernel checks max |x| + max |y| <= R and clears the
     // norm slots; an exec that stopped early left them set
     if (pl->norms_dirty) FS_TRY(launch_clear_norms(pl->norms, st));
     pl->norms_dirty = true;
-    const BoundCheck bc{pl->norms, pl->flag, pl->norm_lim, same ? 1 : 0};
+    const BoundCheck bc{pl->norms, pl->flag, pl->norm_lim, (same && !prefix) ? 1 : 0};
+    // a sorted plan keeps the targets in rows of their own
+    const bool shared = same && !(prefix && pl->sorted);
+    if (prefix && !pl->sorted)
+        FS_TRY(launch_point_norms(y, M, pl->d, (float)(1.0 / pl->r.p.R),
+                                  pl->norms + kNormRoleUints, st));
     fastsum_status r = FASTSUM_OK;
     if (pl->sorted) {
-        r = sorted_pass(pl, x, w, N, y, M, s, same, bc, st);
+        r = sorted_pass(pl, x, w, N, y, M, s, shared, bc, st);
     } else if (pl->fused) {
         r = fused_pass(pl, x, w, N, y, M, s, bc, st);
     } else {
@@ -1081,7 +1089,7 @@ fastsum_status fastsum_exec(fastsum_plan pl, const float* x, int64_t N, const fl
     pl->norms_dirty = false;
     pl->have_exec = true;
     pl->have_proj = !pl->fused;
-    pl->last_same = same;
+    pl->last_same = shared;
     pl->last_x = x;
     pl->last_w = w;
     pl->last_y = y;

@@ -70,7 +70,9 @@ class MMDFlow:
         """grad G_y at the particles x (N x d); returns a new tensor."""
         self.z[: self.N].copy_(x)
         self._ensure_plan(x)
-        self.plan(self.z, self.w, x, out=self.s)
+        # targets: the particles as the first N rows of z (the plan projects
+        # them once, as sources and as targets)
+        self.plan(self.z, self.w, self.z[: self.N], out=self.s)
         gy, _ = self.plan.grad(self.ones, want_y=True, want_w=False)
         return gy
 

@@ -122,3 +122,31 @@ def test_batch_sum_bound_violation_is_flagged(materialize):
     b(xs, ws, ys)
     b.check()
     b.close()
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_prefix_targets_bound(path):
+    """Targets passed as the first M rows of the sources (y == x, M < N): the
+    bound takes the targets' own largest norm, not the sources' twice."""
+    import paper_2410_01316_amd as F
+    from paper_2410_01316_amd import _lib as L
+    from workloads import directions
+    kernel, d, kw, fused = PATHS[path]
+    rng = np.random.default_rng(7 + len(path))
+    R, N, M, P = 2.0, 900, 300, 24
+    xi = directions("orth" if d > 50 else "distance", d, P, 5)
+    plan = F.Plan(xi, kernel=kernel, n_ft=128 if kernel == "gauss" else 1024, scale=1.0, R=R,
+                  n_max=N, m_max=N, **kw)
+    w = to_dev(rng.standard_normal(N))[0]
+    print(path, flush=True)
+    # targets at 0.3 R, the other sources at 0.6 R: 0.9 R <= R
+    x = to_dev(np.concatenate([_sphere(M, d, 0.3 * R, rng), _sphere(N - M, d, 0.6 * R, rng)]))[0]
+    plan(x, w, x[:M])
+    plan.check()
+    # targets at 0.45 R: 1.05 R > R
+    x = to_dev(np.concatenate([_sphere(M, d, 0.45 * R, rng), _sphere(N - M, d, 0.6 * R, rng)]))[0]
+    plan(x, w, x[:M])
+    with pytest.raises(F.FastSumError) as e:
+        plan.check()
+    assert e.value.status == L.ERANGE
+    plan.close()

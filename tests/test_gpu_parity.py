@@ -246,8 +246,9 @@ def test_error_paths(materialize):
     p = lambda t: ctypes.c_void_p(t.data_ptr())
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     N, M = x.shape[0], y.shape[0]
-    # empty, over capacity, and targets equal to the sources with M != N
-    for n, m, yy in [(0, M, y), (N + 1, M, y), (N, 0, y), (N, M + 1, y), (N, N - 1, x)]:
+    # empty, over capacity, and targets equal to the sources with M > N (M < N
+    # takes the first M sources as the targets)
+    for n, m, yy in [(0, M, y), (N + 1, M, y), (N, 0, y), (N, M + 1, y), (N - 1, N, x)]:
         r = good._lib.fastsum_exec(good._h, p(x), n, p(w), p(yy), m, p(out), st)
         assert r == L.EINVAL, (n, m)
     with pytest.raises(F.FastSumError) as e:
