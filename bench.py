@@ -239,7 +239,14 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0,
     import oracle as O
     plan = make_plan(cfg, proj=proj, grad=grad, sorting=sorting)
     x, w = f32dev(cfg["x"]), f32dev(cfg["w"])
-    y = x if cfg.get("same_xy") else f32dev(cfg["y"])
+    # targets that are the first M sources go in as that view of x (the
+    # library projects them once)
+    if cfg.get("same_xy"):
+        y = x
+    elif cfg.get("targets_prefix"):
+        y = x[: cfg["M"]]
+    else:
+        y = f32dev(cfg["y"])
     out = torch.empty(cfg["M"], dtype=torch.float32, device="cuda")
     ones = torch.ones(cfg["M"], dtype=torch.float32, device="cuda")
 
@@ -269,7 +276,7 @@ def run_form(name, cfg, steps, warmup, proj="fp32", grad=False, err_targets=0,
     if not res["fused"] and "project" in res["phases_us_per_step"]:
         # the stored projection GEMM on the matrix cores: 2 d P flops per
         # projected point (once when sources = targets)
-        pts = cfg["N"] + (0 if cfg.get("same_xy") else cfg["M"])
+        pts = cfg["N"] + (0 if cfg.get("same_xy") or cfg.get("targets_prefix") else cfg["M"])
         flops = 2.0 * pts * cfg["d"] * cfg["P"]
         t = res["phases_us_per_step"]["project"] * 1e-6
         if proj == "bf16":

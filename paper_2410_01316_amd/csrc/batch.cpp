@@ -169,7 +169,7 @@ void fused_tasks(int i, const BatchProblem& d, const fastsum_problem_io& q, int 
         }
     }
     for (int a = 0; a < (P + 1) / 2; ++a) ph[kBatchFftconv].push_back({i, a, 0, 0});
-    const int64_t tile = fused_gather_tile();
+    const int64_t tile = fused_gather_tile(0, 4);    // batched plans: narrow grids
     const int gtiles = (int)((q.M + tile - 1) / tile);
     for (int r = 0; r < d.ngroup; ++r)
         for (int t = 0; t < gtiles; ++t) {
@@ -410,7 +410,8 @@ fastsum_status fastsum_batch_create(const fastsum_params* common, const fastsum_
     }
     b->fused = (common->flags & FASTSUM_FLAG_MATERIALIZE) == 0;
     for (int i = 0; i < n_problems; ++i)
-        b->fused = b->fused && fused_supported(b->plans[i].r.p.d, b->plans[i].geom.nr);
+        b->fused = b->fused && fused_supported(b->plans[i].r.p.d, b->plans[i].geom.nr) &&
+                   !fused_wide(b->plans[i].geom.nr);
     if (b->fused)
         for (int i = 0; i < n_problems; ++i) {
             split_dirs_host(probs[i].xi, b->plans[i].r.p.d, b->P, Ats[i]);

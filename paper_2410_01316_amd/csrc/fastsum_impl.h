@@ -178,8 +178,11 @@ inline int split_kblocks(int d) { return (d + 31) / 32; }
 
 // true if the fused kernels handle dimension d and grids of nr cells
 bool fused_supported(int d, int nr);
-// targets per fused gather workgroup
-int64_t fused_gather_tile();
+// grids too wide for the narrow fused kernels (16 nr > 16384 cells): the
+// wide variants (batched plans take only narrow grids)
+bool fused_wide(int nr);
+// targets per fused gather workgroup (grids of nr cells, window width W)
+int64_t fused_gather_tile(int nr, int W);
 // resident workgroups per CU of the fused spread and gather kernels
 void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_blocks);
 // bytes of the split tiles of `rows` rows of dimension d

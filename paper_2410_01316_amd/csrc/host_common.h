@@ -64,7 +64,7 @@ void split_dirs_host(const float* xi, int d, int P, std::vector<uint16_t>& out);
 // of the plan's rule for grids of nr stored cells
 int64_t fused_chunk_len(int64_t N, int nchunk);
 int fused_chunks(int64_t N, int P, int64_t slots, int nr);
-int fused_dir_range(int64_t M, int P, int64_t slots);
+int fused_dir_range(int64_t M, int P, int64_t slots, int nr, int W);
 int64_t round_up(int64_t v, int64_t m);
 fastsum_status status_of(hipError_t e);
 

@@ -993,10 +993,16 @@ constexpr int kSpreadBlock = 512;                          // 8 waves
 constexpr int kSpreadWaves = kSpreadBlock / 64;
 constexpr int kFuseAcc = 32;                               // FP32 cell accumulators per thread
 constexpr int kFuseMaxCells = kFuseAcc * kSpreadBlock;     // kFuseDirs * nr <= this
+// wide grids (kFuseDirs * nr up to 16 x 2048, e.g. the energy kernel at
+// T = 0.45): twice the accumulators, one workgroup per CU, and the gathers
+// stage one group's grids at a time (two would not fit in LDS)
+constexpr int kFuseAccWide = 64;
+constexpr int kFuseMaxCellsWide = kFuseAccWide * kSpreadBlock;
 constexpr int kGatherBlock = 512;                          // 8 waves, one workgroup per CU
 constexpr int kGatherWaves = kGatherBlock / 64;
 constexpr int kGatherNB = 8;                               // 16-target batches per wave
-constexpr int kGatherTargets = kGatherWaves * kGatherNB * 16;
+// wide grids: fewer batches (registers; W = 8 takes three)
+constexpr int gather_nb(bool wide, int W) { return !wide ? kGatherNB : (W >= 8 ? 3 : 4); }
 constexpr int kDmaBytes = 64 * 16;                         // one wave's 16-byte LDS-direct loads
 
 // split_points_kernel: one thread per (tile, lane), all k-blocks; rows >= N
@@ -1143,7 +1149,7 @@ __device__ __forceinline__ f32x4 split_mfma(const SplitOp<KB>& a, const SplitOp<
 // spread_tile) flushed after every slice into per-thread FP32 accumulators.
 // v = <xi_p, x_n / R>; x~ = pscale v with pscale = tau R.  The range check
 // of these points was done when they were split.
-template <int W, int KB>
+template <int W, int KB, int ACC>
 __device__ __forceinline__ void spread_fused_body(
     int* cells, const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
     const float* __restrict__ w, int P, const GridGeom& g, float pscale, int64_t chunk_len,
@@ -1155,9 +1161,9 @@ __device__ __forceinline__ void spread_fused_body(
     const int ncell = kFuseDirs * g.nr;
     SplitOp<KB> dop;
     load_split<KB>(dop, At, dgroup, lane);
-    float acc[kFuseAcc];
+    float acc[ACC];
 #pragma unroll
-    for (int q = 0; q < kFuseAcc; ++q) acc[q] = 0.f;
+    for (int q = 0; q < ACC; ++q) acc[q] = 0.f;
     for (int j = tid; j < ncell; j += kSpreadBlock) cells[j] = 0;
     __syncthreads();
     int* gcol = cells + c * g.nr;                     // grid of direction p0 + c
@@ -1210,7 +1216,7 @@ __device__ __forceinline__ void spread_fused_body(
         __syncthreads();
         const float unscale = ldexpf(1.f, -k);
 #pragma unroll
-        for (int q = 0; q < kFuseAcc; ++q) {
+        for (int q = 0; q < ACC; ++q) {
             const int j = tid + q * kSpreadBlock;
             if (j < ncell) {
                 acc[q] = fmaf((float)cells[j], unscale, acc[q]);
@@ -1224,20 +1230,20 @@ __device__ __forceinline__ void spread_fused_body(
     const int nvalid = min(kFuseDirs, P - p0) * g.nr;
     float* __restrict__ dst = partial + ((int64_t)chunk * P + p0) * g.nr;
 #pragma unroll
-    for (int q = 0; q < kFuseAcc; ++q) {
+    for (int q = 0; q < ACC; ++q) {
         const int j = tid + q * kSpreadBlock;
         if (j < nvalid) dst[j] = acc[q];
     }
 }
 
 // workgroup (x, y): direction group x, source chunk y
-template <int W, int KB>
+template <int W, int KB, int ACC>
 __global__ __launch_bounds__(kSpreadBlock) void spread_fused_kernel(
     const uint16_t* __restrict__ Xt, int64_t N, const uint16_t* __restrict__ At,
     const float* __restrict__ w, int P, GridGeom g, float pscale, int64_t chunk_len,
     const float* __restrict__ slice_max, WindowArgs win, float* __restrict__ partial) {
     extern __shared__ int cells[];
-    spread_fused_body<W, KB>(cells, Xt, N, At, w, P, g, pscale, chunk_len, slice_max, win,
+    spread_fused_body<W, KB, ACC>(cells, Xt, N, At, w, P, g, pscale, chunk_len, slice_max, win,
                              partial, blockIdx.x, blockIdx.y);
 }
 
@@ -1258,22 +1264,25 @@ __device__ __forceinline__ void gather_stage(const float* __restrict__ grid, int
 }
 
 // Gather with projections computed in registers.  A workgroup owns the
-// kGatherTargets targets of tile `tile` and the direction range `range`
+// TGT = 128 NB targets of tile `tile` (NB = gather_nb(WIDE, W)) and
+// the direction range `range`
 // (prange directions, a multiple of kFuseDirs).  The grids of each group of 16
 // directions are staged in one of two LDS buffers while the previous group
-// is interpolated; lane (c, r) holds directions 4r .. 4r+3 of target c of
-// each batch.  Per target the four directions are summed in FP32, the
-// groups in FP64.
-template <int W, int KB>
+// is interpolated (WIDE: one buffer, refilled after each group); lane (c, r)
+// holds directions 4r .. 4r+3 of target c of each batch.  Per target the
+// four directions are summed in FP32, the groups in FP64.
+template <int W, int KB, bool WIDE>
 __device__ __forceinline__ void gather_fused_body(
     float* gls, const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At,
     int P, const GridGeom& g, float pscale, const float* __restrict__ grid, int prange,
     int stage, const WindowArgs& win, double* __restrict__ spart, int64_t ldm, int tile,
     int range) {
+    constexpr int NB = gather_nb(WIDE, W);                         // batches per wave
+    constexpr int TGT = kGatherWaves * NB * 16;                    // targets per workgroup
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, r = lane >> 4;
-    const int64_t mb = (int64_t)tile * kGatherTargets;
-    const int64_t tw = (mb + wave * (kGatherNB * 16)) / 16;   // wave's first target tile
+    const int64_t mb = (int64_t)tile * TGT;
+    const int64_t tw = (mb + wave * (NB * 16)) / 16;   // wave's first target tile
     const int p_begin = range * prange;
     const int p_end = min(P, p_begin + prange);
     gather_stage(grid, p_begin, min(kFuseDirs, p_end - p_begin), g.nr, gls, wave, lane);
@@ -1281,13 +1290,13 @@ __device__ __forceinline__ void gather_fused_body(
     const int64_t ntiles = (M + 15) / 16;
     const __amdgpu_buffer_rsrc_t ys =
         buffer_rsrc(Yt + tw * KB * 2 * (kSplitTileBytes / 2),
-                    max((int64_t)0, min((int64_t)kGatherNB, ntiles - tw)) * KB * 2 * kSplitTileBytes);
-    SplitOp<KB> yop[kGatherNB];
+                    max((int64_t)0, min((int64_t)NB, ntiles - tw)) * KB * 2 * kSplitTileBytes);
+    SplitOp<KB> yop[NB];
 #pragma unroll
-    for (int b = 0; b < kGatherNB; ++b) load_split<KB>(yop[b], ys, b, lane);
-    double accd[kGatherNB];
+    for (int b = 0; b < NB; ++b) load_split<KB>(yop[b], ys, b, lane);
+    double accd[NB];
 #pragma unroll
-    for (int b = 0; b < kGatherNB; ++b) accd[b] = 0.0;
+    for (int b = 0; b < NB; ++b) accd[b] = 0.0;
     const WinEval<W> ev(g, win, pscale);
     // Projections of all batches on one group, k-block by k-block across
     // the batches (independent accumulations), then the interpolation.
@@ -1295,26 +1304,26 @@ __device__ __forceinline__ void gather_fused_body(
     // whatever its LDS row holds and the result is masked to zero by bits
     // (a select here would be turned into a branch around the LDS reads).
     auto group = [&](int np, const float* gb, const SplitOp<KB>& dop) {
-        f32x4 pr[kGatherNB];
+        f32x4 pr[NB];
 #pragma unroll
-        for (int b = 0; b < kGatherNB; ++b) pr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NB; ++b) pr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
-            for (int b = 0; b < kGatherNB; ++b)
+            for (int b = 0; b < NB; ++b)
                 pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.hi[kb], yop[b].lo[kb], pr[b], 0, 0, 0);
 #pragma unroll
-            for (int b = 0; b < kGatherNB; ++b)
+            for (int b = 0; b < NB; ++b)
                 pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.lo[kb], yop[b].hi[kb], pr[b], 0, 0, 0);
         }
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-            for (int b = 0; b < kGatherNB; ++b)
+            for (int b = 0; b < NB; ++b)
                 // C[dir][target]: lane holds directions 4r + i of target c
                 pr[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(dop.hi[kb], yop[b].hi[kb], pr[b], 0, 0, 0);
 #pragma unroll
-        for (int b = 0; b < kGatherNB; ++b) {
+        for (int b = 0; b < NB; ++b) {
             float t = 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -1333,46 +1342,70 @@ __device__ __forceinline__ void gather_fused_body(
     // still reads the buffer about to be refilled.
     SplitOp<KB> da, db;
     load_split<KB>(da, At, p_begin / kFuseDirs, lane);
-    float* buf0 = gls;
-    float* buf1 = gls + stage;
-    for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        const int p1 = p0 + kFuseDirs;
-        if (p1 < p_end) {
-            gather_stage(grid, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
-            load_split<KB>(db, At, p1 / kFuseDirs, lane);
+    if constexpr (WIDE) {
+        // one buffer: after a group every wave leaves it before the next
+        // group's grids go in; the next direction operand still loads
+        // during the group
+        for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p1 = p0 + kFuseDirs;
+            if (p1 < p_end) load_split<KB>(db, At, p1 / kFuseDirs, lane);
+            group(min(kFuseDirs, p_end - p0), gls, da);
+            if (p1 >= p_end) break;
+            __syncthreads();
+            gather_stage(grid, p1, min(kFuseDirs, p_end - p1), g.nr, gls, wave, lane);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p2 = p1 + kFuseDirs;
+            if (p2 < p_end) load_split<KB>(da, At, p2 / kFuseDirs, lane);
+            group(min(kFuseDirs, p_end - p1), gls, db);
+            if (p2 >= p_end) break;
+            __syncthreads();
+            gather_stage(grid, p2, min(kFuseDirs, p_end - p2), g.nr, gls, wave, lane);
         }
-        group(min(kFuseDirs, p_end - p0), buf0, da);
-        if (p1 >= p_end) break;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        const int p2 = p1 + kFuseDirs;
-        if (p2 < p_end) {
-            gather_stage(grid, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
-            load_split<KB>(da, At, p2 / kFuseDirs, lane);
+    } else {
+        float* buf0 = gls;
+        float* buf1 = gls + stage;
+        for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p1 = p0 + kFuseDirs;
+            if (p1 < p_end) {
+                gather_stage(grid, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
+                load_split<KB>(db, At, p1 / kFuseDirs, lane);
+            }
+            group(min(kFuseDirs, p_end - p0), buf0, da);
+            if (p1 >= p_end) break;
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p2 = p1 + kFuseDirs;
+            if (p2 < p_end) {
+                gather_stage(grid, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
+                load_split<KB>(da, At, p2 / kFuseDirs, lane);
+            }
+            group(min(kFuseDirs, p_end - p1), buf1, db);
         }
-        group(min(kFuseDirs, p_end - p1), buf1, db);
     }
     // sum the four lane groups r holding the same targets
 #pragma unroll
-    for (int b = 0; b < kGatherNB; ++b) {
+    for (int b = 0; b < NB; ++b) {
         double v = accd[b];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
-        const int64_t m = mb + wave * (kGatherNB * 16) + 16 * b + c;
+        const int64_t m = mb + wave * (NB * 16) + 16 * b + c;
         if (r == 0 && m < M) spart[(int64_t)range * ldm + m] = v;
     }
 }
 
 // workgroup (x, y): target tile x, direction range y
-template <int W, int KB>
+template <int W, int KB, bool WIDE>
 __global__ __launch_bounds__(kGatherBlock) void gather_fused_kernel(
     const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At, int P,
     GridGeom g, float pscale, const float* __restrict__ grid, int prange, int stage,
     WindowArgs win, double* __restrict__ spart, int64_t ldm) {
-    extern __shared__ float gls[];                    // 2 x stage floats
-    gather_fused_body<W, KB>(gls, Yt, M, At, P, g, pscale, grid, prange, stage, win, spart, ldm,
+    extern __shared__ float gls[];                    // 2 x stage floats (WIDE: 1 x)
+    gather_fused_body<W, KB, WIDE>(gls, Yt, M, At, P, g, pscale, grid, prange, stage, win, spart, ldm,
                              blockIdx.x, blockIdx.y);
 }
 
@@ -1392,7 +1425,7 @@ constexpr int kGradNB = 4;                                   // 16-target batche
 constexpr int kGradTargets = kGatherWaves * kGradNB * 16;
 constexpr int kGradMaxDC = kSplitMaxD / 16;
 
-template <int W, int KB>
+template <int W, int KB, bool WIDE>
 __global__ __launch_bounds__(kGatherBlock) void gather_grad_fused_kernel(
     const uint16_t* __restrict__ Yt, int64_t M, const uint16_t* __restrict__ At,
     const float* __restrict__ Ab, int DC, int P, GridGeom g, float pscale,
@@ -1467,25 +1500,47 @@ __global__ __launch_bounds__(kGatherBlock) void gather_grad_fused_kernel(
     SplitOp<KB> da, db;
     load_split<KB>(da, At, p_begin / kFuseDirs, lane);
     float* buf0 = gls;
-    float* buf1 = gls + stage;
-    for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        const int p1 = p0 + kFuseDirs;
-        if (p1 < p_end) {
-            gather_stage(grid_d, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
-            load_split<KB>(db, At, p1 / kFuseDirs, lane);
-        }
-        group(min(kFuseDirs, p_end - p0), buf0, da, p0 / kFuseDirs);
-        if (p1 >= p_end) break;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        const int p2 = p1 + kFuseDirs;
-        if (p2 < p_end) {
+    if constexpr (WIDE) {
+        // one buffer, refilled after each group (see gather_fused_body)
+        for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p1 = p0 + kFuseDirs;
+            if (p1 < p_end) load_split<KB>(db, At, p1 / kFuseDirs, lane);
+            group(min(kFuseDirs, p_end - p0), buf0, da, p0 / kFuseDirs);
+            if (p1 >= p_end) break;
+            __syncthreads();
+            gather_stage(grid_d, p1, min(kFuseDirs, p_end - p1), g.nr, buf0, wave, lane);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p2 = p1 + kFuseDirs;
+            if (p2 < p_end) load_split<KB>(da, At, p2 / kFuseDirs, lane);
+            group(min(kFuseDirs, p_end - p1), buf0, db, p1 / kFuseDirs);
+            if (p2 >= p_end) break;
+            __syncthreads();
             gather_stage(grid_d, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
-            load_split<KB>(da, At, p2 / kFuseDirs, lane);
         }
-        group(min(kFuseDirs, p_end - p1), buf1, db, p1 / kFuseDirs);
+    } else {
+        float* buf1 = gls + stage;
+        for (int p0 = p_begin; p0 < p_end; p0 += 2 * kFuseDirs) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p1 = p0 + kFuseDirs;
+            if (p1 < p_end) {
+                gather_stage(grid_d, p1, min(kFuseDirs, p_end - p1), g.nr, buf1, wave, lane);
+                load_split<KB>(db, At, p1 / kFuseDirs, lane);
+            }
+            group(min(kFuseDirs, p_end - p0), buf0, da, p0 / kFuseDirs);
+            if (p1 >= p_end) break;
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            const int p2 = p1 + kFuseDirs;
+            if (p2 < p_end) {
+                gather_stage(grid_d, p2, min(kFuseDirs, p_end - p2), g.nr, buf0, wave, lane);
+                load_split<KB>(da, At, p2 / kFuseDirs, lane);
+            }
+            group(min(kFuseDirs, p_end - p1), buf1, db, p1 / kFuseDirs);
+        }
     }
     // lane (c, r) holds coordinates 16 q + 4 r + j of target c
     const int dcp = 16 * DC;
@@ -1517,44 +1572,51 @@ __global__ __launch_bounds__(kBlock) void grad_reduce_kernel(
     grad_y[e] = coef * v[m] * s;
 }
 
-template <int W, int KB>
+template <int W, int KB, int ACC>
 void launch_spread_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Xt,
                            int64_t N, const uint16_t* At, const float* w, int P,
                            const GridGeom& g, float pscale, int64_t chunk_len,
                            const float* slice_max, const WindowArgs& win, float* partial) {
-    hipLaunchKernelGGL((spread_fused_kernel<W, KB>), grid, dim3(kSpreadBlock), lds, stream, Xt, N,
-                       At, w, P, g, pscale, chunk_len, slice_max, win, partial);
+    static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&spread_fused_kernel<W, KB, ACC>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  ACC * kSpreadBlock * (int)sizeof(int));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((spread_fused_kernel<W, KB, ACC>), grid, dim3(kSpreadBlock), lds, stream,
+                       Xt, N, At, w, P, g, pscale, chunk_len, slice_max, win, partial);
 }
 
-template <int W, int KB>
+template <int W, int KB, bool WIDE>
 void launch_gather_fused_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Yt,
                            int64_t M, const uint16_t* At, int P, const GridGeom& g, float pscale,
                            const float* gridv, int prange, int stage, const WindowArgs& win,
                            double* spart, int64_t ldm) {
     static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_fused_kernel<W, KB>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_fused_kernel<W, KB, WIDE>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   2 * kFuseMaxCells * (int)sizeof(float));
         attr_set = true;
     }
-    hipLaunchKernelGGL((gather_fused_kernel<W, KB>), grid, dim3(kGatherBlock), lds, stream, Yt,
+    hipLaunchKernelGGL((gather_fused_kernel<W, KB, WIDE>), grid, dim3(kGatherBlock), lds, stream, Yt,
                        M, At, P, g, pscale, gridv, prange, stage, win, spart, ldm);
 }
 
-template <int W, int KB>
+template <int W, int KB, bool WIDE>
 void launch_gather_grad_t(dim3 grid, size_t lds, hipStream_t stream, const uint16_t* Yt,
                           int64_t M, const uint16_t* At, const float* Ab, int DC, int P,
                           const GridGeom& g, float pscale, const float* grid_d, int prange,
                           int stage, const WindowArgs& win, float* gpart, int64_t ldg) {
     static bool attr_set = false;      // dynamic LDS above 64 KB must be enabled per kernel
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_grad_fused_kernel<W, KB>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gather_grad_fused_kernel<W, KB, WIDE>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   2 * kFuseMaxCells * (int)sizeof(float));
         attr_set = true;
     }
-    hipLaunchKernelGGL((gather_grad_fused_kernel<W, KB>), grid, dim3(kGatherBlock), lds, stream,
+    hipLaunchKernelGGL((gather_grad_fused_kernel<W, KB, WIDE>), grid, dim3(kGatherBlock), lds, stream,
                        Yt, M, At, Ab, DC, P, g, pscale, grid_d, prange, stage, win, gpart, ldg);
 }
 
@@ -1569,17 +1631,23 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
     using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*,
                        const float*, int, int, const GridGeom&, float, const float*, int, int,
                        const WindowArgs&, float*, int64_t);
-    static const L t[3][2] = {{launch_gather_grad_t<4, 1>, launch_gather_grad_t<4, 2>},
-                              {launch_gather_grad_t<6, 1>, launch_gather_grad_t<6, 2>},
-                              {launch_gather_grad_t<8, 1>, launch_gather_grad_t<8, 2>}};
+    static const L t[2][3][2] = {
+        {{launch_gather_grad_t<4, 1, false>, launch_gather_grad_t<4, 2, false>},
+         {launch_gather_grad_t<6, 1, false>, launch_gather_grad_t<6, 2, false>},
+         {launch_gather_grad_t<8, 1, false>, launch_gather_grad_t<8, 2, false>}},
+        {{launch_gather_grad_t<4, 1, true>, launch_gather_grad_t<4, 2, true>},
+         {launch_gather_grad_t<6, 1, true>, launch_gather_grad_t<6, 2, true>},
+         {launch_gather_grad_t<8, 1, true>, launch_gather_grad_t<8, 2, true>}}};
     const int wi = W == 4 ? 0 : W == 6 ? 1 : W == 8 ? 2 : -1;
     if (wi < 0) return hipErrorInvalidValue;
     const int DC = (d + 15) / 16;
     const int stage = (kFuseDirs * g.nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
     const int nrange = (P + prange - 1) / prange;
     dim3 gd((unsigned)((M + kGradTargets - 1) / kGradTargets), (unsigned)nrange);
-    t[wi][split_kblocks(d) - 1](gd, (size_t)2 * stage * sizeof(float), stream, Yt, M, At, Ab, DC, P,
-                                g, pscale, grid_d, prange, stage, win, gpart, ldg);
+    const bool wide = fused_wide(g.nr);
+    t[wide][wi][split_kblocks(d) - 1](gd, (size_t)(wide ? 1 : 2) * stage * sizeof(float), stream,
+                                      Yt, M, At, Ab, DC, P, g, pscale, grid_d, prange, stage, win,
+                                      gpart, ldg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)((M * d + kBlock - 1) / kBlock)),
@@ -1588,10 +1656,14 @@ hipError_t launch_grad_fused(int W, const uint16_t* Yt, int64_t M, int d, const 
 }
 
 bool fused_supported(int d, int nr) {
-    return d >= 1 && d <= kSplitMaxD && kFuseDirs * nr <= kFuseMaxCells;
+    return d >= 1 && d <= kSplitMaxD && kFuseDirs * nr <= kFuseMaxCellsWide;
 }
 
-int64_t fused_gather_tile() { return kGatherTargets; }
+bool fused_wide(int nr) { return kFuseDirs * nr > kFuseMaxCells; }
+
+int64_t fused_gather_tile(int nr, int W) {
+    return (int64_t)kGatherWaves * 16 * gather_nb(fused_wide(nr), W);
+}
 
 int64_t split_tiles_bytes(int64_t rows, int d) {
     return (rows + 15) / 16 * split_kblocks(d) * 2 * kSplitTileBytes;
@@ -1613,16 +1685,28 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
     *spread_blocks = 1;
     *gather_blocks = 1;
     if (!fused_supported(d, nr)) return;
+    const bool wide = fused_wide(nr);
     const void* sk = nullptr;
     const void* gk = nullptr;
     // occupancy is set by LDS and registers; the larger operand shape
     // stands for both
     switch (W) {
-        case 4: sk = (const void*)&spread_fused_kernel<4, 2>; gk = (const void*)&gather_fused_kernel<4, 2>; break;
-        case 6: sk = (const void*)&spread_fused_kernel<6, 2>; gk = (const void*)&gather_fused_kernel<6, 2>; break;
-        default: sk = (const void*)&spread_fused_kernel<8, 2>; gk = (const void*)&gather_fused_kernel<8, 2>; break;
+        case 4:
+            sk = wide ? (const void*)&spread_fused_kernel<4, 2, kFuseAccWide> : (const void*)&spread_fused_kernel<4, 2, kFuseAcc>;
+            gk = wide ? (const void*)&gather_fused_kernel<4, 2, true> : (const void*)&gather_fused_kernel<4, 2, false>;
+            break;
+        case 6:
+            sk = wide ? (const void*)&spread_fused_kernel<6, 2, kFuseAccWide> : (const void*)&spread_fused_kernel<6, 2, kFuseAcc>;
+            gk = wide ? (const void*)&gather_fused_kernel<6, 2, true> : (const void*)&gather_fused_kernel<6, 2, false>;
+            break;
+        default:
+            sk = wide ? (const void*)&spread_fused_kernel<8, 2, kFuseAccWide> : (const void*)&spread_fused_kernel<8, 2, kFuseAcc>;
+            gk = wide ? (const void*)&gather_fused_kernel<8, 2, true> : (const void*)&gather_fused_kernel<8, 2, false>;
+            break;
     }
     const int stage = (kFuseDirs * nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
+    (void)hipFuncSetAttribute(sk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kFuseMaxCellsWide * (int)sizeof(int));
     (void)hipFuncSetAttribute(gk, hipFuncAttributeMaxDynamicSharedMemorySize,
                               2 * kFuseMaxCells * (int)sizeof(float));
     int b = 0;
@@ -1630,7 +1714,7 @@ void fused_occupancy(int W, int d, int nr, int* spread_blocks, int* gather_block
                                                      (size_t)kFuseDirs * nr * sizeof(int)) == hipSuccess && b > 0)
         *spread_blocks = b;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gk, kGatherBlock,
-                                                     (size_t)2 * stage * sizeof(float)) == hipSuccess && b > 0)
+                                                     (size_t)(wide ? 1 : 2) * stage * sizeof(float)) == hipSuccess && b > 0)
         *gather_blocks = b;
 }
 
@@ -1643,16 +1727,21 @@ hipError_t launch_spread_fused(int W, const uint16_t* Xt, int64_t N, int d, cons
     using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*,
                        const float*, int, const GridGeom&, float, int64_t, const float*,
                        const WindowArgs&, float*);
-    static const L t[3][2] = {{launch_spread_fused_t<4, 1>, launch_spread_fused_t<4, 2>},
-                              {launch_spread_fused_t<6, 1>, launch_spread_fused_t<6, 2>},
-                              {launch_spread_fused_t<8, 1>, launch_spread_fused_t<8, 2>}};
+    static const L t[2][3][2] = {
+        {{launch_spread_fused_t<4, 1, kFuseAcc>, launch_spread_fused_t<4, 2, kFuseAcc>},
+         {launch_spread_fused_t<6, 1, kFuseAcc>, launch_spread_fused_t<6, 2, kFuseAcc>},
+         {launch_spread_fused_t<8, 1, kFuseAcc>, launch_spread_fused_t<8, 2, kFuseAcc>}},
+        {{launch_spread_fused_t<4, 1, kFuseAccWide>, launch_spread_fused_t<4, 2, kFuseAccWide>},
+         {launch_spread_fused_t<6, 1, kFuseAccWide>, launch_spread_fused_t<6, 2, kFuseAccWide>},
+         {launch_spread_fused_t<8, 1, kFuseAccWide>, launch_spread_fused_t<8, 2, kFuseAccWide>}}};
     const int wi = W == 4 ? 0 : W == 6 ? 1 : W == 8 ? 2 : -1;
     if (wi < 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(slice_max_kernel, dim3((unsigned)((N + kSlice - 1) / kSlice)), dim3(kBlock),
                        0, stream, w, N, slice_max);
     dim3 grid((unsigned)((P + kFuseDirs - 1) / kFuseDirs), (unsigned)nchunk);
-    t[wi][split_kblocks(d) - 1](grid, (size_t)kFuseDirs * g.nr * sizeof(int), stream, Xt, N, At,
-                                w, P, g, pscale, chunk_len, slice_max, win, partial);
+    t[fused_wide(g.nr)][wi][split_kblocks(d) - 1](grid, (size_t)kFuseDirs * g.nr * sizeof(int),
+                                                  stream, Xt, N, At, w, P, g, pscale, chunk_len,
+                                                  slice_max, win, partial);
     return hipGetLastError();
 }
 
@@ -1664,17 +1753,24 @@ hipError_t launch_gather_fused(int W, const uint16_t* Yt, int64_t M, int d, cons
     using L = void (*)(dim3, size_t, hipStream_t, const uint16_t*, int64_t, const uint16_t*, int,
                        const GridGeom&, float, const float*, int, int, const WindowArgs&, double*,
                        int64_t);
-    static const L t[3][2] = {{launch_gather_fused_t<4, 1>, launch_gather_fused_t<4, 2>},
-                              {launch_gather_fused_t<6, 1>, launch_gather_fused_t<6, 2>},
-                              {launch_gather_fused_t<8, 1>, launch_gather_fused_t<8, 2>}};
+    static const L t[2][3][2] = {
+        {{launch_gather_fused_t<4, 1, false>, launch_gather_fused_t<4, 2, false>},
+         {launch_gather_fused_t<6, 1, false>, launch_gather_fused_t<6, 2, false>},
+         {launch_gather_fused_t<8, 1, false>, launch_gather_fused_t<8, 2, false>}},
+        {{launch_gather_fused_t<4, 1, true>, launch_gather_fused_t<4, 2, true>},
+         {launch_gather_fused_t<6, 1, true>, launch_gather_fused_t<6, 2, true>},
+         {launch_gather_fused_t<8, 1, true>, launch_gather_fused_t<8, 2, true>}}};
     const int wi = W == 4 ? 0 : W == 6 ? 1 : W == 8 ? 2 : -1;
     if (wi < 0) return hipErrorInvalidValue;
     // one staging buffer: the group's grids rounded up to whole 1 KB pieces
     const int stage = (kFuseDirs * g.nr + kDmaBytes / 4 - 1) / (kDmaBytes / 4) * (kDmaBytes / 4);
-    dim3 gd((unsigned)((M + kGatherTargets - 1) / kGatherTargets),
+    const int64_t tgt = fused_gather_tile(g.nr, W);
+    dim3 gd((unsigned)((M + tgt - 1) / tgt),
             (unsigned)((P + prange - 1) / prange));
-    t[wi][split_kblocks(d) - 1](gd, (size_t)2 * stage * sizeof(float), stream, Yt, M, At, P, g,
-                                pscale, grid, prange, stage, win, spart, ldm);
+    const bool wide = fused_wide(g.nr);
+    t[wide][wi][split_kblocks(d) - 1](gd, (size_t)(wide ? 1 : 2) * stage * sizeof(float), stream,
+                                      Yt, M, At, P, g, pscale, grid, prange, stage, win, spart,
+                                      ldm);
     return hipGetLastError();
 }
 
@@ -1808,10 +1904,10 @@ batch_spread_fused_kernel(
         const BatchTask tk = tasks[t];
         const BatchProblem& pr = probs[tk.prob];
         if (pr.kb == 1)
-            spread_fused_body<W, 1>(bcells, pr.xt, pr.N, pr.at, pr.w, P, pr.g, pr.pscale,
+            spread_fused_body<W, 1, kFuseAcc>(bcells, pr.xt, pr.N, pr.at, pr.w, P, pr.g, pr.pscale,
                                     pr.chunk_len, pr.slice_max, win, pr.partial, tk.a, tk.b);
         else
-            spread_fused_body<W, 2>(bcells, pr.xt, pr.N, pr.at, pr.w, P, pr.g, pr.pscale,
+            spread_fused_body<W, 2, kFuseAcc>(bcells, pr.xt, pr.N, pr.at, pr.w, P, pr.g, pr.pscale,
                                     pr.chunk_len, pr.slice_max, win, pr.partial, tk.a, tk.b);
         __syncthreads();
     }
@@ -1830,10 +1926,10 @@ __global__ __launch_bounds__(kGatherBlock) void batch_gather_fused_kernel(
         // no wave may still read the staging buffers of the previous task
         __syncthreads();
         if (pr.kb == 1)
-            gather_fused_body<W, 1>(bgls, yt, pr.M, pr.at, P, pr.g, pr.pscale, pr.grid, pr.pg,
+            gather_fused_body<W, 1, false>(bgls, yt, pr.M, pr.at, P, pr.g, pr.pscale, pr.grid, pr.pg,
                                     stage, win, pr.spart, pr.ldm, tk.a, tk.b);
         else
-            gather_fused_body<W, 2>(bgls, yt, pr.M, pr.at, P, pr.g, pr.pscale, pr.grid, pr.pg,
+            gather_fused_body<W, 2, false>(bgls, yt, pr.M, pr.at, P, pr.g, pr.pscale, pr.grid, pr.pg,
                                     stage, win, pr.spart, pr.ldm, tk.a, tk.b);
     }
 }

@@ -326,11 +326,11 @@ int fused_chunks(int64_t N, int P, int64_t slots, int nr) {
     return (int)best;
 }
 
-int fused_dir_range(int64_t M, int P, int64_t slots) {
+int fused_dir_range(int64_t M, int P, int64_t slots, int nr, int W) {
     // ranges of whole 16-direction groups; at least three rounds of
     // workgroups when P allows, then the fullest rounds (fewest ranges
     // among near ties: each range re-reads the targets)
-    const int64_t tiles = (M + fused_gather_tile() - 1) / fused_gather_tile();
+    const int64_t tiles = (M + fused_gather_tile(nr, W) - 1) / fused_gather_tile(nr, W);
     const int64_t groups = (P + kFuseDirs - 1) / kFuseDirs;
     int64_t best_pr = groups * kFuseDirs;
     double best_eff = -1.0;
@@ -647,7 +647,7 @@ fastsum_status fused_sum(fastsum_plan_s* pl, const uint16_t* xt, const float* w,
                               grid_d ? pl->mult_d : nullptr, grid, grid_d, st));
     }
     const int prange = pl->tune_dir_range > 0 ? pl->tune_dir_range
-                                              : fused_dir_range(M, P, pl->gather_slots);
+                                              : fused_dir_range(M, P, pl->gather_slots, pl->geom.nr, pl->W);
     const int nrange = (P + prange - 1) / prange;
     pl->last_nchunk = nchunk;
     pl->last_ngroup = nrange;

@@ -97,7 +97,7 @@ def test_mmd_full_size_gradients(kernel):
     g3 = O.grad_y_fourier(kernel, xo, yo[idx], wo, xio[:, :2], cfg["scale"], cfg["n_ft"], _tau(cfg))
     e3 = rel_l2(g2[idx], g3)
     s_f, g_f, fused = grads(cfg)
-    assert fused == (1 if kernel == "gauss" else 0)     # the energy grids are too wide to fuse
+    assert fused == 1                      # the energy kernel on the wide fused kernels
     g1 = O.grad_y_direct(kernel, xo, yo[idx], wo, cfg["scale"])
     e1 = rel_l2(g_f[idx], g1)
     msg = f"{kernel} mmd full size: 2 dirs grad_y vs O3 {e3:.2e}, 512 dirs vs direct {e1:.2e}"

@@ -125,6 +125,50 @@ def test_fused_energy_and_laplace():
         assert _err3(cfg, s_f) < 2e-5
 
 
+@pytest.mark.parametrize("d,N,M,P,W,same", [(3, 5001, 2077, 37, 4, False),
+                                            (20, 3000, 1300, 64, 6, False),
+                                            (64, 1500, 1500, 21, 8, True)])
+def test_fused_wide_grids_equal_stored(d, N, M, P, W, same):
+    """Energy kernel at N_ft = 1024, T = 0.45: grids of ~1856 cells, past the
+    narrow fused kernels (16 nr > 16384 cells): the wide spread (64 cell
+    accumulators per thread) and the one-buffer gathers (fewer target
+    batches; W = 8 the fewest) against the stored plan on the same inputs,
+    the sum and all three adjoints, element by element (ragged tiles and
+    direction groups, sources equal to targets); and the fused sum against
+    O3 on sampled targets."""
+    rng = np.random.default_rng(d * 11 + P)
+    x = rng.standard_normal((N, d)) * 0.7
+    y = x if same else rng.standard_normal((M, d)) * 0.7
+    M = y.shape[0]
+    w = rng.standard_normal(N)
+    from workloads.configs import bound_R
+    cfg = dict(x=x, y=y, w=w, xi=directions("distance", d, P, d), kernel="energy", scale=1.0,
+               n_ft=1024, R=bound_R(x, y))
+    v = rng.standard_normal(M)
+    res = {}
+    for mat in (False, True):
+        plan = gpu_plan(cfg, grad=True, materialize=mat, window_w=W)
+        info = plan.info()
+        assert info["fused"] == (0 if mat else 1)
+        assert 16 * info["grid_nr"] > 16384
+        xd, wd = to_dev(x, w)
+        yd = xd if same else to_dev(y)[0]
+        s = plan(xd, wd, yd)
+        gx, gy, gw = plan.grad(to_dev(v)[0], want_x=True)
+        plan.check()
+        res[mat] = [g.cpu().numpy().astype(np.float64) for g in (s, gy, gw, gx)]
+    es = err_scale(res[False][0], res[True][0], _sabs(cfg))
+    ey, ew, ex = [rel_l2(a, b) for a, b in zip(res[False][1:], res[True][1:])]
+    print(f"wide d={d} W={W} nr={info['grid_nr']}: s {es:.2e} grad_y {ey:.2e} grad_w {ew:.2e} "
+          f"grad_x {ex:.2e}")
+    assert es < 1e-6 and ey < 5e-5 and ew < 5e-5 and ex < 5e-5
+    idx = np.sort(np.random.default_rng(5).choice(M, 48, replace=False))
+    sub = dict(cfg, y=y[idx])
+    e3 = err_scale(res[False][0][idx], _o3(sub), _sabs(sub))
+    print(f"wide d={d} W={W}: fused vs O3 on 48 targets {e3:.2e}")
+    assert e3 < 2e-5
+
+
 @pytest.mark.parametrize("d,N,M,P,same", [(3, 3001, 2077, 37, False), (20, 2500, 1300, 64, False),
                                           (50, 1800, 1800, 45, True), (64, 1000, 517, 16, False)])
 def test_fused_adjoint_equals_stored(d, N, M, P, same):

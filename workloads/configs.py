@@ -97,8 +97,9 @@ def make_config(name, kernel=None, frac=1.0, dirs=None, P=None, seed=None):
         sigma = median_rule_sigma(part, targ, rng) if kern != "energy" else 1.0
         P = P or 512
         xi = _cached_dirs(dirs or "distance", 20, P, 104)
+        # the targets (particles) are the first n sources
         cfg = dict(x=src, y=part, w=w, xi=xi, kernel=kern, scale=sigma,
-                   n_ft=1024)
+                   n_ft=1024, targets_prefix=True)
     else:
         raise ValueError(f"unknown workload {name!r}")
     cfg["name"] = name
