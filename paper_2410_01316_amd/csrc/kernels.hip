@@ -558,6 +558,7 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 // through the twiddle and the butterfly.  tw[m] = exp(-2 pi i m / n) is the
 // LDS copy of the table; sgn = +1 forward, -1 inverse (exp(+2 pi i ...), no
 // 1/n: the multiplier table carries the normalisation).
+
 __device__ __forceinline__ void dft4(float2 (&c)[4], float sgn) {
     const float2 t0 = cadd(c[0], c[2]), t1 = csub(c[0], c[2]), t2 = cadd(c[1], c[3]);
     const float2 d13 = csub(c[1], c[3]);
@@ -656,67 +657,88 @@ __device__ __forceinline__ void fftconv_tile(
     const float2* __restrict__ tw, const float2* __restrict__ mult,
     const float2* __restrict__ mult_d, float* __restrict__ grid, float* __restrict__ grid_d,
     int pair) {
+    constexpr int kPer = 2048 / kBlock;   // table entries per thread (n <= 2048)
+    constexpr int kInFlight = 8;          // chunk partials per direction loaded at once
     const int n = g.n;
+    const int tid = threadIdx.x;
     float2* twl = cbuf;
     float2* b0 = cbuf + n;
     float2* b1 = cbuf + 2 * n;
     float2* b2 = cbuf + 3 * n;            // only with derivative grids
     const int pa = 2 * pair, pb = pa + 1;
     const bool has_b = pb < P;
-    __syncthreads();               // LDS may still be read by a previous tile
-    // cells outside [lo, lo + nr) are zero; inside, the sum of the chunk
-    // partials of both directions, read as float4 (nr is a multiple of 4)
-    // with four chunks' loads in flight at a time
-    for (int j = threadIdx.x; j < n; j += kBlock) {
-        twl[j] = tw[j];
-        if (j < g.lo || j >= g.lo + g.nr) b0[j] = make_float2(0.f, 0.f);
+    // the twiddles and multipliers (tables shared by every pair) are loaded
+    // into registers first, so their latency overlaps the partials'
+    float2 twv[kPer], mv[kPer], mdv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int j = tid + q * kBlock;
+        if (j < n) {
+            twv[q] = tw[j];
+            mv[q] = mult[j];
+            if (grid_d != nullptr) mdv[q] = mult_d[j];
+        }
     }
+    __syncthreads();               // LDS may still be read by a previous tile
+    // inside [lo, lo + nr): the sum of the chunk partials of both directions
+    // (in chunk order), read as float4 (nr is a multiple of 4) with up to
+    // kInFlight chunks of both directions in flight
     const float4* __restrict__ pa4 = reinterpret_cast<const float4*>(partial + (int64_t)pa * g.nr);
     const float4* __restrict__ pb4 = reinterpret_cast<const float4*>(partial + (int64_t)(has_b ? pb : pa) * g.nr);
     const int64_t cstride4 = (int64_t)P * g.nr / 4;
-    for (int r4 = threadIdx.x; r4 < g.nr / 4; r4 += kBlock) {
+    for (int r4 = tid; r4 < g.nr / 4; r4 += kBlock) {
         float4 sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa;
-        int c = 0;
-        for (; c + 4 <= nchunk; c += 4) {
-            float4 va[4], vb[4];
+        for (int c0 = 0; c0 < nchunk; c0 += kInFlight) {
+            float4 va[kInFlight], vb[kInFlight];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                va[q] = pa4[(c + q) * cstride4 + r4];
-                vb[q] = pb4[(c + q) * cstride4 + r4];
+            for (int q = 0; q < kInFlight; ++q) {
+                if (c0 + q < nchunk) {
+                    va[q] = pa4[(c0 + q) * cstride4 + r4];
+                    vb[q] = pb4[(c0 + q) * cstride4 + r4];
+                }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                sa.x += va[q].x; sa.y += va[q].y; sa.z += va[q].z; sa.w += va[q].w;
-                sb.x += vb[q].x; sb.y += vb[q].y; sb.z += vb[q].z; sb.w += vb[q].w;
+            for (int q = 0; q < kInFlight; ++q) {
+                if (c0 + q < nchunk) {
+                    sa.x += va[q].x; sa.y += va[q].y; sa.z += va[q].z; sa.w += va[q].w;
+                    sb.x += vb[q].x; sb.y += vb[q].y; sb.z += vb[q].z; sb.w += vb[q].w;
+                }
             }
-        }
-        for (; c < nchunk; ++c) {
-            const float4 va = pa4[c * cstride4 + r4], vb = pb4[c * cstride4 + r4];
-            sa.x += va.x; sa.y += va.y; sa.z += va.z; sa.w += va.w;
-            sb.x += vb.x; sb.y += vb.y; sb.z += vb.z; sb.w += vb.w;
         }
         if (!has_b) sb = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2* dst = b0 + g.lo + 4 * r4;
-        dst[0] = make_float2(sa.x, sb.x);
-        dst[1] = make_float2(sa.y, sb.y);
-        dst[2] = make_float2(sa.z, sb.z);
-        dst[3] = make_float2(sa.w, sb.w);
+        const int j0 = g.lo + 4 * r4;
+        b0[j0] = make_float2(sa.x, sb.x);
+        b0[j0 + 1] = make_float2(sa.y, sb.y);
+        b0[j0 + 2] = make_float2(sa.z, sb.z);
+        b0[j0 + 3] = make_float2(sa.w, sb.w);
+    }
+    // cells outside [lo, lo + nr) are zero
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int j = tid + q * kBlock;
+        if (j < n) {
+            twl[j] = twv[q];
+            if (j < g.lo || j >= g.lo + g.nr) b0[j] = make_float2(0.f, 0.f);
+        }
     }
     __syncthreads();
     float2* spec = fft_lds(b0, b1, n, twl, false);
     float2* other = (spec == b0) ? b1 : b0;
     const int passes = grid_d ? 2 : 1;
     for (int pass = 0; pass < passes; ++pass) {
-        const float2* __restrict__ m = pass ? mult_d : mult;
         float* __restrict__ out = pass ? grid_d : grid;
         // with one pass the spectrum is multiplied in place; with two it is
         // kept for the second multiplier
         float2* wa = (passes == 1) ? spec : (pass == 0 ? other : spec);
         float2* wb = (passes == 1) ? other : b2;
-        for (int j = threadIdx.x; j < n; j += kBlock) wa[j] = cmul(spec[j], m[j]);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int j = tid + q * kBlock;
+            if (j < n) wa[j] = cmul(spec[j], pass ? mdv[q] : mv[q]);
+        }
         __syncthreads();
         const float2* res = fft_lds(wa, wb, n, twl, true);
-        for (int r = threadIdx.x; r < g.nr; r += kBlock) {
+        for (int r = tid; r < g.nr; r += kBlock) {
             const float2 v = res[g.lo + r];
             out[(int64_t)pa * g.nr + r] = v.x;
             if (has_b) out[(int64_t)pb * g.nr + r] = v.y;
@@ -1094,7 +1116,7 @@ hipError_t launch_clear_norms(unsigned* norms, hipStream_t stream) {
 
 hipError_t launch_point_norms(const float* X, int64_t N, int d, float scale, unsigned* slot,
                               hipStream_t stream) {
-    const int64_t waves = std::min<int64_t>(N, (int64_t)4096);
+    const int64_t waves = std::min<int64_t>(N, (int64_t)32768);   // 128 per CU
     hipLaunchKernelGGL(point_norms_kernel, dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, stream, X, N, d, scale, slot);
     return hipGetLastError();
