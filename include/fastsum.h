@@ -99,11 +99,11 @@ typedef enum {
  * direction's sum is stored in FP32 and their mean taken in FP64.  The only
  * approximation left is the slicing (eq. (3)); n_ft, window_w and
  * oversample are validated but unused.  Stores the projections.  With
- * FASTSUM_FLAG_GRAD, fastsum_grad_xyw is exact too: an ascending and a
- * descending sort of sources and targets give per direction the weight sums
- * over strictly smaller and strictly larger keys, i.e. the derivative
- * sum_n w_n sign(y~ - x~_n) with sign(0) = 0 where projections coincide, and
- * the transposed sums for grad_w.  The plan needs P * L < 2^32 with
+ * FASTSUM_FLAG_GRAD, fastsum_grad_xyw is exact too: one scan of the rows the
+ * exec sorted gives per direction the weight sums over strictly smaller and
+ * strictly larger keys (entries of equal key form runs, handled as one),
+ * i.e. the derivative sum_n w_n sign(y~ - x~_n) with sign(0) = 0 where
+ * projections coincide, and the transposed sums for grad_w.  The plan needs P * L < 2^32 with
  * L = round_up(n_max, 64) + round_up(m_max, 64), and about
  * 4 P L (keys) + 4 P L (sorted keys) + 4 P L (positions) + 8 P L (sort
  * workspace) + 6 P ldm (per-direction sums and their target offsets) +
@@ -227,7 +227,7 @@ FASTSUM_API fastsum_status fastsum_grad(fastsum_plan plan, const float* grad_s,
  *     interpolated at the sources and back-projected as for grad_y.
  * grad_w and grad_x share that transposed spreading and FFT.  Sorted plans
  * (FASTSUM_FLAG_SORTED) take the exact derivatives instead: t' is
- * -(c_d/tau) sum_n w_n sign(y~ - x~_n) from an ascending and a descending sort
+ * -(c_d/tau) sum_n w_n sign(y~ - x~_n) from the rows the last exec sorted
  * (sign(0) = 0), the source side likewise with v, and grad_w the transposed
  * sorted sums; only the requested outputs are computed.  The weights w of
  * the last exec must still be valid.  Asynchronous.
@@ -406,11 +406,29 @@ FASTSUM_API void fastsum_batch_destroy(fastsum_batch batch);
  *   stream  the steps run on it; the call returns after they finish
  * Allocates its workspace for the call (8 P d bytes plus partial sums of
  * at most 260 P ceil(2048 / ceil(P/64)) bytes).  FP32 arithmetic; the
- * randomisation of App. E (a random rotation) is the caller's.
+ * randomisation of App. E is fastsum_rotate_directions.
  * Errors: EINVAL, ENOMEM, EDEVICE.
  */
 FASTSUM_API fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t iters, double lr,
                                                 float* xi, void* stream);
+
+/*
+ * Randomised directions (App. E): a QMC design rotated by an orthogonal
+ * matrix Q drawn from the Haar measure keeps every direction uniformly
+ * distributed on the sphere, so the sliced estimator stays unbiased.  Row p
+ * of xi becomes Q xi_p / |Q xi_p|, (Q xi_p)_i = sum_j Q_ij (xi_p)_j (the
+ * renormalisation only removes rounding when Q is orthogonal).
+ *   q       device, d x d row-major FP32, caller-owned; the random draw is
+ *           the caller's (passed in as an input)
+ *   xi      device, P x d row-major (the layout of fastsum_distance_qmc),
+ *           replaced in place
+ *   d       1..64;  P >= 1
+ *   stream  the kernel runs on it; the call returns after it finishes
+ * FP32 products and sums.  A row that Q maps to zero becomes NaN.
+ * Errors: EINVAL (arguments), EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_rotate_directions(int32_t d, int32_t P, const float* q,
+                                                     float* xi, void* stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

@@ -23,7 +23,7 @@ from .kernels import (KERNELS, basis_F, basis_dF, energy_cd, sliced_ft,
                       truncated_coefficients)
 from .direct import kernel_sum_direct, kernel_sum_direct_gram, grad_y_direct
 from .sliced import kernel_sum_sliced, grad_sliced_energy
-from .qmc import distance_energy, distance_energy_grad, projected_adam
+from .qmc import distance_energy, distance_energy_grad, projected_adam, rotate_directions
 from .fourier import (kernel_sum_fourier, grad_y_fourier, grad_w_fourier, grad_x_fourier,
                       project)
 
@@ -32,5 +32,5 @@ __all__ = [
     "rescale_tau", "fourier_coefficients", "truncated_coefficients",
     "kernel_sum_direct", "kernel_sum_direct_gram", "grad_y_direct", "kernel_sum_sliced", "grad_sliced_energy",
     "kernel_sum_fourier", "grad_y_fourier", "grad_w_fourier", "grad_x_fourier", "project",
-    "distance_energy", "distance_energy_grad", "projected_adam",
+    "distance_energy", "distance_energy_grad", "projected_adam", "rotate_directions",
 ]

@@ -45,3 +45,13 @@ def projected_adam(xi0, iters, lr, b1=0.9, b2=0.999, eps=1e-12):
         xi = xi + step * (m / (1 - b1 ** it)) / (np.sqrt(v / (1 - b2 ** it)) + eps)
         xi /= np.linalg.norm(xi, axis=1, keepdims=True)
     return xi
+
+
+def rotate_directions(q, xi):
+    """The randomised design of App. E for a given orthogonal matrix q: every
+    direction (row of xi, shape (P, d)) mapped to q xi_p, then rescaled to
+    unit length (which only removes rounding when q is orthogonal)."""
+    q = np.asarray(q, dtype=np.float64)
+    xi = np.asarray(xi, dtype=np.float64)
+    out = xi @ q.T                         # row p: sum_j q[i, j] xi[p, j]
+    return out / np.linalg.norm(out, axis=1, keepdims=True)

@@ -84,6 +84,7 @@ SIGNATURES = {
     "fastsum_bound": (_st, [_vp, _i64, _vp, _i64, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_double)]),
     "fastsum_distance_qmc_noalloc": (_st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_double, _vp, _vp]),
+    "fastsum_rotate_directions": (_st, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
 }
 
 _lib = None

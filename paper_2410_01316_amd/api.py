@@ -239,9 +239,11 @@ def kernel_sum(x, y, w, xi, *, kernel, scale=1.0, n_ft=None, R=None, sorting=Fal
 def distance_qmc(d, P, *, iters=400, lr=None, seed=0, rotate=True, device=None):
     """Distance QMC directions (App. H) built on the GPU by
     fastsum_distance_qmc: `iters` projected Adam steps from P seeded i.i.d.
-    unit vectors (d <= 64), then, with `rotate`, a seeded random rotation
-    (App. E) so the sliced estimator stays unbiased.  Returns the (d, P)
-    float32 array of unit columns that Plan takes."""
+    unit vectors (d <= 64), then, with `rotate`, a seeded Haar-random
+    rotation (App. E) applied by fastsum_rotate_directions, so the sliced
+    estimator stays unbiased.  Only the random draws (the start and the
+    rotation matrix) are made here.  Returns the (d, P) float32 array of
+    unit columns that Plan takes."""
     lib = L.load()
     rng = np.random.default_rng(seed)
     x0 = rng.standard_normal((P, d))
@@ -255,13 +257,15 @@ def distance_qmc(d, P, *, iters=400, lr=None, seed=0, rotate=True, device=None):
     with torch.cuda.device(dev):
         st = lib.fastsum_distance_qmc(int(d), int(P), int(iters), float(lr), _ptr(t),
                                       _stream_ptr(dev))
-    L.check(st, "fastsum_distance_qmc")
-    xi = t.cpu().numpy().astype(np.float64).T
-    if rotate:
-        q, r = np.linalg.qr(rng.standard_normal((d, d)))
-        xi = (q * np.sign(np.diag(r))) @ xi
-    xi /= np.linalg.norm(xi, axis=0, keepdims=True)
-    return xi.astype(np.float32)
+        L.check(st, "fastsum_distance_qmc")
+        if rotate:
+            # a Haar draw: QR of a Gaussian matrix, columns signed by diag(R)
+            q, r = np.linalg.qr(rng.standard_normal((d, d)))
+            qd = torch.from_numpy((q * np.sign(np.diag(r))).astype(np.float32)).to(dev)
+            st = lib.fastsum_rotate_directions(int(d), int(P), _ptr(qd), _ptr(t),
+                                               _stream_ptr(dev))
+            L.check(st, "fastsum_rotate_directions")
+    return t.cpu().numpy().T.copy()
 
 
 def host_tables(kernel, d, n_ft, R, scale=1.0, T=0.0, gmax_factor=0.0, window_w=0,

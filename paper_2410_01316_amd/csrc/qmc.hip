@@ -113,6 +113,27 @@ __global__ __launch_bounds__(kQmcBlock) void qmc_step_kernel(
     if (on) xi[k] = xn * inv;
 }
 
+// Randomised design (App. E): row p of xi becomes Q xi_p / |Q xi_p|, Q
+// (d x d, row-major) applied as y_i = sum_j Q_ij x_j.  One wave per row,
+// lane i for coordinate i; the coordinates of the row reach every lane by
+// shuffles, so the row is replaced in place after it has been read whole.
+__global__ __launch_bounds__(kQmcBlock) void rotate_rows_kernel(
+    const float* __restrict__ q, float* __restrict__ xi, int P, int d) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * (kQmcBlock / 64) + (threadIdx.x >> 6);
+    if (p >= P) return;                        // whole waves; no barriers below
+    const bool on = lane < d;
+    const int64_t k = (int64_t)p * d + lane;
+    const float x = on ? xi[k] : 0.f;
+    float y = 0.f;
+    for (int j = 0; j < d; ++j) {
+        const float xj = __shfl(x, j, 64);
+        if (on) y = fmaf(q[(int64_t)lane * d + j], xj, y);
+    }
+    const float nrm = sqrtf(qmc_wave_sum(y * y));
+    if (on) xi[k] = y / nrm;
+}
+
 // q-chunks so that the gradient has about 2048 workgroups (at least 8 per
 // CU), each chunk a whole number of tiles
 int qmc_chunk_len(int P) {
@@ -162,6 +183,13 @@ hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* m,
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t rotate_directions(const float* q, float* xi, int P, int d, hipStream_t st) {
+    if (P < 1 || d < 1 || d > 64) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((P + kQmcBlock / 64 - 1) / (kQmcBlock / 64)));
+    hipLaunchKernelGGL(rotate_rows_kernel, grid, dim3(kQmcBlock), 0, st, q, xi, P, d);
+    return hipGetLastError();
 }
 
 }  // namespace fastsum

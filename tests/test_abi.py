@@ -150,3 +150,8 @@ def test_sorted_flag_validation_without_device():
     assert lib.fastsum_distance_qmc(3, 0, 1, 0.01, buf, None) == L.EINVAL
     assert lib.fastsum_distance_qmc(3, 10, 1, 0.0, buf, None) == L.EINVAL
     assert lib.fastsum_distance_qmc(3, 10, 1, 0.01, None, None) == L.EINVAL
+    assert lib.fastsum_rotate_directions(65, 10, buf, buf, None) == L.EINVAL
+    assert lib.fastsum_rotate_directions(0, 10, buf, buf, None) == L.EINVAL
+    assert lib.fastsum_rotate_directions(3, 0, buf, buf, None) == L.EINVAL
+    assert lib.fastsum_rotate_directions(3, 10, None, buf, None) == L.EINVAL
+    assert lib.fastsum_rotate_directions(3, 10, buf, None, None) == L.EINVAL

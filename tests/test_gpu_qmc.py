@@ -103,3 +103,44 @@ def test_one_step_elementwise_48_wide_rows(d):
     err = np.abs(g1 - o1)[stable].max()
     print("d=%d: one step on %d of %d rows, max |gpu - oracle| %.1e" % (d, stable.sum(), P, err))
     assert err < 2e-6
+
+
+def _haar(d, rng):
+    q, r = np.linalg.qr(rng.standard_normal((d, d)))
+    return q * np.sign(np.diag(r))
+
+
+@pytest.mark.parametrize("P,d", [(1, 1), (257, 3), (100, 17), (3500, 50), (513, 64)])
+def test_rotate_directions_matches_oracle(P, d):
+    """fastsum_rotate_directions (App. E) against the oracle's FP64 rotation
+    with the same FP32 matrix, element by element.  Rows and q rows are unit,
+    so every output is a dot product with sum |q_ij x_j| <= 1: FP32 sums of
+    d <= 64 terms stay within 64 * 2^-24 < 4e-6."""
+    import torch
+    from paper_2410_01316_amd import _lib as L
+    rng = np.random.default_rng(900 + d)
+    x0 = _start(P, d, 17 * d + P)
+    q = _haar(d, rng).astype(np.float32)
+    t = torch.from_numpy(x0.astype(np.float32)).cuda()
+    qd = torch.from_numpy(q).cuda()
+    st = L.load().fastsum_rotate_directions(d, P, ctypes.c_void_p(qd.data_ptr()),
+                                             ctypes.c_void_p(t.data_ptr()),
+                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    L.check(st, "fastsum_rotate_directions")
+    ref = O.rotate_directions(q.astype(np.float64), x0)
+    assert np.abs(t.cpu().numpy().astype(np.float64) - ref).max() < 4e-6
+
+
+def test_distance_qmc_rotation_is_the_library_rotation():
+    """distance_qmc(rotate=True) is the unrotated design rotated by the Haar
+    draw that follows the start in the seeded stream (App. E)."""
+    import paper_2410_01316_amd as F
+    d, P, seed = 12, 200, 5
+    plain = F.distance_qmc(d, P, iters=20, seed=seed, rotate=False)
+    rot = F.distance_qmc(d, P, iters=20, seed=seed, rotate=True)
+    rng = np.random.default_rng(seed)
+    rng.standard_normal((P, d))
+    q = _haar(d, rng).astype(np.float32).astype(np.float64)
+    ref = O.rotate_directions(q, plain.T.astype(np.float64)).T
+    assert np.abs(rot - ref).max() < 4e-6
+    assert np.allclose(np.linalg.norm(rot, axis=0), 1.0, atol=1e-6)

@@ -611,3 +611,26 @@ def test_distance_energy_gradient_and_adam():
     x0 = rng.standard_normal((5, 5))
     orth = O.projected_adam(x0, 2000, 0.05)
     assert np.abs(orth @ orth.T - np.eye(5)).max() < 1e-3
+
+
+def test_rotate_directions_orientation_and_invariants():
+    """App. E rotation: a cyclic coordinate shift q (q[i, i+1] = 1) sends
+    coordinate i+1 of each direction to coordinate i (a transposed q would
+    shift the other way); an orthogonal q keeps every inner product and so
+    the distance energy; a multiple of q gives the same unit rows."""
+    rng = np.random.default_rng(71)
+    d, P = 6, 9
+    xi = rng.standard_normal((P, d))
+    xi /= np.linalg.norm(xi, axis=1, keepdims=True)
+    shift = np.zeros((d, d))
+    for i in range(d):
+        shift[i, (i + 1) % d] = 1.0
+    out = O.rotate_directions(shift, xi)
+    assert np.abs(out - np.roll(xi, -1, axis=1)).max() < 1e-15
+    q, r = np.linalg.qr(rng.standard_normal((d, d)))
+    q *= np.sign(np.diag(r))
+    rot = O.rotate_directions(q, xi)
+    assert np.abs(rot @ rot.T - xi @ xi.T).max() < 1e-13
+    assert abs(O.distance_energy(rot) - O.distance_energy(xi)) < 1e-12 * O.distance_energy(xi)
+    assert np.abs(O.rotate_directions(3.0 * q, xi) - rot).max() < 1e-15
+    assert not np.allclose(rot, xi)
