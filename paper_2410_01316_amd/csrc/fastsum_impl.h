@@ -249,15 +249,16 @@ hipError_t launch_sorted_bucket_reduce(const float* stv, const unsigned short* s
 // s[m] = scale * sum_p V[p ldm + m] (FP64, directions in order), then bc
 hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, double scale,
                                 float* s, const BoundCheck& bc, hipStream_t stream);
-// Adjoint pieces per direction from an ascending and a descending sort of
-// the rows (sources at i < N with weights w, targets at yoff + m with
-// cotangent v; sign(0) = 0 at equal keys), all P x ldm FP32:
+// Adjoint pieces per direction from the rows launch_sorted_energy sorted
+// (keys_sorted, vals; the same L, N, yoff, M, same_xy; sources at i < N
+// with weights w, targets at yoff + m with cotangent v; sign(0) = 0 at
+// equal keys), all P x ldm FP32:
 //   Ty[p][m] = coef sum_n w_n sign(y~_m - x~_n) (want bit 0),
 //   Tx[p][n] = coef sum_m v_m sign(x~_n - y~_m) (bit 1),
 //   U[p][n] = coef sum_m v_m |x~_n - y~_m| (bit 2).
-hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned int* vals_out,
-                              void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
-                              int M, const float* w, const float* v, double coef, float* Ty,
+hipError_t launch_sorted_grad(const float* keys_in, const float* keys_sorted,
+                              const unsigned int* vals, int64_t L, int P, int N, int yoff, int M,
+                              int same_xy, const float* w, const float* v, double coef, float* Ty,
                               float* Tx, float* U, int64_t ldm, int want, hipStream_t stream);
 
 // ---- distance QMC directions (qmc.hip) ----
@@ -266,6 +267,9 @@ hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned in
 size_t distance_qmc_part_floats(int P);
 hipError_t distance_qmc(float* xi, int P, int d, int iters, double lr, float* m, float* v,
                         float* part, hipStream_t st);
+// Rows of xi (P x d, d <= 64) replaced by Q xi_p / |Q xi_p| (App. E), Q
+// device d x d row-major; asynchronous on st.
+hipError_t rotate_directions(const float* q, float* xi, int P, int d, hipStream_t st);
 
 // ---- batched form: one persistent launch per phase over a task list ----
 

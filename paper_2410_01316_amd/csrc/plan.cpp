@@ -753,25 +753,23 @@ fastsum_status sorted_pass(fastsum_plan_s* pl, const float* x, const float* w, i
     return FASTSUM_OK;
 }
 
-// Adjoint of a sorted exec: an ascending and a descending sort of the rows
-// (sources x, targets y) give per direction the one-sided sums of w and v
-// at every point; back-projection with tau Xi and the weights v or w gives
-// grad_y and grad_x, the FP64 mean of the transposed sums grad_w.
+// Adjoint of a sorted exec from the rows that exec sorted (sources x,
+// targets y, or one copy of the points when they were both): per
+// direction the weight sums over strictly smaller and larger keys give the
+// derivatives at every point; back-projection with tau Xi and the weights
+// v or w gives grad_y and grad_x, the FP64 mean of the transposed sums
+// grad_w.
 fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, float* grad_y,
                            float* grad_w, hipStream_t st) {
     const int64_t L = pl->sort_L, yoff = pl->sort_yoff, N = pl->last_N, M = pl->last_M;
     const int P = pl->P;
     if (!grad_x && !grad_y && !grad_w) return FASTSUM_OK;
-    if (pl->last_same) {          // the exec projected one copy; the adjoint needs both roles
-        fastsum_status r = project(pl, pl->last_x, N, pl->keys + yoff, L, nullptr, st);
-        if (r != FASTSUM_OK) return r;
-    }
     const double coef = -energy_cd(pl->d) / pl->r.tau;
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SORT, st);
-        FS_TRY(launch_sorted_grad(pl->keys, pl->keys_out, pl->vals, pl->sort_temp,
-                                  pl->sort_temp_bytes, L, P, (int)N, (int)yoff, (int)M,
-                                  pl->last_w, v, coef, pl->sty, pl->stx, pl->sv, pl->ldm,
+        FS_TRY(launch_sorted_grad(pl->keys, pl->keys_out, pl->vals, L, P, (int)N, (int)yoff,
+                                  (int)M, pl->last_same ? 1 : 0, pl->last_w, v, coef, pl->sty,
+                                  pl->stx, pl->sv, pl->ldm,
                                   (grad_y ? 1 : 0) | (grad_x ? 2 : 0) | (grad_w ? 4 : 0), st));
     }
     const float inv_p = (float)(1.0 / P);
@@ -1247,6 +1245,14 @@ fastsum_status fastsum_distance_qmc(int32_t d, int32_t P, int32_t iters, double 
     for (float* b : {m, v, part}) (void)hipFree(b);
     if (e == hipErrorInvalidValue) return FASTSUM_EINVAL;
     return (e == hipSuccess && es == hipSuccess) ? FASTSUM_OK : FASTSUM_EDEVICE;
+}
+
+fastsum_status fastsum_rotate_directions(int32_t d, int32_t P, const float* q, float* xi,
+                                         void* stream) {
+    if (!q || !xi || d < 1 || d > 64 || P < 1) return FASTSUM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (rotate_directions(q, xi, P, d, st) != hipSuccess) return FASTSUM_EDEVICE;
+    return hipStreamSynchronize(st) == hipSuccess ? FASTSUM_OK : FASTSUM_EDEVICE;
 }
 
 fastsum_status fastsum_set_launch(fastsum_plan pl, int64_t chunk_len, int32_t dir_range) {

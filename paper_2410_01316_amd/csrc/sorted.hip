@@ -337,49 +337,57 @@ __global__ __launch_bounds__(kBucketThreads) void sorted_bucket_reduce_kernel(
     }
 }
 
-// Both directions are stable: equal keys keep the order of their positions.
-// The radix order puts -0.0 below +0.0; the projections never produce -0.0
+// The sort is stable: equal keys keep the order of their positions.  The
+// radix order puts -0.0 below +0.0; the projections never produce -0.0
 // (their accumulations start from +0.0, and +0.0 + -0.0 = +0.0), so equal
 // keys are equal bit patterns.
 hipError_t run_sort(void* temp, size_t& temp_bytes, const float* keys_in, float* keys_out,
-                    unsigned int* vals_out, int64_t L, int P, int n_tot, hipStream_t stream,
-                    bool descending = false) {
+                    unsigned int* vals_out, int64_t L, int P, int n_tot, hipStream_t stream) {
     const rocprim::counting_iterator<unsigned int> rows(0u);
     const OffsetIt begin(rows, RowOffset{L, 0});
     const OffsetIt end(rows, RowOffset{L, n_tot});
-    if (descending)
-        return rocprim::segmented_radix_sort_pairs_desc<SortConfig>(
-            temp, temp_bytes, keys_in, keys_out, rocprim::counting_iterator<unsigned int>(0u),
-            vals_out, (unsigned int)(P * L), (unsigned int)P, begin, end, 0, 32, stream);
     return rocprim::segmented_radix_sort_pairs<SortConfig>(temp, temp_bytes, keys_in, keys_out,
                                                rocprim::counting_iterator<unsigned int>(0u),
                                                vals_out, (unsigned int)(P * L), (unsigned int)P,
                                                begin, end, 0, 32, stream);
 }
 
-// Adjoint of the sorted energy sums.  The row holds the sources x (weights
-// w, positions i < N) and the targets y (cotangent v, positions yoff + m).
-// Per direction, with coef = -c_d / tau and sign(0) = 0 at equal keys,
+// Adjoint of the sorted energy sums, from the ascending sort the exec made.
+// The row holds the sources x (weights w, positions i < N) and the targets
+// y (cotangent v, positions yoff + m; same_xy: every i < N is source and
+// target i).  Per direction, with coef = -c_d / tau and sign(0) = 0:
 //   Ty[p][m] = coef sum_n w_n sign(y~_m - x~_n) = coef (W_< - W_>)   (d/dy~ of the sum)
 //   Tx[p][n] = coef sum_m v_m sign(x~_n - y~_m) = coef (V_< - V_>)   (d/dx~ of the transposed sum)
 //   U[p][n]  = coef sum_m v_m |x~_n - y~_m|                         (the transposed sum)
-// The sums over strictly smaller or larger keys come from two stable sorts
-// of the same row, in which every x precedes every y of equal key:
-//   ascending (DESC = 0): x before y_m  = W_<=, y before x_n = V_<;
-//   descending (DESC = 1): x before y_m = W_>=, y before x_n = V_>.
-// Pass 0 writes Ty = coef (W_<= - W), Tx = coef V_<, U; pass 1 adds
-// coef (W - W_>=) to Ty and -coef V_> to Tx (each entry once per row).
+// with W_<, W_> the weight of the sources of strictly smaller / larger key.
+// Equal keys are adjacent in sorted order, so the entries of one key form a
+// run and share Ty and Tx: at the run's last entry, with Wi the inclusive
+// prefix sum of w there and Wr the run's own weight, W_< = Wi - Wr and
+// W_> = W - Wi, so Ty = coef (2 Wi - Wr - W) (Tx likewise with v).  The run
+// sums are a segmented scan (restarted where the key changes); each run's
+// values go to an LDS slot named by its first entry, which every entry of
+// the run finds by a max-scan of run starts.  A run still open at the end
+// of a chunk is written once it ends: its entries in earlier chunks are
+// read back from the sorted row.  U needs no runs: tied pairs add |0|.
 // want: bit 0 Ty, bit 1 Tx, bit 2 U (the others are neither read nor written).
-template <bool DESC>
-__global__ __launch_bounds__(kSortBlock) void sorted_grad_kernel(
+constexpr int kAdjItems = 8;
+constexpr int kAdjChunk = kSortBlock * kAdjItems;
+
+__global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
     const float* __restrict__ keys_in, const float* __restrict__ keys,
-    const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M,
+    const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M, int same_xy,
     const float* __restrict__ w, const float* __restrict__ v, double coef,
     float* __restrict__ Ty, float* __restrict__ Tx, float* __restrict__ U, int64_t ldm,
     int want) {
     __shared__ double sa[2][kSortWaves], sb[2][kSortWaves], sc[2][kSortWaves];
+    __shared__ double ra[2][kSortWaves], rb[2][kSortWaves];   // run sums of w, v
+    __shared__ int rf[2][kSortWaves], rs[2][kSortWaves];       // a run starts inside; last start
+    __shared__ float slot_y[kAdjChunk], slot_x[kAdjChunk];
+    __shared__ int open_start[2];
+    __shared__ double open_w[2], open_v[2];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n_tot = yoff + M;
+    const int n_tot = same_xy ? N : yoff + M;
+    const int toff = same_xy ? 0 : yoff;
     const int64_t base = (int64_t)p * L;
     const float* __restrict__ kr = keys + base;
     const unsigned int* __restrict__ vr = vals + base;
@@ -394,7 +402,7 @@ __global__ __launch_bounds__(kSortBlock) void sorted_grad_kernel(
         for (int m = tid; m < M; m += kSortBlock) {
             const double vm = v[m];
             V += vm;
-            SV += vm * (double)xr[yoff + m];
+            SV += vm * (double)xr[toff + m];
         }
         W = wave_sum(W);
         V = wave_sum(V);
@@ -405,67 +413,149 @@ __global__ __launch_bounds__(kSortBlock) void sorted_grad_kernel(
 #pragma unroll
         for (int k = 0; k < kSortWaves; ++k) { W += sa[1][k]; V += sb[1][k]; SV += sc[1][k]; }
     }
-    double cw = 0.0, cv = 0.0, csv = 0.0;             // sums of the earlier chunks
+    double cw = 0.0, cv = 0.0, csv = 0.0;       // plain sums of the earlier chunks
+    int ostart = -1;                            // first entry of the run open at the last chunk's end
+    double ow = 0.0, ov = 0.0;                  // and its sums so far
     int par = 0;
-    for (int c0 = 0; c0 < n_tot; c0 += kSortChunk, par ^= 1) {
-        const int i0 = c0 + tid * kSortItems;
-        float kk[kSortItems];
-        int ii[kSortItems];
-        load_sorted<kSortItems>(kr, vr, base, i0, n_tot, kk, ii);
-        // x entries ii < N, y entries ii >= yoff, padding otherwise
-        double lw[kSortItems], lv[kSortItems], lsv[kSortItems];
+    for (int c0 = 0; c0 < n_tot; c0 += kAdjChunk, par ^= 1) {
+        const int i0 = c0 + tid * kAdjItems;
+        float kk[kAdjItems];
+        int ii[kAdjItems];
+        load_sorted<kAdjItems>(kr, vr, base, i0, n_tot, kk, ii);
+        const float kprev = (i0 > 0 && i0 <= n_tot) ? kr[i0 - 1] : 0.f;
+        const float knext = (i0 + kAdjItems < n_tot) ? kr[i0 + kAdjItems] : 0.f;
+        float lw[kAdjItems], lv[kAdjItems];
+        unsigned int fst = 0u, lst = 0u;        // bit j: item j starts / ends a run
         double tw = 0.0, tv = 0.0, tsv = 0.0;
+        bool tf = false;                        // this thread's run aggregate
+        double trw = 0.0, trv = 0.0;
+        int ts = -1;
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            lw[j] = lv[j] = lsv[j] = 0.0;
-            if (ii[j] >= 0 && ii[j] < N) lw[j] = w[ii[j]];
-            if (ii[j] >= yoff) {
-                lv[j] = v[ii[j] - yoff];
-                lsv[j] = lv[j] * (double)kk[j];
+        for (int j = 0; j < kAdjItems; ++j) {
+            const int i = i0 + j, pos = ii[j];
+            const bool src = pos >= 0 && pos < N;
+            const bool tgt = same_xy ? src : pos >= yoff;          // pos < n_tot
+            lw[j] = src ? w[pos] : 0.f;
+            lv[j] = tgt ? v[pos - toff] : 0.f;
+            tw += (double)lw[j];
+            tv += (double)lv[j];
+            tsv += (double)lv[j] * (double)kk[j];
+            const float kp = j == 0 ? kprev : kk[j - 1];
+            const float kn = j == kAdjItems - 1 ? knext : kk[j + 1];
+            const bool valid = i < n_tot;
+            if (!valid || i == 0 || kk[j] != kp) {
+                fst |= 1u << j;
+                tf = true;
+                trw = trv = 0.0;
+                ts = i;
             }
-            tw += lw[j];
-            tv += lv[j];
-            tsv += lsv[j];
+            if (!valid || i + 1 >= n_tot || kk[j] != kn) lst |= 1u << j;
+            trw += (double)lw[j];
+            trv += (double)lv[j];
         }
         const double iw = wave_incl_scan(tw), iv = wave_incl_scan(tv), isv = wave_incl_scan(tsv);
-        if (lane == 63) { sa[par][wave] = iw; sb[par][wave] = iv; sc[par][wave] = isv; }
+        // segmented inclusive scan of the run sums (a start discards what is
+        // before it) and max-scan of the run starts
+        double sw = trw, sv = trv;
+        int sf = tf ? 1 : 0, ss = ts;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double pw = __shfl_up(sw, o, 64), pv = __shfl_up(sv, o, 64);
+            const int pf = __shfl_up(sf, o, 64), ps = __shfl_up(ss, o, 64);
+            if (lane >= o) {
+                if (!sf) { sw += pw; sv += pv; }
+                sf |= pf;
+                ss = max(ss, ps);
+            }
+        }
+        if (lane == 63) {
+            sa[par][wave] = iw; sb[par][wave] = iv; sc[par][wave] = isv;
+            ra[par][wave] = sw; rb[par][wave] = sv; rf[par][wave] = sf; rs[par][wave] = ss;
+        }
+        // the lane before's inclusive aggregate is this lane's exclusive one
+        const double xw = __shfl_up(sw, 1, 64), xv = __shfl_up(sv, 1, 64);
+        const int xf = __shfl_up(sf, 1, 64), xs = __shfl_up(ss, 1, 64);
         __syncthreads();
         double ew = cw, ev = cv, esv = csv;
+        double rw = ow, rv = ov;                // run sums entering this thread
+        int rstart = ostart;
 #pragma unroll
         for (int k = 0; k < kSortWaves; ++k) {
             const double xa = sa[par][k], xb = sb[par][k], xc = sc[par][k];
-            if (k < wave) { ew += xa; ev += xb; esv += xc; }
+            if (k < wave) {
+                ew += xa; ev += xb; esv += xc;
+                if (rf[par][k]) { rw = ra[par][k]; rv = rb[par][k]; }
+                else { rw += ra[par][k]; rv += rb[par][k]; }
+                rstart = max(rstart, rs[par][k]);
+            }
             cw += xa;
             cv += xb;
             csv += xc;
         }
-        ew += iw - tw;                                  // exclusive prefixes of item 0
+        if (lane > 0) {
+            if (xf) { rw = xw; rv = xv; }
+            else { rw += xw; rv += xv; }
+            rstart = max(rstart, xs);
+        }
+        ew += iw - tw;                          // exclusive prefixes of item 0
         ev += iv - tv;
         esv += isv - tsv;
+        int start[kAdjItems];
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            if (ii[j] >= yoff) {
-                const int m = ii[j] - yoff;
-                if (want & 1) {
-                    if (!DESC) ty[m] = (float)(coef * (ew - W));
-                    else ty[m] = (float)((double)ty[m] + coef * (W - ew));
-                }
-            } else if (ii[j] >= 0 && ii[j] < N) {
-                const int n = ii[j];
-                if (!DESC) {
-                    if (want & 2) tx[n] = (float)(coef * ev);
-                    if (want & 4) {
-                        const double x = kk[j];
-                        u[n] = (float)(coef * (x * (2.0 * ev - V) - (2.0 * esv - SV)));
-                    }
-                } else if (want & 2) {
-                    tx[n] = (float)((double)tx[n] - coef * ev);
-                }
+        for (int j = 0; j < kAdjItems; ++j) {
+            if ((fst >> j) & 1u) { rw = rv = 0.0; rstart = i0 + j; }
+            rw += (double)lw[j];
+            rv += (double)lv[j];
+            start[j] = rstart;
+            const double inw = ew + (double)lw[j], inv = ev + (double)lv[j];
+            if (((lst >> j) & 1u) && i0 + j < n_tot) {
+                const int sl = max(rstart, c0) - c0;
+                slot_y[sl] = (float)(coef * (2.0 * inw - rw - W));
+                slot_x[sl] = (float)(coef * (2.0 * inv - rv - V));
             }
-            ew += lw[j];
-            ev += lv[j];
-            esv += lsv[j];
+            const int pos = ii[j];
+            if ((want & 4) && pos >= 0 && pos < N) {
+                const double x = kk[j];
+                u[pos] = (float)(coef * (x * (2.0 * ev - V) - (2.0 * esv - SV)));
+            }
+            ew = inw;
+            ev = inv;
+            esv += (double)lv[j] * (double)kk[j];
         }
+        // a run still open at the chunk's end ends at its last entry, item
+        // kAdjItems - 1 of the last thread (a chunk that ends the row closes it)
+        if (tid == kSortBlock - 1) {
+            const bool open = !((lst >> (kAdjItems - 1)) & 1u);
+            open_start[par] = open ? start[kAdjItems - 1] : -1;
+            open_w[par] = rw;
+            open_v[par] = rv;
+        }
+        __syncthreads();
+        const int still_open = open_start[par];
+#pragma unroll
+        for (int j = 0; j < kAdjItems; ++j) {
+            const int pos = ii[j];
+            if (pos < 0 || start[j] == still_open) continue;
+            const int sl = max(start[j], c0) - c0;
+            const bool src = pos < N;
+            const bool tgt = same_xy ? src : pos >= yoff;
+            if ((want & 1) && tgt) ty[pos - toff] = slot_y[sl];
+            if ((want & 2) && src) tx[pos] = slot_x[sl];
+        }
+        // the entries before this chunk of a run that ends in it (slot 0)
+        if (ostart >= 0 && still_open != ostart) {
+            for (int i = ostart + tid; i < c0; i += kSortBlock) {
+                const int pos = (int)((int64_t)vr[i] - base);
+                if (pos < 0 || pos >= n_tot) continue;
+                const bool src = pos < N;
+                const bool tgt = same_xy ? src : pos >= yoff;
+                if ((want & 1) && tgt) ty[pos - toff] = slot_y[0];
+                if ((want & 2) && src) tx[pos] = slot_x[0];
+            }
+        }
+        ostart = still_open;
+        ow = open_w[par];
+        ov = open_v[par];
     }
 }
 
@@ -491,41 +581,24 @@ hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, d
 }
 
 size_t sorted_energy_temp_bytes(int64_t L, int P) {
-    size_t up = 0, down = 0;
-    if (run_sort(nullptr, up, nullptr, nullptr, nullptr, L, P, (int)L, nullptr) != hipSuccess ||
-        run_sort(nullptr, down, nullptr, nullptr, nullptr, L, P, (int)L, nullptr, true) !=
-            hipSuccess)
+    size_t bytes = 0;
+    if (run_sort(nullptr, bytes, nullptr, nullptr, nullptr, L, P, (int)L, nullptr) != hipSuccess)
         return 0;
-    return up > down ? up : down;
+    return bytes;
 }
 
-hipError_t launch_sorted_grad(const float* keys_in, float* keys_out, unsigned int* vals_out,
-                              void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,
-                              int M, const float* w, const float* v, double coef, float* Ty,
+hipError_t launch_sorted_grad(const float* keys_in, const float* keys_sorted,
+                              const unsigned int* vals, int64_t L, int P, int N, int yoff, int M,
+                              int same_xy, const float* w, const float* v, double coef, float* Ty,
                               float* Tx, float* U, int64_t ldm, int want, hipStream_t stream) {
-    const int n_tot = yoff + M;
-    if (N < 1 || M < 1 || yoff < N || n_tot > L || N > ldm || M > ldm ||
-        (int64_t)P * L >= ((int64_t)1 << 32))
+    const int n_tot = same_xy ? N : yoff + M;
+    if (N < 1 || M < 1 || (same_xy && M != N) || (!same_xy && yoff < N) || n_tot > L ||
+        N > ldm || M > ldm || (int64_t)P * L >= ((int64_t)1 << 32))
         return hipErrorInvalidValue;
-    // the descending pass only completes the derivatives
-    const int passes = (want & 3) ? 2 : 1;
-    for (int pass = 0; pass < passes; ++pass) {
-        size_t bytes = temp_bytes;
-        hipError_t e = run_sort(temp, bytes, keys_in, keys_out, vals_out, L, P, n_tot, stream,
-                                pass == 1);
-        if (e != hipSuccess) return e;
-        if (pass == 0)
-            hipLaunchKernelGGL(sorted_grad_kernel<false>, dim3((unsigned)P), dim3(kSortBlock), 0,
-                               stream, keys_in, keys_out, vals_out, L, N, yoff, M, w, v, coef, Ty,
-                               Tx, U, ldm, want);
-        else
-            hipLaunchKernelGGL(sorted_grad_kernel<true>, dim3((unsigned)P), dim3(kSortBlock), 0,
-                               stream, keys_in, keys_out, vals_out, L, N, yoff, M, w, v, coef, Ty,
-                               Tx, U, ldm, want);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    hipLaunchKernelGGL(sorted_adjoint_kernel, dim3((unsigned)P), dim3(kSortBlock), 0, stream,
+                       keys_in, keys_sorted, vals, L, N, yoff, M, same_xy, w, v, coef, Ty, Tx, U,
+                       ldm, want);
+    return hipGetLastError();
 }
 
 int sorted_reduce_ranges(int64_t M, int P) {

@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 from workloads.configs import make_config
 from workloads.directions import directions
-from helpers import rel_l2, err_scale, to_dev, oracle_inputs, DEFAULT_T
+from helpers import rel_l2, max_rel, err_scale, to_dev, oracle_inputs, DEFAULT_T
 
 pytestmark = pytest.mark.gpu
 
@@ -247,6 +247,33 @@ def test_sorted_gradients_exact_ties(same):
     e = [rel_l2(s, s2), rel_l2(gx, ox), rel_l2(gy, oy), rel_l2(gw, ow)]
     print("sorted grads, ties (same=%s): s %.1e gx %.1e gy %.1e gw %.1e" % (same, *e))
     assert max(e) < 1e-5
+
+
+@pytest.mark.parametrize("levels,d,same", [(2, 2, False), (2, 2, True), (17, 3, False)])
+def test_sorted_gradients_runs_across_chunks(levels, d, same):
+    """Equal keys in runs longer than the adjoint's 4096-entry chunks: with
+    coordinates in {0, 1} each axis direction has two keys, so a run covers
+    whole chunks and its values are written when it ends (entries of
+    earlier chunks read back); with 17 levels in [-1, 1] runs of ~900
+    entries straddle chunk boundaries.  same: one sorted copy of the points,
+    each entry source and target."""
+    N, M = 9000, 6000
+    rng = np.random.default_rng(81 + levels + 2 * d + same)
+    grid = np.linspace(0.0, 1.0, 2) if levels == 2 else np.linspace(-1.0, 1.0, levels)
+    x = grid[rng.integers(0, levels, size=(N, d))]
+    y = x.copy() if same else grid[rng.integers(0, levels, size=(M, d))]
+    M = y.shape[0]
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    w = f32(rng.standard_normal(N))
+    v = f32(rng.standard_normal(M))
+    xi = np.concatenate([np.eye(d), -np.eye(d)], axis=1)
+    s, gx, gy, gw = _sorted_grads(x, y, w, v, xi, same)
+    ox, oy, ow = O.grad_sliced_energy(x, y, w, v, xi)
+    e = [rel_l2(gx, ox), rel_l2(gy, oy), rel_l2(gw, ow)]
+    print("sorted grads, long runs (levels %d, same=%s): gx %.1e gy %.1e gw %.1e"
+          % (levels, same, *e))
+    assert max(e) < 1e-5
+    assert max_rel(gx, ox) < 1e-4 and max_rel(gy, oy) < 1e-4
 
 
 def test_sorted_gradients_qmc_directions():
