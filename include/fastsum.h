@@ -103,12 +103,13 @@ typedef enum {
  * exec sorted gives per direction the weight sums over strictly smaller and
  * strictly larger keys (entries of equal key form runs, handled as one),
  * i.e. the derivative sum_n w_n sign(y~ - x~_n) with sign(0) = 0 where
- * projections coincide, and the transposed sums for grad_w.  The plan needs P * L < 2^32 with
- * L = round_up(n_max, 64) + round_up(m_max, 64), and about
- * 4 P L (keys) + 4 P L (sorted keys) + 4 P L (positions) + 8 P L (sort
- * workspace) + 6 P ldm (per-direction sums and their target offsets) +
- * 384 ldm bytes of device memory, ldm = round_up(max(n_max, m_max), 64),
- * plus 8 P ldm with FASTSUM_FLAG_GRAD. */
+ * projections coincide, and the transposed sums for grad_w.  The plan
+ * needs n_max, m_max <= 2^24 and P * L < 2^32 with
+ * L = round_up(n_max, 64) + round_up(m_max, 64),
+ * and about 4 P L (keys) + 4 P L (sorted keys) + 4 P L (positions) + 8 P L
+ * (sort workspace) + 6 P ldm (per-direction sums and their target offsets)
+ * + 384 ldm bytes of device memory, ldm = round_up(max(n_max, m_max), 64),
+ * plus 20 P ldm with FASTSUM_FLAG_GRAD. */
 #define FASTSUM_FLAG_SORTED 4u
 
 /*

@@ -252,14 +252,21 @@ hipError_t launch_sorted_reduce(const float* V, int P, int64_t ldm, int64_t M, d
 // Adjoint pieces per direction from the rows launch_sorted_energy sorted
 // (keys_sorted, vals; the same L, N, yoff, M, same_xy; sources at i < N
 // with weights w, targets at yoff + m with cotangent v; sign(0) = 0 at
-// equal keys), all P x ldm FP32:
-//   Ty[p][m] = coef sum_n w_n sign(y~_m - x~_n) (want bit 0),
-//   Tx[p][n] = coef sum_m v_m sign(x~_n - y~_m) (bit 1),
-//   U[p][n] = coef sum_m v_m |x~_n - y~_m| (bit 2).
+// equal keys), each staged by 4096-index bucket as a P x ldm FP32 value
+// row and a P x ldm offset row (as the forward's sums):
+//   Ty[p][m] = coef sum_n w_n sign(y~_m - x~_n) (want bit 0; Tyv, Tyo),
+//   Tx[p][n] = coef sum_m v_m sign(x~_n - y~_m) (bit 1; Txv, Txo),
+//   U[p][n] = coef sum_m v_m |x~_n - y~_m| (bit 2; Uv, Uo).
+// launch_sorted_place puts Ty or Tx back in index order (out, P x ldm);
+// launch_sorted_bucket_reduce takes the mean of U over the directions.
 hipError_t launch_sorted_grad(const float* keys_in, const float* keys_sorted,
                               const unsigned int* vals, int64_t L, int P, int N, int yoff, int M,
-                              int same_xy, const float* w, const float* v, double coef, float* Ty,
-                              float* Tx, float* U, int64_t ldm, int want, hipStream_t stream);
+                              int same_xy, const float* w, const float* v, double coef,
+                              float* Tyv, unsigned short* Tyo, float* Txv, unsigned short* Txo,
+                              float* Uv, unsigned short* Uo, int64_t ldm, int want,
+                              hipStream_t stream);
+hipError_t launch_sorted_place(const float* stv, const unsigned short* sti, int P, int64_t ldm,
+                               int M, float* out, hipStream_t stream);
 
 // ---- distance QMC directions (qmc.hip) ----
 // iters projected Adam steps on the rows of xi (P x d, d <= 64, unit rows)

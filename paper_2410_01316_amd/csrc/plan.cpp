@@ -493,6 +493,10 @@ struct fastsum_plan_s {
     unsigned short* sti = nullptr; // each staged sum's target offset in its 4096-target bucket
     float* sty = nullptr;          // sorted adjoint: d/dy~ and d/dx~ per direction, P x ldm
     float* stx = nullptr;
+    float* styb = nullptr;         // the same, staged by bucket (values, offsets)
+    unsigned short* styo = nullptr;
+    float* stxb = nullptr;
+    unsigned short* stxo = nullptr;
     int64_t sort_L = 0, sort_yoff = 0;
     // back-projection on the tile GEMM (d above the fused range): split
     // tiles of xi^T, the derivative matrix as tiles, abs-max slots
@@ -525,7 +529,7 @@ void free_plan(fastsum_plan_s* p) {
                     p->slice_max, p->ab, p->gpart, p->grid_wd, p->tout, p->keys,
                     p->keys_out, p->vals, p->sort_temp, p->sv, p->sty, p->stx, p->norms,
                     p->xit, p->bp_tiles, p->bp_scratch,
-                    p->sti};
+                    p->sti, p->styb, p->styo, p->stxb, p->stxo};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -768,9 +772,11 @@ fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, fl
     {
         PhaseTimer t(pl, FASTSUM_PHASE_SORT, st);
         FS_TRY(launch_sorted_grad(pl->keys, pl->keys_out, pl->vals, L, P, (int)N, (int)yoff,
-                                  (int)M, pl->last_same ? 1 : 0, pl->last_w, v, coef, pl->sty,
-                                  pl->stx, pl->sv, pl->ldm,
+                                  (int)M, pl->last_same ? 1 : 0, pl->last_w, v, coef, pl->styb,
+                                  pl->styo, pl->stxb, pl->stxo, pl->sv, pl->sti, pl->ldm,
                                   (grad_y ? 1 : 0) | (grad_x ? 2 : 0) | (grad_w ? 4 : 0), st));
+        if (grad_y) FS_TRY(launch_sorted_place(pl->styb, pl->styo, P, pl->ldm, (int)M, pl->sty, st));
+        if (grad_x) FS_TRY(launch_sorted_place(pl->stxb, pl->stxo, P, pl->ldm, (int)N, pl->stx, st));
     }
     const float inv_p = (float)(1.0 / P);
     if (grad_y) {
@@ -785,7 +791,8 @@ fastsum_status sorted_grad(fastsum_plan_s* pl, const float* v, float* grad_x, fl
     }
     if (grad_w) {
         PhaseTimer t(pl, FASTSUM_PHASE_REDUCE, st);
-        FS_TRY(launch_sorted_reduce(pl->sv, P, pl->ldm, N, 1.0 / P, grad_w, BoundCheck{}, st));
+        FS_TRY(launch_sorted_bucket_reduce(pl->sv, pl->sti, P, pl->ldm, (int)N, pl->spart,
+                                           1.0 / P, grad_w, BoundCheck{}, st));
     }
     return FASTSUM_OK;
 }
@@ -887,7 +894,9 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     if (pl->sorted) {
         pl->sort_yoff = pl->ld_x;
         pl->sort_L = pl->ld_x + pl->ld_y;
-        if (pl->sort_L > INT32_MAX / 2 || (int64_t)P * pl->sort_L >= ((int64_t)1 << 32)) {
+        // the bucket counters of the scans live in LDS: at most 2^12 buckets of 4096
+        if (pl->sort_L > INT32_MAX / 2 || (int64_t)P * pl->sort_L >= ((int64_t)1 << 32) ||
+            pl->ldm > ((int64_t)1 << 24)) {
             delete pl;
             return FASTSUM_EINVAL;
         }
@@ -928,7 +937,9 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
     const int DC = (pl->d + 15) / 16;
     pl->ldg = cap;       // the source adjoint back-projects at the sources
     if (ok && grad && pl->sorted)
-        ok = dev_alloc(&pl->sty, (size_t)P * pl->ldm) && dev_alloc(&pl->stx, (size_t)P * pl->ldm);
+        ok = dev_alloc(&pl->sty, (size_t)P * pl->ldm) && dev_alloc(&pl->stx, (size_t)P * pl->ldm) &&
+             dev_alloc(&pl->styb, (size_t)P * pl->ldm) && dev_alloc(&pl->styo, (size_t)P * pl->ldm) &&
+             dev_alloc(&pl->stxb, (size_t)P * pl->ldm) && dev_alloc(&pl->stxo, (size_t)P * pl->ldm);
     if (ok && grad && !pl->sorted)
         ok = dev_alloc(&pl->grid_d, (size_t)P * nr) && dev_alloc(&pl->grid_w, (size_t)P * nr) &&
              dev_alloc(&pl->grid_wd, (size_t)P * nr) && dev_alloc(&pl->tout, (size_t)cap) &&

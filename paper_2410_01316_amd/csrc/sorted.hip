@@ -369,44 +369,137 @@ hipError_t run_sort(void* temp, size_t& temp_bytes, const float* keys_in, float*
 // the run finds by a max-scan of run starts.  A run still open at the end
 // of a chunk is written once it ends: its entries in earlier chunks are
 // read back from the sorted row.  U needs no runs: tied pairs add |0|.
-// want: bit 0 Ty, bit 1 Tx, bit 2 U (the others are neither read nor written).
+// The values leave as the forward's do, staged by 4096-index bucket
+// (stage_bucketed): each output has a value row and an offset row per
+// direction, which sorted_place_kernel (Ty, Tx) puts back in index order
+// and sorted_bucket_reduce_kernel (U) sums over the directions.
+// want: bit 0 Ty, bit 1 Tx, bit 2 U (the others are neither read nor
+// written).  FULL = false serves want == 1 alone: no v sums, fewer
+// registers, two workgroups per CU.
 constexpr int kAdjItems = 8;
 constexpr int kAdjChunk = kSortBlock * kAdjItems;
 
-__global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
-    const float* __restrict__ keys_in, const float* __restrict__ keys,
-    const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M, int same_xy,
-    const float* __restrict__ w, const float* __restrict__ v, double coef,
-    float* __restrict__ Ty, float* __restrict__ Tx, float* __restrict__ U, int64_t ldm,
-    int want) {
+// LDS of one staging round and the bucket counters of the three outputs.
+struct StageLds {
+    float* cval;             // kAdjChunk values of the round, ordered by bucket
+    int* cidx;               // and their indices
+    unsigned int* cnt;       // [nbmax] this round's counts per bucket (zero between rounds)
+    unsigned int* coff;      // [nbmax + 1] this round's bucket offsets
+};
+
+// One staging round of up to kAdjChunk entries (idx < 0: none) of the
+// workgroup: slots from LDS counters per bucket idx >> kBucketShift, the
+// values ordered by bucket in LDS, then written as runs after the entries
+// the bucket's region already holds (run[b]); each value's offset in its
+// bucket goes beside it.  Called by every thread (barriers inside).
+__device__ __forceinline__ void stage_bucketed(const int (&idx)[kAdjItems],
+                                               const float (&val)[kAdjItems], int nb,
+                                               const StageLds& sl, unsigned int* run,
+                                               float* __restrict__ outv,
+                                               unsigned short* __restrict__ outi) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int slot[kAdjItems];
+#pragma unroll
+    for (int j = 0; j < kAdjItems; ++j)
+        slot[j] = idx[j] >= 0 ? (int)atomicAdd(&sl.cnt[idx[j] >> kBucketShift], 1u) : -1;
+    __syncthreads();
+    if (wave == 0) {
+        unsigned int acc = 0u;
+        for (int b0 = 0; b0 < nb; b0 += 64) {
+            const unsigned int c = (b0 + lane < nb) ? sl.cnt[b0 + lane] : 0u;
+            unsigned int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned int t = (unsigned int)__shfl_up((int)incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            if (b0 + lane < nb) sl.coff[b0 + lane] = acc + incl - c;
+            acc += (unsigned int)__shfl((int)incl, 63, 64);
+        }
+        if (lane == 0) sl.coff[nb] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kAdjItems; ++j) {
+        if (slot[j] >= 0) {
+            const int k = (int)sl.coff[idx[j] >> kBucketShift] + slot[j];
+            sl.cval[k] = val[j];
+            sl.cidx[k] = idx[j];
+        }
+    }
+    __syncthreads();
+    const int total = (int)sl.coff[nb];
+    for (int k = tid; k < total; k += kSortBlock) {
+        const int m = sl.cidx[k];
+        const int bk = m >> kBucketShift;
+        const int64_t pos = ((int64_t)bk << kBucketShift) + run[bk] + (k - (int)sl.coff[bk]);
+        outv[pos] = sl.cval[k];
+        outi[pos] = (unsigned short)(m & (kBucket - 1));
+    }
+    __syncthreads();
+    for (int bk = tid; bk < nb; bk += kSortBlock) {
+        run[bk] += sl.cnt[bk];
+        sl.cnt[bk] = 0u;
+    }
+    __syncthreads();
+}
+
+template <bool FULL>
+__global__ __launch_bounds__(kSortBlock) __attribute__((amdgpu_waves_per_eu(FULL ? 1 : 4))) void
+sorted_adjoint_kernel(const float* __restrict__ keys_in, const float* __restrict__ keys,
+                      const unsigned int* __restrict__ vals, int64_t L, int N, int yoff, int M,
+                      int same_xy, const float* __restrict__ w, const float* __restrict__ v,
+                      double coef, float* __restrict__ Tyv, unsigned short* __restrict__ Tyo,
+                      float* __restrict__ Txv, unsigned short* __restrict__ Txo,
+                      float* __restrict__ Uv, unsigned short* __restrict__ Uo, int64_t ldm,
+                      int want) {
     __shared__ double sa[2][kSortWaves], sb[2][kSortWaves], sc[2][kSortWaves];
     __shared__ double ra[2][kSortWaves], rb[2][kSortWaves];   // run sums of w, v
     __shared__ int rf[2][kSortWaves], rs[2][kSortWaves];       // a run starts inside; last start
-    __shared__ float slot_y[kAdjChunk], slot_x[kAdjChunk];
+    __shared__ float slot_y[kAdjChunk], slot_x[FULL ? kAdjChunk : 1];
+    __shared__ float cval[kAdjChunk];
+    __shared__ int cidx[kAdjChunk];
     __shared__ int open_start[2];
     __shared__ double open_w[2], open_v[2];
+    // [0, nbm) counts, [nbm, 2 nbm + 1) offsets, then the running counts of
+    // Ty (nby), Tx (nbx) and U (nbx)
+    extern __shared__ unsigned int bcnt[];
     const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_tot = same_xy ? N : yoff + M;
     const int toff = same_xy ? 0 : yoff;
+    const int nby = (M + kBucket - 1) >> kBucketShift, nbx = (N + kBucket - 1) >> kBucketShift;
+    const int nbm = max(nby, nbx);
+    const StageLds sl{cval, cidx, bcnt, bcnt + nbm};
+    unsigned int* run_y = bcnt + 2 * nbm + 1;
+    unsigned int* run_x = run_y + nby;
+    unsigned int* run_u = run_x + nbx;
+    for (int b = tid; b < 2 * nbm + 1 + nby + 2 * nbx; b += kSortBlock) bcnt[b] = 0u;
     const int64_t base = (int64_t)p * L;
     const float* __restrict__ kr = keys + base;
     const unsigned int* __restrict__ vr = vals + base;
-    float* __restrict__ ty = Ty + (int64_t)p * ldm;
-    float* __restrict__ tx = Tx + (int64_t)p * ldm;
-    float* __restrict__ u = U + (int64_t)p * ldm;
+    float* __restrict__ tyv = Tyv + (int64_t)p * ldm;
+    unsigned short* __restrict__ tyo = Tyo + (int64_t)p * ldm;
+    float* __restrict__ txv = Txv + (int64_t)p * ldm;
+    unsigned short* __restrict__ txo = Txo + (int64_t)p * ldm;
+    float* __restrict__ uv = Uv + (int64_t)p * ldm;
+    unsigned short* __restrict__ uo = Uo + (int64_t)p * ldm;
     // totals W = sum w, V = sum v, SV = sum v y~ over the unsorted row
     double W = 0.0, V = 0.0, SV = 0.0;
     {
         const float* __restrict__ xr = keys_in + base;
         for (int n = tid; n < N; n += kSortBlock) W += (double)w[n];
-        for (int m = tid; m < M; m += kSortBlock) {
-            const double vm = v[m];
-            V += vm;
-            SV += vm * (double)xr[toff + m];
+        if constexpr (FULL) {
+            for (int m = tid; m < M; m += kSortBlock) {
+                const double vm = v[m];
+                V += vm;
+                SV += vm * (double)xr[toff + m];
+            }
         }
         W = wave_sum(W);
-        V = wave_sum(V);
-        SV = wave_sum(SV);
+        if constexpr (FULL) {
+            V = wave_sum(V);
+            SV = wave_sum(SV);
+        }
         if (lane == 0) { sa[1][wave] = W; sb[1][wave] = V; sc[1][wave] = SV; }
         __syncthreads();
         W = V = SV = 0.0;
@@ -434,12 +527,16 @@ __global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
         for (int j = 0; j < kAdjItems; ++j) {
             const int i = i0 + j, pos = ii[j];
             const bool src = pos >= 0 && pos < N;
-            const bool tgt = same_xy ? src : pos >= yoff;          // pos < n_tot
             lw[j] = src ? w[pos] : 0.f;
-            lv[j] = tgt ? v[pos - toff] : 0.f;
             tw += (double)lw[j];
-            tv += (double)lv[j];
-            tsv += (double)lv[j] * (double)kk[j];
+            if constexpr (FULL) {
+                const bool tgt = same_xy ? src : pos >= yoff;      // pos < n_tot
+                lv[j] = tgt ? v[pos - toff] : 0.f;
+                tv += (double)lv[j];
+                tsv += (double)lv[j] * (double)kk[j];
+            } else {
+                lv[j] = 0.f;
+            }
             const float kp = j == 0 ? kprev : kk[j - 1];
             const float kn = j == kAdjItems - 1 ? knext : kk[j + 1];
             const bool valid = i < n_tot;
@@ -451,19 +548,29 @@ __global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
             }
             if (!valid || i + 1 >= n_tot || kk[j] != kn) lst |= 1u << j;
             trw += (double)lw[j];
-            trv += (double)lv[j];
+            if constexpr (FULL) trv += (double)lv[j];
         }
-        const double iw = wave_incl_scan(tw), iv = wave_incl_scan(tv), isv = wave_incl_scan(tsv);
+        const double iw = wave_incl_scan(tw);
+        double iv = 0.0, isv = 0.0;
+        if constexpr (FULL) {
+            iv = wave_incl_scan(tv);
+            isv = wave_incl_scan(tsv);
+        }
         // segmented inclusive scan of the run sums (a start discards what is
         // before it) and max-scan of the run starts
         double sw = trw, sv = trv;
         int sf = tf ? 1 : 0, ss = ts;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const double pw = __shfl_up(sw, o, 64), pv = __shfl_up(sv, o, 64);
+            const double pw = __shfl_up(sw, o, 64);
+            double pv = 0.0;
+            if constexpr (FULL) pv = __shfl_up(sv, o, 64);
             const int pf = __shfl_up(sf, o, 64), ps = __shfl_up(ss, o, 64);
             if (lane >= o) {
-                if (!sf) { sw += pw; sv += pv; }
+                if (!sf) {
+                    sw += pw;
+                    if constexpr (FULL) sv += pv;
+                }
                 sf |= pf;
                 ss = max(ss, ps);
             }
@@ -473,7 +580,9 @@ __global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
             ra[par][wave] = sw; rb[par][wave] = sv; rf[par][wave] = sf; rs[par][wave] = ss;
         }
         // the lane before's inclusive aggregate is this lane's exclusive one
-        const double xw = __shfl_up(sw, 1, 64), xv = __shfl_up(sv, 1, 64);
+        const double xw = __shfl_up(sw, 1, 64);
+        double xv = 0.0;
+        if constexpr (FULL) xv = __shfl_up(sv, 1, 64);
         const int xf = __shfl_up(sf, 1, 64), xs = __shfl_up(ss, 1, 64);
         __syncthreads();
         double ew = cw, ev = cv, esv = csv;
@@ -481,11 +590,18 @@ __global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
         int rstart = ostart;
 #pragma unroll
         for (int k = 0; k < kSortWaves; ++k) {
-            const double xa = sa[par][k], xb = sb[par][k], xc = sc[par][k];
+            const double xa = sa[par][k];
+            double xb = 0.0, xc = 0.0;
+            if constexpr (FULL) { xb = sb[par][k]; xc = sc[par][k]; }
             if (k < wave) {
                 ew += xa; ev += xb; esv += xc;
-                if (rf[par][k]) { rw = ra[par][k]; rv = rb[par][k]; }
-                else { rw += ra[par][k]; rv += rb[par][k]; }
+                if (rf[par][k]) {
+                    rw = ra[par][k];
+                    if constexpr (FULL) rv = rb[par][k];
+                } else {
+                    rw += ra[par][k];
+                    if constexpr (FULL) rv += rb[par][k];
+                }
                 rstart = max(rstart, rs[par][k]);
             }
             cw += xa;
@@ -501,26 +617,26 @@ __global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
         ev += iv - tv;
         esv += isv - tsv;
         int start[kAdjItems];
+        float uval[kAdjItems];
 #pragma unroll
         for (int j = 0; j < kAdjItems; ++j) {
             if ((fst >> j) & 1u) { rw = rv = 0.0; rstart = i0 + j; }
             rw += (double)lw[j];
-            rv += (double)lv[j];
+            if constexpr (FULL) rv += (double)lv[j];
             start[j] = rstart;
             const double inw = ew + (double)lw[j], inv = ev + (double)lv[j];
             if (((lst >> j) & 1u) && i0 + j < n_tot) {
-                const int sl = max(rstart, c0) - c0;
-                slot_y[sl] = (float)(coef * (2.0 * inw - rw - W));
-                slot_x[sl] = (float)(coef * (2.0 * inv - rv - V));
+                const int sl_ = max(rstart, c0) - c0;
+                slot_y[sl_] = (float)(coef * (2.0 * inw - rw - W));
+                if constexpr (FULL) slot_x[sl_] = (float)(coef * (2.0 * inv - rv - V));
             }
-            const int pos = ii[j];
-            if ((want & 4) && pos >= 0 && pos < N) {
+            if constexpr (FULL) {
                 const double x = kk[j];
-                u[pos] = (float)(coef * (x * (2.0 * ev - V) - (2.0 * esv - SV)));
+                uval[j] = (float)(coef * (x * (2.0 * ev - V) - (2.0 * esv - SV)));
+                esv += (double)lv[j] * (double)kk[j];
             }
             ew = inw;
             ev = inv;
-            esv += (double)lv[j] * (double)kk[j];
         }
         // a run still open at the chunk's end ends at its last entry, item
         // kAdjItems - 1 of the last thread (a chunk that ends the row closes it)
@@ -532,30 +648,115 @@ __global__ __launch_bounds__(kSortBlock) void sorted_adjoint_kernel(
         }
         __syncthreads();
         const int still_open = open_start[par];
+        // this chunk's entries of the runs that ended in it
+        {
+            int idx[kAdjItems];
+            float val[kAdjItems];
+            if (want & 1) {
 #pragma unroll
-        for (int j = 0; j < kAdjItems; ++j) {
-            const int pos = ii[j];
-            if (pos < 0 || start[j] == still_open) continue;
-            const int sl = max(start[j], c0) - c0;
-            const bool src = pos < N;
-            const bool tgt = same_xy ? src : pos >= yoff;
-            if ((want & 1) && tgt) ty[pos - toff] = slot_y[sl];
-            if ((want & 2) && src) tx[pos] = slot_x[sl];
+                for (int j = 0; j < kAdjItems; ++j) {
+                    const int pos = ii[j];
+                    const bool tgt = pos >= 0 && (same_xy ? pos < N : pos >= yoff);
+                    idx[j] = (tgt && start[j] != still_open) ? pos - toff : -1;
+                    val[j] = slot_y[max(start[j], c0) - c0];
+                }
+                stage_bucketed(idx, val, nby, sl, run_y, tyv, tyo);
+            }
+            if constexpr (FULL) {
+                if (want & 2) {
+#pragma unroll
+                    for (int j = 0; j < kAdjItems; ++j) {
+                        const int pos = ii[j];
+                        idx[j] = (pos >= 0 && pos < N && start[j] != still_open) ? pos : -1;
+                        val[j] = slot_x[max(start[j], c0) - c0];
+                    }
+                    stage_bucketed(idx, val, nbx, sl, run_x, txv, txo);
+                }
+                if (want & 4) {
+#pragma unroll
+                    for (int j = 0; j < kAdjItems; ++j) idx[j] = (ii[j] >= 0 && ii[j] < N) ? ii[j] : -1;
+                    stage_bucketed(idx, uval, nbx, sl, run_u, uv, uo);
+                }
+            }
         }
-        // the entries before this chunk of a run that ends in it (slot 0)
+        // the entries before this chunk of a run that ends in it (slot 0),
+        // kAdjChunk at a time
         if (ostart >= 0 && still_open != ostart) {
-            for (int i = ostart + tid; i < c0; i += kSortBlock) {
-                const int pos = (int)((int64_t)vr[i] - base);
-                if (pos < 0 || pos >= n_tot) continue;
-                const bool src = pos < N;
-                const bool tgt = same_xy ? src : pos >= yoff;
-                if ((want & 1) && tgt) ty[pos - toff] = slot_y[0];
-                if ((want & 2) && src) tx[pos] = slot_x[0];
+            for (int b0 = ostart; b0 < c0; b0 += kAdjChunk) {
+                int pos[kAdjItems], idx[kAdjItems];
+                float val[kAdjItems];
+#pragma unroll
+                for (int j = 0; j < kAdjItems; ++j) {
+                    const int i = b0 + tid * kAdjItems + j;
+                    const int q = i < c0 ? (int)((int64_t)vr[i] - base) : -1;
+                    pos[j] = (q >= 0 && q < n_tot) ? q : -1;
+                }
+                if (want & 1) {
+#pragma unroll
+                    for (int j = 0; j < kAdjItems; ++j) {
+                        const bool tgt = pos[j] >= 0 && (same_xy ? pos[j] < N : pos[j] >= yoff);
+                        idx[j] = tgt ? pos[j] - toff : -1;
+                        val[j] = slot_y[0];
+                    }
+                    stage_bucketed(idx, val, nby, sl, run_y, tyv, tyo);
+                }
+                if constexpr (FULL) {
+                    if (want & 2) {
+#pragma unroll
+                        for (int j = 0; j < kAdjItems; ++j) {
+                            idx[j] = (pos[j] >= 0 && pos[j] < N) ? pos[j] : -1;
+                            val[j] = slot_x[0];
+                        }
+                        stage_bucketed(idx, val, nbx, sl, run_x, txv, txo);
+                    }
+                }
             }
         }
         ostart = still_open;
         ow = open_w[par];
         ov = open_v[par];
+    }
+}
+
+// Rows of per-direction values staged by 4096-index bucket (values and
+// their offsets in the bucket) put back in index order: workgroup (bucket,
+// direction range) places each direction's entries into LDS by offset and
+// writes them out contiguously.
+__global__ __launch_bounds__(kBucketThreads) void sorted_place_kernel(
+    const float* __restrict__ stv, const unsigned short* __restrict__ sti, int P, int prange,
+    int64_t ldm, int M, float* __restrict__ out) {
+    __shared__ float vals_lds[kBucket];
+    constexpr int kPer = kBucket / kBucketThreads;
+    const int tid = threadIdx.x, bk = blockIdx.x;
+    const int64_t m0 = (int64_t)bk << kBucketShift;
+    const int size = (int)min((int64_t)kBucket, (int64_t)M - m0);
+    const int p0 = blockIdx.y * prange, p1 = min(P, p0 + prange);
+    float v[kPer];
+    unsigned short ix[kPer];
+    auto load = [&](int p) {
+        const int64_t base = (int64_t)p * ldm + m0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = tid + k * kBucketThreads;
+            const bool in = e < size && p < p1;
+            v[k] = in ? stv[base + e] : 0.f;
+            ix[k] = in ? sti[base + e] : (unsigned short)0;
+        }
+    };
+    load(p0);
+    for (int p = p0; p < p1; ++p) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (tid + k * kBucketThreads < size) vals_lds[ix[k]] = v[k];
+        __syncthreads();
+        load(p + 1);
+        float* __restrict__ row = out + (int64_t)p * ldm + m0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int e = tid + k * kBucketThreads;
+            if (e < size) row[e] = vals_lds[e];
+        }
+        __syncthreads();
     }
 }
 
@@ -587,26 +788,46 @@ size_t sorted_energy_temp_bytes(int64_t L, int P) {
     return bytes;
 }
 
-hipError_t launch_sorted_grad(const float* keys_in, const float* keys_sorted,
-                              const unsigned int* vals, int64_t L, int P, int N, int yoff, int M,
-                              int same_xy, const float* w, const float* v, double coef, float* Ty,
-                              float* Tx, float* U, int64_t ldm, int want, hipStream_t stream) {
-    const int n_tot = same_xy ? N : yoff + M;
-    if (N < 1 || M < 1 || (same_xy && M != N) || (!same_xy && yoff < N) || n_tot > L ||
-        N > ldm || M > ldm || (int64_t)P * L >= ((int64_t)1 << 32))
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sorted_adjoint_kernel, dim3((unsigned)P), dim3(kSortBlock), 0, stream,
-                       keys_in, keys_sorted, vals, L, N, yoff, M, same_xy, w, v, coef, Ty, Tx, U,
-                       ldm, want);
-    return hipGetLastError();
-}
-
 int sorted_reduce_ranges(int64_t M, int P) {
     // about 2048 workgroups (8 per CU) over the buckets and direction ranges
     const int64_t nb = (M + kBucket - 1) / kBucket;
     return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSortMaxRanges, (int64_t)P,
                                                          (2048 + nb - 1) / nb}));
 }
+
+hipError_t launch_sorted_grad(const float* keys_in, const float* keys_sorted,
+                              const unsigned int* vals, int64_t L, int P, int N, int yoff, int M,
+                              int same_xy, const float* w, const float* v, double coef,
+                              float* Tyv, unsigned short* Tyo, float* Txv, unsigned short* Txo,
+                              float* Uv, unsigned short* Uo, int64_t ldm, int want,
+                              hipStream_t stream) {
+    const int n_tot = same_xy ? N : yoff + M;
+    if (N < 1 || M < 1 || (same_xy && M != N) || (!same_xy && yoff < N) || n_tot > L ||
+        N > ldm || M > ldm || (int64_t)P * L >= ((int64_t)1 << 32))
+        return hipErrorInvalidValue;
+    const int nby = (M + kBucket - 1) >> kBucketShift, nbx = (N + kBucket - 1) >> kBucketShift;
+    const size_t lds = (size_t)(2 * std::max(nby, nbx) + 1 + nby + 2 * nbx) * sizeof(unsigned int);
+    if (want == 1)
+        hipLaunchKernelGGL(sorted_adjoint_kernel<false>, dim3((unsigned)P), dim3(kSortBlock), lds,
+                           stream, keys_in, keys_sorted, vals, L, N, yoff, M, same_xy, w, v, coef,
+                           Tyv, Tyo, Txv, Txo, Uv, Uo, ldm, want);
+    else
+        hipLaunchKernelGGL(sorted_adjoint_kernel<true>, dim3((unsigned)P), dim3(kSortBlock), lds,
+                           stream, keys_in, keys_sorted, vals, L, N, yoff, M, same_xy, w, v, coef,
+                           Tyv, Tyo, Txv, Txo, Uv, Uo, ldm, want);
+    return hipGetLastError();
+}
+
+hipError_t launch_sorted_place(const float* stv, const unsigned short* sti, int P, int64_t ldm,
+                               int M, float* out, hipStream_t stream) {
+    const int nb = (M + kBucket - 1) >> kBucketShift;
+    const int nr = sorted_reduce_ranges(M, P);
+    const int prange = (P + nr - 1) / nr;
+    hipLaunchKernelGGL(sorted_place_kernel, dim3((unsigned)nb, (unsigned)((P + prange - 1) / prange)),
+                       dim3(kBucketThreads), 0, stream, stv, sti, P, prange, ldm, M, out);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_sorted_energy(const float* keys_in, float* keys_out, unsigned int* vals_out,
                                 void* temp, size_t temp_bytes, int64_t L, int P, int N, int yoff,

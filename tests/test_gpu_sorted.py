@@ -145,6 +145,9 @@ def test_sorted_plan_errors():
     with pytest.raises(F.FastSumError):
         F.Plan(xi, kernel="laplace", n_ft=1024, scale=1.0, R=4.0, sorting=True, grad=True,
                n_max=10, m_max=10)
+    with pytest.raises(F.FastSumError):       # bucket counters beyond the LDS budget
+        F.Plan(xi, kernel="energy", n_ft=1024, R=4.0, sorting=True, n_max=(1 << 24) + 1,
+               m_max=10)
     plan = F.Plan(xi, kernel="energy", n_ft=1024, R=4.0, sorting=True, n_max=10, m_max=10)
     import torch
     x = torch.zeros((10, 3), device="cuda")
