@@ -954,6 +954,13 @@ fastsum_status fastsum_plan_create(const fastsum_params* prm, const float* xi, i
              dev_alloc(&pl->bp_scratch, backproject_scratch_bytes() / sizeof(unsigned));
     }
     if (!ok) { free_plan(pl); return FASTSUM_ENOMEM; }
+    // the padding between a sorted row's sources and targets is sorted
+    // along with zero weight: keep its keys finite (0 * key must be 0 in the
+    // prefix sums), once, since no projection writes there
+    if (pl->sorted && hipMemset(pl->keys, 0, PL * sizeof(float)) != hipSuccess) {
+        free_plan(pl);
+        return FASTSUM_EDEVICE;
+    }
 
     // tables
     std::vector<float2> mult, mult_d, tw;

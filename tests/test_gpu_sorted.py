@@ -377,3 +377,24 @@ def test_sorted_bitwise_reproducible():
     plan.close()
     for a, b in zip(*runs):
         assert np.array_equal(a, b)
+
+
+def test_sorted_padding_keys_finite_in_reused_memory():
+    """The padding between a row's sources and targets (N not a multiple of
+    64) is sorted along with zero weight; a plan made in device memory that
+    last held NaN must still give finite sums that match the oracle."""
+    import paper_2410_01316_amd as F
+    import torch
+    N, M, d, P = 1001, 777, 4, 24
+    junk = torch.full((64 << 20,), float("nan"), device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    cfg = _points(N, M, d, seed=91)
+    cfg["xi"] = directions("distance", d, P, 3)
+    plan = _plan(cfg)
+    s = _gpu(plan, cfg)
+    plan.close()
+    s2, s_abs = _oracle(cfg)
+    assert np.all(np.isfinite(s))
+    assert err_scale(s, s2, s_abs) < _bar(d)
