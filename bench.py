@@ -9,8 +9,9 @@ with the target projections computed on the matrix cores and the FP64
 reduction over directions.  P is the smallest
 number of distance-QMC directions in a fixed ladder whose result is within
 1e-3 rel-L2 of the FP64 direct sum on 2500 seeded targets (the same direct
-sum, timed on every host core, is the CPU baseline; a disjoint sample of 1000
-targets confirms the error); the nominal P = 1000 point is reported beside it.
+sum, timed on every host core, is the CPU baseline; a disjoint sample of as
+many targets confirms the error); the nominal P = 1000 point is reported
+beside it.
 
 Prints ONE JSON line.  value = N*M*steps / elapsed (pairs per second).
 Beside it: the dominant kernel's roofline (algorithmic bytes or flops per
@@ -503,7 +504,8 @@ def main():
     ap.add_argument("--P", type=int, default=0,
                     help="fixed number of directions (skips the 1e-3 operating-point search)")
     ap.add_argument("--cpu-sample", type=int, default=2500,
-                    help="targets of the CPU oracle baseline and of the P selection (~25 core-seconds)")
+                    help="targets of the CPU oracle baseline and of the P selection (about 13 "
+                         "core-seconds at 2500)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--dirs-cache", default="",
