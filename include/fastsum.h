@@ -451,6 +451,22 @@ FASTSUM_API fastsum_status fastsum_distance_qmc_noalloc(int32_t d, int32_t P, in
                                                         double lr, float* xi, void* stream);
 
 /*
+ * Momentum step of the MMD gradient flow (App. MMD flows), in place:
+ *   v <- g + m v,   x <- x - step v,
+ * for N particles of d coordinates (device, row-major float32; g the
+ * gradient of the MMD functional at x, as fastsum_grad returns it).  z
+ * (device, N x d, or NULL, or equal to x) receives a copy of the new x:
+ * the particles' rows among the flow's sources.  *max_norm2 (device, one
+ * float, caller-owned) is set to max_n ||x_n||^2 of the new particles, the
+ * first term of the next step's bound (App. J, eq. radius_xy).  One pass,
+ * FP32 (each update one fused multiply-add).  Asynchronous on `stream`.
+ * Errors: EINVAL (arguments), EDEVICE.
+ */
+FASTSUM_API fastsum_status fastsum_flow_update(int64_t N, int32_t d, float momentum, float step,
+                                               const float* g, float* v, float* x, float* z,
+                                               float* max_norm2, void* stream);
+
+/*
  * Host-only N_ft selection rule: the smallest candidate N_ft whose discarded
  * Fourier mass sum_{|k| > N_ft/2} |c_k| is at most tol * sum_k |c_k| (FP64,
  * c_k of prm's kernel, d, scale, T, R; tails summed to |k| = 4096).  Falls

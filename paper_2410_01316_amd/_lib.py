@@ -85,6 +85,8 @@ SIGNATURES = {
     "fastsum_distance_qmc_noalloc": (_st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_double, _vp, _vp]),
     "fastsum_rotate_directions": (_st, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+    "fastsum_flow_update": (_st, [_i64, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _vp, _vp,
+                                  _vp, _vp, _vp, _vp]),
 }
 
 _lib = None

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfastsum.so")
 
-SOURCES = ["kernels.hip", "gemm.hip", "sorted.hip", "qmc.hip", "plan.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "gemm.hip", "sorted.hip", "qmc.hip", "flow.hip", "plan.cpp", "batch.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -8,15 +8,19 @@ and grad_{x_i} G is the target derivative of ONE kernel sum: sources
 z = [x; y] with weights [1/N^2 (N times), -1/(MN) (M times)], evaluated at
 the targets x (the symmetric self term is counted twice, which cancels the
 1/2).  A step is one fastsum_exec and one fastsum_grad (grad_y only), then
-the momentum update of the paper:
-    v <- grad G(x) + m v,   x <- x - tau v      (v starts at 0).
-The bound R of the plan must cover the moving particles; the plan is
-rebuilt with a margin whenever they leave it.
+the momentum update of the paper,
+    v <- grad G(x) + m v,   x <- x - tau v      (v starts at 0),
+by fastsum_flow_update, which also writes the new particles into their
+rows of z and returns their largest norm.  The bound R of the plan must
+cover the moving particles: max ||z|| + max ||x|| = max(|x|, |y|) + |x|
+with |y| taken once; the plan is rebuilt with a margin whenever they leave
+it.
 """
 import numpy as np
 import torch
 
-from .api import Plan, bound
+from . import _lib as L
+from .api import Plan, bound, _ptr, _stream_ptr
 
 
 class MMDFlow:
@@ -50,11 +54,25 @@ class MMDFlow:
         self.ones = torch.ones(N, dtype=torch.float32, device=dev)
         self.s = torch.empty(N, dtype=torch.float32, device=dev)
         self.plan, self.R, self.rebuilds = None, 0.0, 0
+        self.y_norm = 0.5 * bound(self.y, self.y)           # max ||y_m||
+        self.x_norm2 = torch.zeros(1, dtype=torch.float32, device=dev)
+        self._synced = None      # (pointer, version) of the x that z[:N] and x_norm2 describe
 
-    def _ensure_plan(self, x):
+    def _sync(self, x):
+        """max ||x_n||; copies x into z first unless the last step wrote it
+        (an in-place change of x since then shows in its version counter)."""
+        if not (x.dtype == torch.float32 and x.is_cuda and x.shape == (self.N, self.d)
+                and x.is_contiguous()):
+            raise ValueError("x must be a contiguous (N, d) float32 tensor on the GPU")
+        if self._synced == (x.data_ptr(), x._version):
+            return float(torch.sqrt(self.x_norm2).item())
+        self.z[: self.N].copy_(x)
+        return 0.5 * bound(x, x)
+
+    def _ensure_plan(self, x_norm):
         # sources z = [x; y] and targets x about the origin (App. J,
-        # eq. radius_xy), on the device; z already holds the particles
-        need = bound(self.z, x)
+        # eq. radius_xy)
+        need = max(x_norm, self.y_norm) + x_norm
         if self.plan is not None and need * (1.0 + 1e-4) <= self.R:
             return
         if self.plan is not None:
@@ -68,8 +86,7 @@ class MMDFlow:
 
     def gradient(self, x):
         """grad G_y at the particles x (N x d); returns a new tensor."""
-        self.z[: self.N].copy_(x)
-        self._ensure_plan(x)
+        self._ensure_plan(self._sync(x))
         # targets: the particles as the first N rows of z (the plan projects
         # them once, as sources and as targets)
         self.plan(self.z, self.w, self.z[: self.N], out=self.s)
@@ -79,8 +96,14 @@ class MMDFlow:
     def step(self, x, v):
         """One momentum step in place on x and v; returns the R used."""
         g = self.gradient(x)
-        v.mul_(self.momentum).add_(g)
-        x.sub_(self.step_size * v)
+        if not (v.dtype == torch.float32 and v.shape == x.shape and v.is_contiguous()
+                and v.device == x.device):
+            raise ValueError("v must be a contiguous float32 tensor shaped like x")
+        st = L.load().fastsum_flow_update(self.N, self.d, self.momentum, self.step_size,
+                                          _ptr(g), _ptr(v), _ptr(x), _ptr(self.z),
+                                          _ptr(self.x_norm2), _stream_ptr(x.device))
+        L.check(st, "fastsum_flow_update")
+        self._synced = (x.data_ptr(), x._version)
         return self.R
 
     def run(self, x0, steps, callback=None):

@@ -155,3 +155,9 @@ def test_sorted_flag_validation_without_device():
     assert lib.fastsum_rotate_directions(3, 0, buf, buf, None) == L.EINVAL
     assert lib.fastsum_rotate_directions(3, 10, None, buf, None) == L.EINVAL
     assert lib.fastsum_rotate_directions(3, 10, buf, None, None) == L.EINVAL
+    assert lib.fastsum_flow_update(0, 3, 0.9, 1.0, buf, buf, buf, None, buf, None) == L.EINVAL
+    assert lib.fastsum_flow_update(10, 0, 0.9, 1.0, buf, buf, buf, None, buf, None) == L.EINVAL
+    assert lib.fastsum_flow_update(10, 3, float("nan"), 1.0, buf, buf, buf, None, buf,
+                                   None) == L.EINVAL
+    assert lib.fastsum_flow_update(10, 3, 0.9, 1.0, None, buf, buf, None, buf, None) == L.EINVAL
+    assert lib.fastsum_flow_update(10, 3, 0.9, 1.0, buf, buf, buf, None, None, None) == L.EINVAL

@@ -96,3 +96,39 @@ def test_sorted_flow_matches_oracle_flow():
     print("sorted flow displacement rel-L2 %.2e" % e)
     assert e < 1e-4
     flow.close()
+
+
+@pytest.mark.parametrize("d,zmode", [(64, "rows"), (37, "rows"), (64, "none"), (37, "same")])
+def test_flow_update_entry(d, zmode):
+    """fastsum_flow_update against the momentum step written out in FP64
+    (App. MMD flows): v' = g + m v, x' = x - tau v', z rows = x', and the
+    largest ||x'||^2.  d = 64 takes the 16-byte path, d = 37 the scalar
+    one; z separate, absent, or the particles themselves.  FP32 with one
+    rounding per fused multiply-add: 1e-6 of the values' scale."""
+    import ctypes
+    import torch
+    from paper_2410_01316_amd import _lib as L
+    rng = np.random.default_rng(40 + d)
+    N, m, tau = 1003, 0.9, 0.37
+    g, v, x = (rng.standard_normal((N, d)).astype(np.float32) for _ in range(3))
+    gd, vd, xd = (torch.from_numpy(a.copy()).cuda() for a in (g, v, x))
+    zd = torch.full((N + 5, d), 7.0, device="cuda")
+    n2 = torch.full((1,), -1.0, device="cuda")
+    zp = {"rows": zd.data_ptr(), "none": None, "same": xd.data_ptr()}[zmode]
+    st = L.load().fastsum_flow_update(N, d, m, tau, ctypes.c_void_p(gd.data_ptr()),
+                                      ctypes.c_void_p(vd.data_ptr()),
+                                      ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(zp),
+                                      ctypes.c_void_p(n2.data_ptr()),
+                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    L.check(st, "fastsum_flow_update")
+    torch.cuda.synchronize()
+    v1 = g.astype(np.float64) + m * v.astype(np.float64)
+    x1 = x.astype(np.float64) - tau * v1
+    assert np.abs(vd.cpu().numpy() - v1).max() < 1e-6 * np.abs(v1).max()
+    assert np.abs(xd.cpu().numpy() - x1).max() < 1e-6 * np.abs(x1).max()
+    zc = zd.cpu().numpy()
+    if zmode == "rows":
+        assert np.array_equal(zc[:N], xd.cpu().numpy())
+    assert np.all(zc[N:] == 7.0) and (zmode == "rows" or np.all(zc == 7.0))
+    ref = (x1 ** 2).sum(1).max()
+    assert abs(float(n2.item()) - ref) < 1e-5 * ref
