@@ -398,3 +398,25 @@ def test_sorted_padding_keys_finite_in_reused_memory():
     s2, s_abs = _oracle(cfg)
     assert np.all(np.isfinite(s))
     assert err_scale(s, s2, s_abs) < _bar(d)
+
+
+@pytest.mark.parametrize("N,M", [(1, 1), (1, 4097), (4097, 1), (4096, 4096)])
+def test_sorted_gradients_degenerate_sizes(N, M):
+    """One source or one target, one bucket exactly full (4096 targets) and
+    one entry past it: the adjoint's staging and placement at their edges,
+    against the oracle's exact sliced gradients."""
+    rng = np.random.default_rng(N + 3 * M)
+    d, P = 3, 8
+    x = rng.standard_normal((N, d))
+    y = rng.standard_normal((M, d))
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    x, y = f32(x), f32(y)
+    w = f32(rng.standard_normal(N))
+    v = f32(rng.standard_normal(M))
+    xi = directions("distance", d, P, 6)
+    s, gx, gy, gw = _sorted_grads(x, y, w, v, xi)
+    xio = xi.astype(np.float32).astype(np.float64)
+    ox, oy, ow = O.grad_sliced_energy(x, y, w, v, xio)
+    e = [rel_l2(gx, ox), rel_l2(gy, oy), rel_l2(gw, ow)]
+    print("sorted grads N=%d M=%d: gx %.1e gy %.1e gw %.1e" % (N, M, *e))
+    assert e[0] < 2e-3 and e[1] < 2e-3 and e[2] < 1e-5
